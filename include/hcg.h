@@ -1,0 +1,225 @@
+/*
+ * hcg.h -- C ABI of the MI355X (gfx950) convolutional gridding library.
+ *
+ * Gridding resamples N non-uniform sky samples (lon_n, lat_n, spectrum s_n)
+ * onto a regular lon/lat grid.  Every output cell g takes the kernel-weighted
+ * mean of the samples within the support radius R (HCGrid, Wang et al. 2020,
+ * Eq. (1) of Section 2.1):
+ *
+ *     V[c][g] = sum_n w(g,n) s_n[c] / W_g,      W_g = sum_n w(g,n),
+ *     w(g,n)  = exp(-d(g,n)^2 / (2 sigma^2))   if d(g,n) <= R, else 0,
+ *
+ * with d the great-circle distance, sigma = FWHM / (2 sqrt(2 ln 2)) and the
+ * Gaussian kernel of Section 3.6 (iii).  A cell with no sample inside R has
+ * W = 0 and V = NaN.
+ *
+ * The work is split in two calls, following the gridding module of Section 3
+ * (pre-ordering, then gather-side convolution), both done on the GPU:
+ *   hcg_plan  -- geometry only: HEALPix ring-scheme pixel of every sample
+ *                (Section 3.2), a stable sort of (pixel, sample index)
+ *                (Section 3.3 step I), the ring lookup table (step III) and,
+ *                for every tile of output cells, the sample ranges that can
+ *                lie within R (the search of Section 3.4, steps i-iv).
+ *   hcg_grid  -- data: weights and the channel accumulation of Eq. (1) for
+ *                any number of channels, normalised, written as a cube.
+ * A plan is immutable after hcg_plan returns and may be reused for any number
+ * of hcg_grid calls (different spectra, channel slabs or precisions).
+ *
+ * Conventions for every entry point:
+ *   - Angles are degrees.  Grid cell (ix, iy) is centred at
+ *       lon0 + (ix - (nx-1)/2) dlon,   lat0 + (iy - (ny-1)/2) dlat.
+ *   - "device" pointers are HIP device memory of the current device; the
+ *     library never takes ownership of caller memory.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).
+ *   - Every call returns a status; on any status other than HCG_OK,
+ *     hcg_last_error() returns a message for the calling thread.  No C++
+ *     exception crosses this interface.
+ *   - The library runs on gfx950 only; it fails with HCG_E_UNSUPPORTED on
+ *     any other device.
+ */
+#ifndef HCG_H
+#define HCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hcg_plan_s* hcg_plan_t;
+
+typedef enum {
+  HCG_OK = 0,
+  HCG_E_ARG = 1,          /* invalid argument (NULL, out of range, non-finite) */
+  HCG_E_NOMEM = 2,        /* device memory allocation failed */
+  HCG_E_DEVICE = 3,       /* a HIP call or kernel launch failed */
+  HCG_E_UNSUPPORTED = 4,  /* valid request this build or device cannot serve */
+  HCG_E_STATE = 5         /* handle is not a live plan */
+} hcg_status;
+
+/* Storage type of the spectra passed to hcg_grid. */
+typedef enum {
+  HCG_F32 = 0,            /* float32, accumulated in FP32 */
+  HCG_BF16 = 1,           /* reserved */
+  HCG_BF16_SPLIT = 2,     /* reserved */
+  HCG_F16_SCALED = 3,     /* reserved */
+  HCG_FP8E4M3_SCALED = 4  /* reserved */
+} hcg_dtype;
+
+/* Linear lon/lat target grid (degrees).  nx, ny >= 1; dlon, dlat finite and
+ * non-zero; every cell latitude within [-90, 90]. */
+typedef struct {
+  int32_t nx, ny;
+  double lon0_deg, lat0_deg;
+  double dlon_deg, dlat_deg;
+} hcg_grid_desc;
+
+/* Tuning options; a zero field means "choose automatically".
+ *   nside     HEALPix resolution (power of two, 1 .. 16384).  Auto: the
+ *             smallest nside whose mean pixel size is <= sigma/2 (the
+ *             hpx_max_resolution ~ sigma_kernel/2 rule of Section 3.6 (iii)).
+ *   tile_x/y  output-cell tile; only 8 x 8 (or 0) is accepted.
+ *   coarsen, chan_tile, flags: reserved, must be 0. */
+typedef struct {
+  int32_t nside;
+  int32_t tile_x, tile_y;
+  int32_t coarsen;
+  int32_t chan_tile;
+  uint32_t flags;
+} hcg_opts;
+
+/*
+ * hcg_plan -- build the search geometry for N samples and one target grid.
+ *
+ *   out          receives the plan handle; set to NULL on failure.
+ *   lon_deg,     device, float64 [n]: sample coordinates (any longitude;
+ *   lat_deg      latitude within [-90, 90]; all finite).  Read only during
+ *                the call; the plan keeps its own sorted copies.
+ *   n            number of samples, >= 1 and < 2^31.
+ *   grid         host pointer to the target grid.
+ *   fwhm_deg     kernel FWHM (> 0, finite).
+ *   support_deg  support radius R (>= 0, finite, < 90); Section 3.6 (iii)
+ *                recommends 3 to 5 sigma.
+ *   opts         host pointer or NULL (all automatic).
+ *
+ * Synchronous with respect to hip_stream: returns after the plan is built
+ * (it reads back a few bytes once).  Errors: HCG_E_ARG for a NULL pointer,
+ * n out of range, bad grid, fwhm <= 0, support < 0, nside not a power of two
+ * in 1..16384, or any non-finite / out-of-range sample coordinate (checked
+ * on the device); HCG_E_NOMEM; HCG_E_DEVICE; HCG_E_UNSUPPORTED for options
+ * this build does not serve.  Nothing leaks on failure.
+ */
+hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_deg, int64_t n,
+                    const hcg_grid_desc* grid, double fwhm_deg, double support_deg,
+                    const hcg_opts* opts, void* hip_stream);
+
+/*
+ * hcg_grid -- Eq. (1) for every cell and channel of the plan's grid.
+ *
+ *   spectra     device [n][nchan] in the sample order given to hcg_plan,
+ *               channel-fastest; element type per dtype (only HCG_F32 now).
+ *   nchan       >= 1.
+ *   chan_scale  reserved for the scaled dtypes; must be NULL for HCG_F32.
+ *   cube        device float32 [nchan][ny][nx], caller-allocated: the
+ *               normalised map V (NaN where W = 0).
+ *   weights     device float32 [ny][nx] or NULL: the weight map W (FP64 sum
+ *               of the unrounded weights, stored as float32).
+ *
+ * Asynchronous on hip_stream: returns once the work is queued; device faults
+ * surface at the caller's next synchronisation.  The plan is read only, so
+ * calls on different streams may overlap.  Errors: HCG_E_ARG (NULL spectra
+ * or cube, nchan < 1, chan_scale given), HCG_E_UNSUPPORTED (dtype),
+ * HCG_E_STATE (not a live plan), HCG_E_DEVICE (launch failure).
+ */
+hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dtype dtype,
+                    const float* chan_scale, float* cube, float* weights, void* hip_stream);
+
+/* hcg_destroy -- wait for the device, then free the plan.  NULL is a no-op
+ * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE. */
+hcg_status hcg_destroy(hcg_plan_t plan);
+
+/* Message for the last non-OK status returned to the calling thread. */
+const char* hcg_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Inspection of a plan and its intermediate arrays, for tests and tooling.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t n;              /* samples */
+  int32_t nside;          /* HEALPix resolution used */
+  int32_t key_bits;       /* significant bits of (pixel - pix_base) */
+  uint32_t pix_base;      /* smallest pixel index of any sample */
+  uint32_t pix_max;       /* largest pixel index of any sample */
+  int32_t ring_first;     /* ring of pix_base (rings are 1 .. 4 nside - 1) */
+  int32_t ring_last;      /* ring of pix_max */
+  int32_t tile_x, tile_y; /* output-cell tile */
+  int32_t ntiles_x, ntiles_y;
+  int32_t max_ranges;     /* candidate-range slots per tile */
+  int32_t sort_passes;    /* radix passes (8-bit digits) */
+  double sigma_rad, support_rad;
+} hcg_plan_info;
+
+hcg_status hcg_get_plan_info(hcg_plan_t plan, hcg_plan_info* info);
+
+/* Arrays hcg_export copies out of a plan (device to caller device memory):
+ *   HCG_ARR_KEYS     uint32 [n]   sorted keys (pixel - pix_base), non-descending
+ *   HCG_ARR_PERM     uint32 [n]   input index of each sorted sample (stable)
+ *   HCG_ARR_RING_CSR uint32 [ring_last - ring_first + 2]  start of every ring
+ *                    in the sorted order, then the end sentinel n
+ *   HCG_ARR_TILE_NRANGES uint32 [ntiles]  ranges used by each tile
+ *                    (tile t = ty * ntiles_x + tx)
+ *   HCG_ARR_TILE_RANGES  uint32 [ntiles][max_ranges][2]  half-open [a, b)
+ *                    ranges of sorted positions that may lie within R of a
+ *                    cell of the tile (every such sample is covered) */
+typedef enum {
+  HCG_ARR_KEYS = 0,
+  HCG_ARR_PERM = 1,
+  HCG_ARR_RING_CSR = 2,
+  HCG_ARR_TILE_NRANGES = 3,
+  HCG_ARR_TILE_RANGES = 4
+} hcg_array;
+
+/* Copies array `which` into device memory dst of `bytes` bytes (must equal
+ * the array size).  Asynchronous on hip_stream. */
+hcg_status hcg_export(hcg_plan_t plan, hcg_array which, void* dst, int64_t bytes,
+                      void* hip_stream);
+
+/* Size in bytes of array `which` of a plan. */
+hcg_status hcg_export_size(hcg_plan_t plan, hcg_array which, int64_t* bytes);
+
+typedef struct {
+  int64_t pairs;       /* (cell, sample) pairs with d <= R: the nonzeros of Eq. (1) */
+  int64_t candidates;  /* sum over tiles of the candidate samples searched */
+  int64_t cells;       /* nx * ny */
+} hcg_plan_stats;
+
+/* Counts the exact pair work of a plan (runs a counting kernel, then
+ * synchronises hip_stream). */
+hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Single steps of the plan, callable on their own (same kernels).           */
+/* ------------------------------------------------------------------------ */
+
+/* HEALPix ring-scheme pixel of every sample (Section 3.2): device float64
+ * lon_deg/lat_deg [n] -> device uint32 pix [n].  nside a power of two in
+ * 1..16384.  Inputs with a non-finite coordinate or |lat| > 90 get pixel
+ * 0xFFFFFFFF and make the call return HCG_E_ARG (after the kernel, so the
+ * call synchronises hip_stream).  n >= 0. */
+hcg_status hcg_ang2pix(const double* lon_deg, const double* lat_deg, int64_t n, int32_t nside,
+                       uint32_t* pix, void* hip_stream);
+
+/* Stable LSD radix sort of uint32 keys, sorting only the low key_bits bits
+ * (1..32; higher bits must be zero): device keys_in [n] -> device keys_out
+ * [n] (non-descending) and perm_out [n] (input index of each output element;
+ * equal keys keep input order, Section 3.3 step I).  keys_in is not
+ * modified.  Synchronous with respect to hip_stream.  0 <= n < 2^31. */
+hcg_status hcg_sort_keys(const uint32_t* keys_in, int64_t n, int32_t key_bits, uint32_t* keys_out,
+                         uint32_t* perm_out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCG_H */

@@ -1,0 +1,226 @@
+"""Python binding of libhcg.so, the MI355X convolutional gridding library.
+
+Argument marshalling only: every step of the gridding path runs in the HIP
+kernels of ``csrc/`` behind the C ABI of ``include/hcg.h``.  PyTorch provides
+device memory and streams.  The binding raises if the compiled library is
+missing; there is no fallback implementation.
+
+Names mirror the C ABI: ``hcg_plan``, ``hcg_grid``, ``hcg_destroy``,
+``hcg_ang2pix``, ``hcg_sort_keys``, ``hcg_get_plan_info``, ``hcg_export``,
+``hcg_get_plan_stats``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhcg.so")
+
+HCG_OK, HCG_E_ARG, HCG_E_NOMEM, HCG_E_DEVICE, HCG_E_UNSUPPORTED, HCG_E_STATE = range(6)
+HCG_F32, HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED, HCG_FP8E4M3_SCALED = range(5)
+HCG_ARR_KEYS, HCG_ARR_PERM, HCG_ARR_RING_CSR, HCG_ARR_TILE_NRANGES, HCG_ARR_TILE_RANGES = range(5)
+STATUS_NAMES = {0: "HCG_OK", 1: "HCG_E_ARG", 2: "HCG_E_NOMEM", 3: "HCG_E_DEVICE",
+                4: "HCG_E_UNSUPPORTED", 5: "HCG_E_STATE"}
+
+
+class HcgError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDescC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("lon0_deg", ctypes.c_double),
+                ("lat0_deg", ctypes.c_double), ("dlon_deg", ctypes.c_double),
+                ("dlat_deg", ctypes.c_double)]
+
+
+class OptsC(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("coarsen", ctypes.c_int32), ("chan_tile", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class PlanInfoC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nside", ctypes.c_int32), ("key_bits", ctypes.c_int32),
+                ("pix_base", ctypes.c_uint32), ("pix_max", ctypes.c_uint32),
+                ("ring_first", ctypes.c_int32), ("ring_last", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("ntiles_x", ctypes.c_int32), ("ntiles_y", ctypes.c_int32),
+                ("max_ranges", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("sigma_rad", ctypes.c_double), ("support_rad", ctypes.c_double)]
+
+
+class PlanStatsC(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("cells", ctypes.c_int64)]
+
+
+EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_plan_info",
+            "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
+            "hcg_sort_keys"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libhcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2012_13173_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.hcg_plan.argtypes = [ctypes.POINTER(vp), vp, vp, i64, ctypes.POINTER(GridDescC), f64, f64,
+                             ctypes.POINTER(OptsC), vp]
+    lib.hcg_grid.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    lib.hcg_destroy.argtypes = [vp]
+    lib.hcg_last_error.restype = ctypes.c_char_p
+    lib.hcg_last_error.argtypes = []
+    lib.hcg_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfoC)]
+    lib.hcg_export.argtypes = [vp, ctypes.c_int, vp, i64, vp]
+    lib.hcg_export_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    lib.hcg_get_plan_stats.argtypes = [vp, ctypes.POINTER(PlanStatsC), vp]
+    lib.hcg_ang2pix.argtypes = [vp, vp, i64, i32, vp, vp]
+    lib.hcg_sort_keys.argtypes = [vp, i64, i32, vp, vp, vp]
+    for name in EXPORTED:
+        if name != "hcg_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str) -> None:
+    if st != HCG_OK:
+        raise HcgError(st, where, load().hcg_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def grid_desc(g) -> GridDescC:
+    return GridDescC(int(g.nx), int(g.ny), float(g.lon0), float(g.lat0), float(g.dlon),
+                     float(g.dlat))
+
+
+class Plan:
+    """Owns an hcg_plan_t; destroyed explicitly or on garbage collection."""
+
+    def __init__(self, handle: ctypes.c_void_p, grid):
+        self.handle = handle
+        self.grid = grid
+
+    def info(self) -> dict:
+        out = PlanInfoC()
+        _check(load().hcg_get_plan_info(self.handle, ctypes.byref(out)), "hcg_get_plan_info")
+        return {k: getattr(out, k) for k, _ in PlanInfoC._fields_}
+
+    def export(self, which: int, stream=None) -> torch.Tensor:
+        nbytes = ctypes.c_int64()
+        _check(load().hcg_export_size(self.handle, which, ctypes.byref(nbytes)), "hcg_export_size")
+        dst = torch.empty(nbytes.value // 4, dtype=torch.int32, device="cuda")
+        _check(load().hcg_export(self.handle, which, ctypes.c_void_p(dst.data_ptr()), nbytes.value,
+                                 _stream(stream)), "hcg_export")
+        return dst
+
+    def stats(self, stream=None) -> dict:
+        out = PlanStatsC()
+        _check(load().hcg_get_plan_stats(self.handle, ctypes.byref(out), _stream(stream)),
+               "hcg_get_plan_stats")
+        return {k: getattr(out, k) for k, _ in PlanStatsC._fields_}
+
+    def destroy(self) -> None:
+        if self.handle is not None and load() is not None:
+            h, self.handle = self.handle, None
+            _check(load().hcg_destroy(h), "hcg_destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def hcg_plan(lon: torch.Tensor, lat: torch.Tensor, grid, fwhm_deg: float, support_deg: float,
+             nside: int = 0, stream=None) -> Plan:
+    """Builds a plan from device float64 lon/lat (degrees) for ``grid``."""
+    lib = load()
+    n = int(lon.shape[0])
+    if int(lat.shape[0]) != n:
+        raise ValueError("lon and lat must have the same length")
+    handle = ctypes.c_void_p()
+    g = grid_desc(grid)
+    opts = OptsC(int(nside), 0, 0, 0, 0, 0)
+    st = lib.hcg_plan(ctypes.byref(handle), _dptr(lon, torch.float64, "lon"),
+                      _dptr(lat, torch.float64, "lat"), n, ctypes.byref(g), float(fwhm_deg),
+                      float(support_deg), ctypes.byref(opts), _stream(stream))
+    _check(st, "hcg_plan")
+    return Plan(handle, grid)
+
+
+def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None,
+             dtype: int = HCG_F32, chan_scale=None, stream=None) -> None:
+    """Grids ``spectra`` [n, C] into ``cube`` [C, ny, nx] (and ``weights`` [ny, nx])."""
+    if spectra.dim() != 2:
+        raise ValueError("spectra must be [n, nchan]")
+    C = int(spectra.shape[1])
+    g = plan.grid
+    if tuple(cube.shape) != (C, g.ny, g.nx):
+        raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
+    if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
+        raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
+    sdt = {HCG_F32: torch.float32}.get(dtype, None)
+    sp = _dptr(spectra, sdt, "spectra") if sdt is not None else ctypes.c_void_p(spectra.data_ptr())
+    st = load().hcg_grid(plan.handle, sp, C, int(dtype),
+                         _dptr(chan_scale, torch.float32, "chan_scale"),
+                         _dptr(cube, torch.float32, "cube"),
+                         _dptr(weights, torch.float32, "weights"), _stream(stream))
+    _check(st, "hcg_grid")
+
+
+def hcg_destroy(plan: Plan) -> None:
+    plan.destroy()
+
+
+def hcg_ang2pix(lon: torch.Tensor, lat: torch.Tensor, nside: int, stream=None) -> torch.Tensor:
+    """Device HEALPix ring pixel (uint32 stored in an int32 tensor)."""
+    n = int(lon.shape[0])
+    pix = torch.empty(n, dtype=torch.int32, device=lon.device)
+    st = load().hcg_ang2pix(_dptr(lon, torch.float64, "lon"), _dptr(lat, torch.float64, "lat"), n,
+                            int(nside), ctypes.c_void_p(pix.data_ptr()), _stream(stream))
+    _check(st, "hcg_ang2pix")
+    return pix
+
+
+def hcg_sort_keys(keys: torch.Tensor, key_bits: int, stream=None):
+    """Stable radix sort of uint32 keys held in an int32 tensor -> (keys, perm)."""
+    n = int(keys.shape[0])
+    ko = torch.empty_like(keys)
+    po = torch.empty_like(keys)
+    st = load().hcg_sort_keys(_dptr(keys, torch.int32, "keys"), n, int(key_bits),
+                              ctypes.c_void_p(ko.data_ptr()), ctypes.c_void_p(po.data_ptr()),
+                              _stream(stream))
+    _check(st, "hcg_sort_keys")
+    return ko, po
+
+
+def u32(t: torch.Tensor):
+    """int32 tensor holding uint32 values -> int64 numpy array."""
+    return t.cpu().numpy().view("uint32").astype("int64")

@@ -1,0 +1,61 @@
+"""Helpers shared by the GPU parity tests: run the HIP path on a workload,
+compute the oracle on the same inputs, and compare them."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+import paper_2012_13173_amd as hcg
+
+
+def run_gpu(w, nside=None, want_plan=False, stream=None):
+    """Plan + grid on cuda:0.  Returns (cube [C, ny, nx] np.float32, W np.float32[, plan])."""
+    dev = torch.device("cuda:0")
+    lon, lat = w.lon.to(dev), w.lat.to(dev)
+    spec = w.spectra.to(dev).contiguous()
+    plan = hcg.hcg_plan(lon, lat, w.grid, w.fwhm_deg, w.support_deg,
+                        nside=w.nside if nside is None else nside, stream=stream)
+    cube = torch.empty((w.nchan, w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev)
+    W = torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=dev)
+    hcg.hcg_grid(plan, spec, cube, W, stream=stream)
+    torch.cuda.synchronize()
+    out = (cube.cpu().numpy(), W.cpu().numpy())
+    if want_plan:
+        return out + (plan,)
+    plan.destroy()
+    return out
+
+
+def run_oracle(w):
+    lon, lat, spec = w.lon.cpu().numpy(), w.lat.cpu().numpy(), w.spectra.cpu().numpy()
+    V, W, npairs = oracle.grid_allpairs(lon, lat, spec, w.grid, w.fwhm_deg, w.support_deg)
+    return V, W, npairs
+
+
+def channel_errors(V_gpu, V_ref):
+    """Per-channel relative L2 error over cells where the reference is finite
+    (the primary norm), after checking that the NaN patterns agree."""
+    V_gpu = np.asarray(V_gpu, dtype=np.float64).reshape(V_gpu.shape[0], -1)
+    V_ref = np.asarray(V_ref, dtype=np.float64).reshape(V_ref.shape[0], -1)
+    nan_g, nan_r = np.isnan(V_gpu), np.isnan(V_ref)
+    assert np.array_equal(nan_g, nan_r), f"NaN patterns differ in {int((nan_g != nan_r).sum())} places"
+    ok = ~nan_r
+    d = np.where(ok, V_gpu - V_ref, 0.0)
+    r = np.where(ok, V_ref, 0.0)
+    num = np.sqrt((d * d).sum(1))
+    den = np.sqrt((r * r).sum(1))
+    return np.where(den > 0, num / np.maximum(den, 1e-300), num)
+
+
+def assert_cube_close(V_gpu, V_ref, tol, what=""):
+    e = channel_errors(V_gpu, V_ref)
+    assert float(e.max()) <= tol, f"{what}: max per-channel rel L2 {e.max():.3e} > {tol:.1e}"
+    return e
+
+
+def assert_weights_close(W_gpu, W_ref, rtol=1e-6):
+    W_gpu = np.asarray(W_gpu, dtype=np.float64)
+    W_ref = np.asarray(W_ref, dtype=np.float64)
+    assert np.array_equal(W_gpu == 0, W_ref == 0)
+    np.testing.assert_allclose(W_gpu, W_ref, rtol=rtol, atol=0)
