@@ -39,11 +39,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, cube_gpu, budget_s=12.0, patch=32, max_patches=12, seed=7):
+def cpu_baseline(w, cubes, budget_s=15.0, patch=32, max_patches=40, seed=7):
     """Times the FP64 oracle on patches of patch x patch cells (all channels)
     until ~budget_s of wall time, and extrapolates to the whole grid.  Also
-    returns the largest per-channel relative L2 difference between the GPU
-    cube and the oracle on those cells."""
+    returns, for every GPU cube in ``cubes`` (name -> [C, ny, nx] tensor), the
+    per-channel relative L2 errors against the oracle on those cells."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     oracle.set_threads(cores)
@@ -51,7 +51,9 @@ def cpu_baseline(w, cube_gpu, budget_s=12.0, patch=32, max_patches=12, seed=7):
     lon = w.lon.cpu().numpy()
     lat = w.lat.cpu().numpy()
     rng = np.random.default_rng(seed)
-    t_total, cells_done, worst = 0.0, 0, 0.0
+    t_total, cells_done = 0.0, 0
+    num = {k: np.zeros(w.nchan) for k in cubes}
+    den = np.zeros(w.nchan)
     R = w.support_deg
     for _ in range(max_patches):
         x0 = int(rng.integers(0, g.nx - patch + 1))
@@ -70,13 +72,15 @@ def cpu_baseline(w, cube_gpu, budget_s=12.0, patch=32, max_patches=12, seed=7):
         dt = time.perf_counter() - t0
         t_total += dt
         cells_done += cells.size
-        gv = cube_gpu.reshape(cube_gpu.shape[0], -1)[:, torch.from_numpy(cells).to(cube_gpu.device)]
-        gv = gv.cpu().numpy().astype(np.float64).T  # [cells, C]
         ok = ~np.isnan(V)
-        assert np.array_equal(ok, ~np.isnan(gv))
-        d = np.where(ok, gv - V, 0.0)
         r = np.where(ok, V, 0.0)
-        worst = max(worst, float((np.sqrt((d * d).sum(0)) / np.sqrt((r * r).sum(0))).max()))
+        den += (r * r).sum(0)
+        for k, cube in cubes.items():
+            idx = torch.from_numpy(cells).to(cube.device)
+            gv = cube.reshape(cube.shape[0], -1)[:, idx].cpu().numpy().astype(np.float64).T
+            assert np.array_equal(ok, ~np.isnan(gv)), k
+            d = np.where(ok, gv - V, 0.0)
+            num[k] += (d * d).sum(0)
         if t_total >= budget_s:
             break
     t_full = t_total * g.ncells / cells_done
@@ -85,7 +89,7 @@ def cpu_baseline(w, cube_gpu, budget_s=12.0, patch=32, max_patches=12, seed=7):
             "sample": f"{cells_done} of {g.ncells} cells ({cells_done // (patch * patch)} random "
                       f"{patch}x{patch}-cell patches), all {w.nchan} channels, FP64 bucketed "
                       f"oracle, {t_total:.1f} s measured, whole-grid time extrapolated by cell "
-                      f"count ({t_full:.0f} s)"}, worst
+                      f"count ({t_full:.0f} s)"}, {k: np.sqrt(num[k] / den) for k in cubes}
 
 
 def main():
@@ -94,6 +98,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the low-precision forms")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (sharding across GPUs is "
@@ -107,6 +114,12 @@ def main():
     log(f"synthesised {w.n} samples x {w.nchan} channels in {time.perf_counter() - t0:.1f} s")
     g = w.grid
     stream = torch.cuda.current_stream()
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=dev)
     wmap = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev)
 
@@ -146,11 +159,37 @@ def main():
 
     updates = w.n * w.nchan
     value = updates / (ms_step * 1e-3)
+
+    # the matrix-core precision forms on the same plan (encoding not timed)
+    forms = {}
+    cubes = {"f32": cube}
+    if not args.no_forms:
+        plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
+        for name, form in (("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
+                           ("bf16_split", hcg.HCG_BF16_SPLIT),
+                           ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED)):
+            enc, scale = hcg.hcg_quantize(w.spectra, form)
+            out = torch.empty_like(cube)
+            hcg.hcg_grid(plan, enc, out, dtype=form, chan_scale=scale)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(3)]
+            for a, b in evs:
+                a.record(stream)
+                hcg.hcg_grid(plan, enc, out, dtype=form, chan_scale=scale)
+                b.record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+            forms[name] = {"grid_ms": ms, "grid_updates_per_s": updates / (ms * 1e-3),
+                           "speedup_vs_f32_grid": grid_avg / ms}
+            cubes[name] = out
+            del enc
+            log(f"form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 gather)")
+        plan.destroy()
     flops = 2.0 * stats["pairs"] * w.nchan
     achieved = flops / (grid_avg * 1e-3) / 1e12
     traffic = None
     out = {
-        "metric": "sample*channel updates/s (FP32 gather)",
+        "metric": "sample*channel updates/s, FP32 gather vs BF16-MFMA at <=1e-3 rel err",
         "value": value,
         "unit": "sample*channel updates/s",
         "n_gpus": 1,
@@ -178,11 +217,18 @@ def main():
     }
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        cb, worst = cpu_baseline(w, cube)
+        cb, errs = cpu_baseline(w, cubes)
         out["cpu_baseline"] = cb
-        out["sampled_parity_max_rel_l2"] = worst
+        for k, e in errs.items():
+            rec = forms.setdefault(k, {"grid_ms": grid_avg, "grid_updates_per_s":
+                                       updates / (grid_avg * 1e-3), "speedup_vs_f32_grid": 1.0})
+            rec["rel_l2_max_over_channels"] = float(e.max())
+            rec["rel_l2_median_over_channels"] = float(np.median(e))
         log(f"cpu baseline {cb['value']:.3g} /s on {cb['cores']} cores "
-            f"({time.perf_counter() - t0:.1f} s); sampled parity {worst:.2e}")
+            f"({time.perf_counter() - t0:.1f} s); sampled errors "
+            + ", ".join(f"{k} {e.max():.2e}" for k, e in errs.items()))
+    if forms:
+        out["forms"] = forms
     print(json.dumps(out), flush=True)
 
 

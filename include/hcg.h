@@ -57,13 +57,27 @@ typedef enum {
   HCG_E_STATE = 5         /* handle is not a live plan */
 } hcg_status;
 
-/* Storage type of the spectra passed to hcg_grid. */
+/* Storage type of the spectra passed to hcg_grid.  Every form accumulates in
+ * FP32 on the matrix cores; the weights are rounded to the operand type of
+ * the form (the spectra's), and V is normalised by the sum of the weights as
+ * rounded, so a constant input still maps to the same constant.
+ *   HCG_F32             float32 [n][C]; FP32 weights.
+ *   HCG_BF16            bfloat16 [n][C]; BF16 weights.
+ *   HCG_BF16_SPLIT      two bfloat16 planes [2][n][C]: hi = bf16(x) then
+ *                       lo = bf16(x - hi); weights split the same way; three
+ *                       products per pair (hi.hi + hi.lo + lo.hi).
+ *   HCG_F16_SCALED      float16 [n][C] holding x / scale[c]; FP16 weights;
+ *                       V is multiplied back by scale[c].
+ *   HCG_FP8E4M3_SCALED  OCP FP8 E4M3 [n][C] holding x / scale[c]; FP8 E4M3
+ *                       weights; V is multiplied back by scale[c].
+ * hcg_quantize produces these encodings (with power-of-two scales) from
+ * float32 spectra. */
 typedef enum {
-  HCG_F32 = 0,            /* float32, accumulated in FP32 */
-  HCG_BF16 = 1,           /* reserved */
-  HCG_BF16_SPLIT = 2,     /* reserved */
-  HCG_F16_SCALED = 3,     /* reserved */
-  HCG_FP8E4M3_SCALED = 4  /* reserved */
+  HCG_F32 = 0,
+  HCG_BF16 = 1,
+  HCG_BF16_SPLIT = 2,
+  HCG_F16_SCALED = 3,
+  HCG_FP8E4M3_SCALED = 4
 } hcg_dtype;
 
 /* Linear lon/lat target grid (degrees).  nx, ny >= 1; dlon, dlat finite and
@@ -117,9 +131,13 @@ hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_de
  * hcg_grid -- Eq. (1) for every cell and channel of the plan's grid.
  *
  *   spectra     device [n][nchan] in the sample order given to hcg_plan,
- *               channel-fastest; element type per dtype (only HCG_F32 now).
+ *               channel-fastest, in the storage type of dtype (two planes
+ *               for HCG_BF16_SPLIT).  Values must be finite: a non-finite
+ *               value reaches every cell of the 4 x 4 cell block that
+ *               shares its matrix-core step, not only the cells within R.
  *   nchan       >= 1.
- *   chan_scale  reserved for the scaled dtypes; must be NULL for HCG_F32.
+ *   chan_scale  device float [nchan] for the scaled dtypes (the scales the
+ *               encoding used); NULL for the others.
  *   cube        device float32 [nchan][ny][nx], caller-allocated: the
  *               normalised map V (NaN where W = 0).
  *   weights     device float32 [ny][nx] or NULL: the weight map W (FP64 sum
@@ -128,11 +146,31 @@ hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_de
  * Asynchronous on hip_stream: returns once the work is queued; device faults
  * surface at the caller's next synchronisation.  The plan is read only, so
  * calls on different streams may overlap.  Errors: HCG_E_ARG (NULL spectra
- * or cube, nchan < 1, chan_scale given), HCG_E_UNSUPPORTED (dtype),
- * HCG_E_STATE (not a live plan), HCG_E_DEVICE (launch failure).
+ * or cube, nchan < 1, chan_scale missing for a scaled dtype or given for
+ * another), HCG_E_UNSUPPORTED (unknown dtype), HCG_E_STATE (not a live
+ * plan), HCG_E_DEVICE (launch failure).
  */
 hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dtype dtype,
                     const float* chan_scale, float* cube, float* weights, void* hip_stream);
+
+/*
+ * hcg_quantize -- encode float32 spectra for a low-precision form of
+ * hcg_grid (the per-channel scaling of the precision forms).
+ *
+ *   in          device float [n][nchan].
+ *   dtype       HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED or HCG_FP8E4M3_SCALED.
+ *   out         device buffer: 2 n nchan bytes (BF16, F16), 4 n nchan bytes
+ *               (BF16 split: hi plane then lo plane), n nchan bytes (FP8).
+ *   chan_scale  device float [nchan], written for the scaled forms:
+ *               scale[c] = 2^ceil(log2(max_n |x[n][c]| / top)) with top =
+ *               2^14 (FP16) or 448 (the largest E4M3 value); 1 for an
+ *               all-zero channel.  NULL for the unscaled forms.
+ * Every element is rounded to nearest even (E4M3 saturates at 448).
+ * Asynchronous on hip_stream.  Errors: HCG_E_ARG (shape, NULL pointer,
+ * dtype not a low-precision form, missing chan_scale), HCG_E_DEVICE.
+ */
+hcg_status hcg_quantize(const float* in, int64_t n, int64_t nchan, hcg_dtype dtype, void* out,
+                        float* chan_scale, void* hip_stream);
 
 /* hcg_destroy -- wait for the device, then free the plan.  NULL is a no-op
  * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE. */

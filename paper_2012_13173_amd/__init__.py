@@ -61,7 +61,7 @@ class PlanStatsC(ctypes.Structure):
 
 EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_plan_info",
             "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
-            "hcg_sort_keys"]
+            "hcg_sort_keys", "hcg_quantize"]
 
 _lib = None
 
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     lib.hcg_get_plan_stats.argtypes = [vp, ctypes.POINTER(PlanStatsC), vp]
     lib.hcg_ang2pix.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.hcg_sort_keys.argtypes = [vp, i64, i32, vp, vp, vp]
+    lib.hcg_quantize.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp, vp]
     for name in EXPORTED:
         if name != "hcg_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -175,24 +176,47 @@ def hcg_plan(lon: torch.Tensor, lat: torch.Tensor, grid, fwhm_deg: float, suppor
     return Plan(handle, grid)
 
 
+# storage dtype of each form's spectra and the shape prefix of its buffer
+_FORM_STORAGE = {HCG_F32: (torch.float32, ()), HCG_BF16: (torch.bfloat16, ()),
+                 HCG_BF16_SPLIT: (torch.bfloat16, (2,)), HCG_F16_SCALED: (torch.float16, ()),
+                 HCG_FP8E4M3_SCALED: (torch.uint8, ())}
+
+
 def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None,
              dtype: int = HCG_F32, chan_scale=None, stream=None) -> None:
-    """Grids ``spectra`` [n, C] into ``cube`` [C, ny, nx] (and ``weights`` [ny, nx])."""
-    if spectra.dim() != 2:
-        raise ValueError("spectra must be [n, nchan]")
-    C = int(spectra.shape[1])
+    """Grids ``spectra`` ([n, C], or [2, n, C] for the split form) into
+    ``cube`` [C, ny, nx] (and ``weights`` [ny, nx])."""
+    sdt, prefix = _FORM_STORAGE[dtype]
+    if spectra.dim() != 2 + len(prefix) or tuple(spectra.shape[:len(prefix)]) != prefix:
+        raise ValueError(f"spectra must be [{', '.join(map(str, prefix + ('n', 'nchan')))}]")
+    C = int(spectra.shape[-1])
     g = plan.grid
     if tuple(cube.shape) != (C, g.ny, g.nx):
         raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
     if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
         raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
-    sdt = {HCG_F32: torch.float32}.get(dtype, None)
-    sp = _dptr(spectra, sdt, "spectra") if sdt is not None else ctypes.c_void_p(spectra.data_ptr())
+    sp = _dptr(spectra, sdt, "spectra")
     st = load().hcg_grid(plan.handle, sp, C, int(dtype),
                          _dptr(chan_scale, torch.float32, "chan_scale"),
                          _dptr(cube, torch.float32, "cube"),
                          _dptr(weights, torch.float32, "weights"), _stream(stream))
     _check(st, "hcg_grid")
+
+
+def hcg_quantize(spectra: torch.Tensor, dtype: int, stream=None):
+    """Encodes float32 spectra [n, C] for a low-precision form.
+
+    Returns (encoded tensor in the form's storage dtype, chan_scale or None)."""
+    n, C = (int(x) for x in spectra.shape)
+    sdt, prefix = _FORM_STORAGE[dtype]
+    out = torch.empty(prefix + (n, C), dtype=sdt, device=spectra.device)
+    scaled = dtype in (HCG_F16_SCALED, HCG_FP8E4M3_SCALED)
+    scale = torch.empty(C, dtype=torch.float32, device=spectra.device) if scaled else None
+    st = load().hcg_quantize(_dptr(spectra, torch.float32, "spectra"), n, C, int(dtype),
+                             ctypes.c_void_p(out.data_ptr()),
+                             _dptr(scale, torch.float32, "chan_scale"), _stream(stream))
+    _check(st, "hcg_quantize")
+    return out, scale
 
 
 def hcg_destroy(plan: Plan) -> None:

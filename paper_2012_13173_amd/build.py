@@ -11,12 +11,12 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["capi.hip", "plan.hip", "gather.hip"]
+SOURCES = ["capi.hip", "plan.hip", "gather.hip", "quant.hip"]
 LIB = os.path.join(PKG, "libhcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def build(verbose: bool = True, jobs: int = 3) -> str:
+def build(verbose: bool = True, jobs: int = 4) -> str:
     flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
              # packed FP32 instructions are kept out of all device code

@@ -3,19 +3,21 @@
 // the samples within its support, so no two workgroups write the same cell).
 //
 // Work decomposition: one workgroup per 8 x 8 tile of output cells (and per
-// 256-channel slab for many channels).  The tile's candidate samples come
-// from the plan's sorted-sample ranges and are staged in blocks of 64:
+// 256- or 512-channel slab for many channels).  The tile's candidate samples
+// come from the plan's sorted-sample ranges and are staged in blocks of 64:
 //   1. weights: FP64 haversine distance of every (cell, candidate) pair of
-//      the block, exact support test, FP64 Gaussian weight; FP64 sums of the
-//      weights per cell;
+//      the block, exact support test, FP64 Gaussian weight, rounded to the
+//      operand type of the form; FP64 sums of the weights per cell;
 //   2. accumulation: for many channels the block is a dense contraction
 //      U[cells x channels] += Wt[cells x 64] . S[64 x channels] done on the
-//      matrix cores (v_mfma_f32_16x16x4_f32: 16 cells x 4 samples x 16
-//      channels per instruction, FP32 products and accumulation), skipping
-//      every 16-cell x 4-sample sub-block whose weights are all zero; for a
-//      few channels each lane owns one cell and accumulates in FP64;
-//   3. epilogue: V = U / W~ (W~ the sum of the weights actually multiplied),
-//      NaN where no sample is within the support; W map = FP64 sum.
+//      matrix cores with FP32 accumulation -- FP32 operands
+//      (v_mfma_f32_16x16x4_f32) or BF16 / FP16 / FP8 operands (16x16x32),
+//      skipping every 16-cell x k-step sub-block whose weights are all zero;
+//      for a few FP32 channels each lane owns one cell and accumulates in
+//      FP64;
+//   3. epilogue: V = U / W~ (W~ the sum of the weights actually multiplied,
+//      times the channel scale for the scaled forms), NaN where no sample is
+//      within the support; W map = FP64 sum of the unrounded weights.
 #include <cmath>
 #include <vector>
 
@@ -26,10 +28,6 @@ namespace hcg {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKB = 64;             // candidates staged per block
-constexpr int kSteps = kKB / 4;     // MFMA k-steps (4 samples each) per block
-constexpr int kMfmaWaves = 4;
-constexpr int kChanPerWave = 64;
-constexpr int kChanPerWG = kMfmaWaves * kChanPerWave;
 
 // Squared great-circle distance from the haversine h = sin^2(d/2):
 // d^2 = 4 asin^2(sqrt h) = 4h (1 + h/3 + 8h^2/45 + 4h^3/35 + ...).
@@ -95,62 +93,140 @@ __device__ __forceinline__ uint32_t cand_pos(uint32_t q, const uint2* s_rng, con
 }
 
 // ---------------------------------------------------------------------------
-// Many channels, FP32: matrix-core contraction per staged block.
-// Workgroup = 4 waves.  Wave w computes the weights of cell block w (16 cells:
-// a 4 x 4 patch of the tile) for the block's 64 candidates, one cell per
-// lane, 16 candidates per lane, directly in the A-operand layout of
-// v_mfma_f32_16x16x4_f32 (lane l holds cell l%16, sample l/16 of each
-// 4-sample step).  In the contraction wave w owns channels
-// [slab + 64w, slab + 64w + 64) for all four cell blocks; lane l streams
-// channels 4(l%16) .. 4(l%16)+3 of sample l/16 of each step (B operand,
-// column j of MFMA q is channel 4j + q of the wave's 64).
+// Storage forms of the spectra and of the weights on the matrix cores.
 // ---------------------------------------------------------------------------
-template <bool kVec4>
-__global__ void __launch_bounds__(256, 2) k_gather_mfma_f32(
-    const double4* __restrict__ trig, const uint32_t* __restrict__ perm,
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ nranges, int maxr,
-    const float* __restrict__ spectra, int64_t C, GridGeom g, int ntx, double hR,
-    double inv_two_sig2, float* __restrict__ cube, float* __restrict__ wmap) {
+enum Form : int { kF32 = 0, kBF16 = 1, kBF16Split = 2, kF16S = 3, kFP8S = 4 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Many channels: matrix-core contraction per staged block of 64 candidates.
+//
+// Workgroup = 4 waves, tile = 8 x 8 cells = four 4 x 4 cell blocks (MFMA M =
+// 16 cells), channel slab = 4 waves x 64 QW channels.  Per block:
+//  - weights: wave w computes the FP64 weights of cell block w for the 64
+//    candidates (one cell per lane), rounds them to the operand type and
+//    writes them to LDS in the A-operand layout; one bit per (cell block,
+//    k-step) marks a non-zero sub-block;
+//  - contraction: wave w streams its channels of the block's candidate rows
+//    from HBM into B operands and issues the MFMAs of the non-zero
+//    sub-blocks for all four cell blocks.
+// Operand layouts (lane l, i = l % 16, g = l / 16):
+//   FP32  v_mfma_f32_16x16x4_f32: A = w(cell i, cand 4s + g), B = spectrum of
+//         cand 4s + g at channel 4i + q (MFMA q of a 64-channel group);
+//   16-bit / FP8 16x16x32: A = w(cell i, cands 32s + 8g .. +7) packed, B = the
+//         same 8 candidates at channel 4i + q, repacked from 8-byte (16-bit)
+//         or 4-byte (FP8) row loads.
+// Output D[i][j]: lane l, register r holds cell 4 (l/16) + r of the block and
+// channel 4 (l % 16) + q of the group.
+// ---------------------------------------------------------------------------
+struct GatherArgs {
+  const double4* trig;
+  const uint32_t* perm;
+  const uint2* ranges;
+  const uint32_t* nranges;
+  int maxr;
+  const void* spec;     // [n][C] in the form's storage type
+  const void* spec_lo;  // low plane for the split form
+  const float* scale;   // [C] per-channel scale for the scaled forms
+  int64_t C;
+  GridGeom g;
+  int ntx, ntiles, tiles_per_xcd;
+  double hR, inv_two_sig2;
+  float* cube;
+  float* wmap;
+};
+
+template <int kForm>
+struct FormTraits;
+template <>
+struct FormTraits<kF32> { static constexpr int kK = 4; };
+template <>
+struct FormTraits<kBF16> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kBF16Split> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kF16S> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kFP8S> { static constexpr int kK = 32; };
+
+template <int kForm>
+__device__ __forceinline__ uint32_t enc_w(float w) {
+  if (kForm == kF16S) return f32_to_f16(w);
+  if (kForm == kFP8S) return f32_to_e4m3(w);
+  return f32_to_bf16(w);
+}
+template <int kForm>
+__device__ __forceinline__ float dec_w(uint32_t c) {
+  if (kForm == kF16S) return f16_to_f32(c);
+  if (kForm == kFP8S) return e4m3_to_f32(c);
+  return bf16_to_f32(c);
+}
+
+// the 16-bit element q (0..3) of an 8-byte load
+__device__ __forceinline__ uint32_t elem16(uint2 d, int q) {
+  const uint32_t w = (q < 2) ? d.x : d.y;
+  return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+template <int kForm, int kQW, bool kVec>
+__global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
+  constexpr int kK = FormTraits<kForm>::kK;
+  constexpr int kNS = kKB / kK;  // k-steps per staged block
   __shared__ uint2 s_rng[kMaxRangesLimit];
   __shared__ uint32_t s_pre[kMaxRangesLimit + 1];
   __shared__ double4 s_trig[kKB];
   __shared__ uint32_t s_row[kKB];
-  __shared__ float s_A[4][kSteps][64];
+  __shared__ uint4 s_Araw[(kForm == kF32) ? 1024 : (kForm == kBF16Split) ? 1024 : 512];
   __shared__ uint32_t s_nz[4];
   __shared__ double s_Wt[kTileCells];
 
-  const int tile = blockIdx.x;
+  // XCD-aware order: the hardware deals consecutive workgroups to the eight
+  // XCDs in turn; give each XCD a contiguous run of tiles so that tiles that
+  // share candidate rows run together behind the same L2.
+  const int per_slab = a.tiles_per_xcd * 8;
+  const int slab = blockIdx.x / per_slab;
+  const int local = blockIdx.x - slab * per_slab;
+  const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
+  if (tile >= a.ntiles) return;
+
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const GridGeom& g = a.g;
+  const int64_t C = a.C;
   const int64_t G = (int64_t)g.nx * g.ny;
 
-  // this lane's cell in the weight phase: block `wave`, cell lane % 16
   const int ci = lane & 15;
   const int my_x = tx * kTileX + (wave & 1) * 4 + (ci & 3);
   const int my_y = ty * kTileY + (wave >> 1) * 4 + (ci >> 2);
   const CellTrig cell = cell_trig(g, my_x, my_y);
 
-  const uint32_t total = stage_ranges(ranges + (int64_t)tile * maxr, nranges[tile], s_rng, s_pre);
+  const uint32_t total =
+      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre);
 
-  floatx4 acc[4][4];
+  floatx4 acc[4][4 * kQW];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-  double wsum = 0.0;   // FP64 sum of unrounded weights (this lane's share)
-  double wtsum = 0.0;  // FP64 sum of the FP32-rounded weights used in the products
+    for (int q = 0; q < 4 * kQW; ++q) acc[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  double wsum = 0.0;   // FP64 sum of the unrounded weights (this lane's share)
+  double wtsum = 0.0;  // FP64 sum of the weights as used in the products
   uint32_t cur = 0;
-  const int64_t c_w = (int64_t)blockIdx.y * kChanPerWG + wave * kChanPerWave;
-  const int64_t my_ch = c_w + 4 * (lane & 15);
+  const int64_t c_w = (int64_t)slab * (256 * kQW) + wave * (64 * kQW);
+  const int64_t my_ch = c_w + 4 * (lane & 15);  // + 64 h + q
+
+  float* sA32 = (float*)s_Araw;                // [4][16][64]
+  uint4* sA16 = s_Araw;                        // [4][kNS][64] (+ lo plane after)
+  uint2* sA8 = (uint2*)s_Araw;                 // [4][kNS][64]
 
   for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
-    // stage the block's candidates
     if (tid < kKB) {
       const uint32_t q = q0 + tid;
       if (q < total) {
         const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
-        s_trig[tid] = trig[pos];
-        s_row[tid] = perm[pos];
+        s_trig[tid] = a.trig[pos];
+        s_row[tid] = a.perm[pos];
       } else {
         const double nan = __builtin_nan("");
         s_trig[tid] = make_double4(nan, nan, nan, nan);
@@ -158,56 +234,211 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma_f32(
       }
     }
     __syncthreads();
-    // weights of cell block `wave`
+
+    // ---- weights of cell block `wave`, in the A-operand layout
     uint32_t nzbits = 0;
+    if (kForm == kF32) {
 #pragma unroll
-    for (int ks = 0; ks < kSteps; ++ks) {
-      const double4 t = s_trig[4 * ks + (lane >> 4)];
-      const double h = pair_hav(cell, t);
-      float wf = 0.f;
-      if (h <= hR) {
-        const double w = exp(-dist2_from_hav(h) * inv_two_sig2);
-        wf = (float)w;
-        wsum += w;
-        wtsum += (double)wf;
+      for (int ks = 0; ks < kNS; ++ks) {
+        const double h = pair_hav(cell, s_trig[4 * ks + (lane >> 4)]);
+        float wf = 0.f;
+        if (h <= a.hR) {
+          const double w = exp(-dist2_from_hav(h) * a.inv_two_sig2);
+          wf = (float)w;
+          wsum += w;
+          wtsum += (double)wf;
+        }
+        sA32[(wave * kNS + ks) * 64 + lane] = wf;
+        if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
       }
-      s_A[wave][ks][lane] = wf;
-      if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < kNS; ++ks) {
+        uint32_t hi[8], lo[8];
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const double h = pair_hav(cell, s_trig[kK * ks + 8 * (lane >> 4) + t]);
+          hi[t] = 0u;
+          lo[t] = 0u;
+          if (h <= a.hR) {
+            const double w = exp(-dist2_from_hav(h) * a.inv_two_sig2);
+            const float wf = (float)w;
+            hi[t] = enc_w<kForm>(wf);
+            double eff = (double)dec_w<kForm>(hi[t]);
+            if (kForm == kBF16Split) {
+              lo[t] = f32_to_bf16(wf - dec_w<kForm>(hi[t]));
+              eff += (double)bf16_to_f32(lo[t]);
+            }
+            wsum += w;
+            wtsum += eff;
+            any = true;
+          }
+        }
+        if (kForm == kFP8S) {
+          uint2 v;
+          v.x = hi[0] | (hi[1] << 8) | (hi[2] << 16) | (hi[3] << 24);
+          v.y = hi[4] | (hi[5] << 8) | (hi[6] << 16) | (hi[7] << 24);
+          sA8[(wave * kNS + ks) * 64 + lane] = v;
+        } else {
+          uint4 v;
+          v.x = hi[0] | (hi[1] << 16);
+          v.y = hi[2] | (hi[3] << 16);
+          v.z = hi[4] | (hi[5] << 16);
+          v.w = hi[6] | (hi[7] << 16);
+          sA16[(wave * kNS + ks) * 64 + lane] = v;
+          if (kForm == kBF16Split) {
+            uint4 u;
+            u.x = lo[0] | (lo[1] << 16);
+            u.y = lo[2] | (lo[3] << 16);
+            u.z = lo[4] | (lo[5] << 16);
+            u.w = lo[6] | (lo[7] << 16);
+            sA16[(4 * kNS + wave * kNS + ks) * 64 + lane] = u;
+          }
+        }
+        if (__ballot(any)) nzbits |= 1u << ks;
+      }
     }
     if (lane == 0) s_nz[wave] = nzbits;
     __syncthreads();
 
-    // contraction over the block: B operands for all 16 steps, then MFMAs
-    const uint32_t nz0 = s_nz[0], nz1 = s_nz[1], nz2 = s_nz[2], nz3 = s_nz[3];
-    floatx4 b[kSteps];
+    // ---- contraction over the block
+    const uint32_t nzc[4] = {s_nz[0], s_nz[1], s_nz[2], s_nz[3]};
+    if (kForm == kF32) {
+      const float* spec = (const float*)a.spec;
+      constexpr int kDepth = 4;
+      floatx4 b[kDepth][kQW];
+      auto load = [&](int ks, floatx4* dst) {
+        const int64_t row = s_row[4 * ks + (lane >> 4)];
 #pragma unroll
-    for (int ks = 0; ks < kSteps; ++ks) {
-      const int64_t row = s_row[4 * ks + (lane >> 4)];
-      const float* src = spectra + row * C + my_ch;
-      if (kVec4) {
-        if (my_ch + 3 < C) {
-          b[ks] = *(const floatx4*)src;
-        } else {
-          b[ks] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int h = 0; h < kQW; ++h) {
+          const int64_t ch = my_ch + 64 * h;
+          const float* src = spec + row * C + ch;
+          if (kVec) {
+            dst[h] = (ch + 3 < C) ? *(const floatx4*)src : floatx4{0.f, 0.f, 0.f, 0.f};
+          } else {
+            dst[h].x = (ch + 0 < C) ? src[0] : 0.f;
+            dst[h].y = (ch + 1 < C) ? src[1] : 0.f;
+            dst[h].z = (ch + 2 < C) ? src[2] : 0.f;
+            dst[h].w = (ch + 3 < C) ? src[3] : 0.f;
+          }
         }
-      } else {
-        b[ks].x = (my_ch + 0 < C) ? src[0] : 0.f;
-        b[ks].y = (my_ch + 1 < C) ? src[1] : 0.f;
-        b[ks].z = (my_ch + 2 < C) ? src[2] : 0.f;
-        b[ks].w = (my_ch + 3 < C) ? src[3] : 0.f;
+      };
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) load(d, b[d]);
+#pragma unroll
+      for (int ks = 0; ks < kNS; ++ks) {
+        floatx4 cb_b[kQW];
+#pragma unroll
+        for (int h = 0; h < kQW; ++h) cb_b[h] = b[ks % kDepth][h];
+        if (ks + kDepth < kNS) load(ks + kDepth, b[ks % kDepth]);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if ((nzc[cb] >> ks) & 1u) {
+            const float av = sA32[(cb * kNS + ks) * 64 + lane];
+#pragma unroll
+            for (int h = 0; h < kQW; ++h) {
+              acc[cb][4 * h + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].x, acc[cb][4 * h + 0], 0, 0, 0);
+              acc[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].y, acc[cb][4 * h + 1], 0, 0, 0);
+              acc[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].z, acc[cb][4 * h + 2], 0, 0, 0);
+              acc[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].w, acc[cb][4 * h + 3], 0, 0, 0);
+            }
+          }
+        }
       }
-    }
+    } else {
 #pragma unroll
-    for (int ks = 0; ks < kSteps; ++ks) {
+      for (int ks = 0; ks < kNS; ++ks) {
+        const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
+        if (!((any >> ks) & 1u)) continue;
+        // one 64-channel group at a time: B fragments of 8 candidates (rows)
+        // x 4 channels, then the MFMAs of every non-zero cell block
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const uint32_t nz = (cb == 0) ? nz0 : (cb == 1) ? nz1 : (cb == 2) ? nz2 : nz3;
-        if ((nz >> ks) & 1u) {
-          const float a = s_A[cb][ks][lane];
-          acc[cb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks].x, acc[cb][0], 0, 0, 0);
-          acc[cb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks].y, acc[cb][1], 0, 0, 0);
-          acc[cb][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks].z, acc[cb][2], 0, 0, 0);
-          acc[cb][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks].w, acc[cb][3], 0, 0, 0);
+        for (int h = 0; h < kQW; ++h) {
+          const int64_t ch = my_ch + 64 * h;
+          uint32_t fb[4][4];   // [q][dword] (16-bit) or [q][0..1] (FP8)
+          uint32_t fbl[4][4];  // low plane (split form)
+          if (kForm == kFP8S) {
+            const uint8_t* spec = (const uint8_t*)a.spec;
+            uint32_t d[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
+              const uint8_t* src = spec + row * C + ch;
+              if (kVec) {
+                d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
+              } else {
+                d[t] = 0u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (ch + e < C) d[t] |= (uint32_t)src[e] << (8 * e);
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              fb[q][0] = ((d[0] >> (8 * q)) & 0xFFu) | (((d[1] >> (8 * q)) & 0xFFu) << 8) |
+                         (((d[2] >> (8 * q)) & 0xFFu) << 16) | (((d[3] >> (8 * q)) & 0xFFu) << 24);
+              fb[q][1] = ((d[4] >> (8 * q)) & 0xFFu) | (((d[5] >> (8 * q)) & 0xFFu) << 8) |
+                         (((d[6] >> (8 * q)) & 0xFFu) << 16) | (((d[7] >> (8 * q)) & 0xFFu) << 24);
+            }
+          } else {
+#pragma unroll
+            for (int plane = 0; plane < (kForm == kBF16Split ? 2 : 1); ++plane) {
+              const uint16_t* spec = (const uint16_t*)(plane ? a.spec_lo : a.spec);
+              uint2 d[8];
+#pragma unroll
+              for (int t = 0; t < 8; ++t) {
+                const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
+                const uint16_t* src = spec + row * C + ch;
+                if (kVec) {
+                  d[t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+                } else {
+                  const uint32_t e0 = (ch + 0 < C) ? src[0] : 0u, e1 = (ch + 1 < C) ? src[1] : 0u;
+                  const uint32_t e2 = (ch + 2 < C) ? src[2] : 0u, e3 = (ch + 3 < C) ? src[3] : 0u;
+                  d[t] = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                  const uint32_t v = elem16(d[2 * m], q) | (elem16(d[2 * m + 1], q) << 16);
+                  if (plane) fbl[q][m] = v; else fb[q][m] = v;
+                }
+            }
+          }
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            if (!((nzc[cb] >> ks) & 1u)) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              floatx4& c = acc[cb][4 * h + q];
+              if (kForm == kFP8S) {
+                const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
+                const long A = (long)(((uint64_t)av.y << 32) | av.x);
+                const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
+              } else {
+                const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
+                const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
+                if (kForm == kF16S) {
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
+                                                            __builtin_bit_cast(halfx8, bv), c, 0, 0, 0);
+                } else {
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                             __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
+                  if (kForm == kBF16Split) {
+                    const uint4 al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
+                    const uint4 bl = make_uint4(fbl[q][0], fbl[q][1], fbl[q][2], fbl[q][3]);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                               __builtin_bit_cast(bf16x8, bl), c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
+                                                               __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
+                  }
+                }
+              }
+            }
+          }
         }
       }
     }
@@ -221,14 +452,11 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma_f32(
   wtsum += __shfl_xor(wtsum, 32);
   if (lane < 16) {
     s_Wt[wave * 16 + lane] = wtsum;
-    if (wmap && blockIdx.y == 0 && my_x < g.nx && my_y < g.ny)
-      wmap[(int64_t)my_y * g.nx + my_x] = (float)wsum;
+    if (a.wmap && slab == 0 && my_x < g.nx && my_y < g.ny)
+      a.wmap[(int64_t)my_y * g.nx + my_x] = (float)wsum;
   }
   __syncthreads();
 
-  // epilogue: D[i][j] of block cb sits in lane l, register r with
-  // i = 4 (l / 16) + r (cell: x = r, y = l / 16 inside the 4 x 4 block) and
-  // j = l % 16 (channel c_w + 4 j + q of MFMA q)
   const float qnan = __builtin_nanf("");
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
@@ -239,12 +467,17 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma_f32(
       if (x >= g.nx || y >= g.ny) continue;
       const double wt = s_Wt[cb * 16 + 4 * (lane >> 4) + r];
       const float inv = (wt > 0.0) ? (float)(1.0 / wt) : 0.f;
-      const int64_t cell = (int64_t)y * g.nx + x;
+      const int64_t cellidx = (int64_t)y * g.nx + x;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t ch = my_ch + q;
-        if (ch < C) cube[ch * G + cell] = (wt > 0.0) ? acc[cb][q][r] * inv : qnan;
-      }
+      for (int h = 0; h < kQW; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t ch = my_ch + 64 * h + q;
+          if (ch >= C) continue;
+          float v = acc[cb][4 * h + q][r] * inv;
+          if (kForm == kF16S || kForm == kFP8S) v *= a.scale[ch];
+          a.cube[ch * G + cellidx] = (wt > 0.0) ? v : qnan;
+        }
     }
   }
 }
@@ -345,6 +578,52 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
   return HCG_OK;
 }
 
+template <int kForm>
+static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void* spec_lo,
+                              const float* scale, int64_t C, float* cube, float* wmap,
+                              hipStream_t stream) {
+  GatherArgs a;
+  a.trig = p->trig;
+  a.perm = p->perm;
+  a.ranges = p->ranges;
+  a.nranges = p->nranges;
+  a.maxr = p->maxr;
+  a.spec = spec;
+  a.spec_lo = spec_lo;
+  a.scale = scale;
+  a.C = C;
+  a.g = p->grid;
+  a.ntx = p->ntx;
+  a.ntiles = p->ntx * p->nty;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.hR = std::pow(std::sin(0.5 * p->support_rad), 2);
+  a.inv_two_sig2 = 1.0 / (2.0 * p->sigma_rad * p->sigma_rad);
+  a.cube = cube;
+  a.wmap = wmap;
+  const size_t esz = (kForm == kF32) ? 4 : (kForm == kFP8S) ? 1 : 2;
+  const bool vec = (C % 4 == 0) && ((uintptr_t)spec % (4 * esz) == 0) &&
+                   (!spec_lo || (uintptr_t)spec_lo % (4 * esz) == 0);
+  // 512-channel slabs (weights computed once per 512 channels) where the
+  // registers allow it, else 256
+  const int qw = (C > 256 && vec && kForm != kBF16Split) ? 2 : 1;
+  const int64_t slab_ch = 256 * qw;
+  const int64_t slabs = (C + slab_ch - 1) / slab_ch;
+  const int64_t blocks = slabs * a.tiles_per_xcd * 8;
+  if (blocks > INT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
+  const dim3 grid((unsigned)blocks), block(256);
+  if constexpr (kForm != kBF16Split) {
+    if (qw == 2) {
+      k_gather_mfma<kForm, 2, true><<<grid, block, 0, stream>>>(a);
+      HCG_LAUNCH_CHECK("k_gather_mfma");
+      return HCG_OK;
+    }
+  }
+  if (vec) k_gather_mfma<kForm, 1, true><<<grid, block, 0, stream>>>(a);
+  else k_gather_mfma<kForm, 1, false><<<grid, block, 0, stream>>>(a);
+  HCG_LAUNCH_CHECK("k_gather_mfma");
+  return HCG_OK;
+}
+
 extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan,
                                hcg_dtype dtype, const float* chan_scale, float* cube,
                                float* weights, void* hip_stream) {
@@ -352,31 +631,29 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
   if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid: not a live plan");
   if (!spectra || !cube) return fail(HCG_E_ARG, "hcg_grid: spectra and cube must not be NULL");
   if (nchan < 1) return fail(HCG_E_ARG, "hcg_grid: nchan must be >= 1");
-  if (dtype != HCG_F32) return fail(HCG_E_UNSUPPORTED, "hcg_grid: dtype %d is not built", (int)dtype);
-  if (chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale must be NULL for HCG_F32");
+  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED);
+  if (dtype < HCG_F32 || dtype > HCG_FP8E4M3_SCALED)
+    return fail(HCG_E_UNSUPPORTED, "hcg_grid: unknown dtype %d", (int)dtype);
+  if (scaled && !chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale is required for this dtype");
+  if (!scaled && chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale must be NULL for this dtype");
   const hcg_plan_s* p = plan;
   hipStream_t stream = (hipStream_t)hip_stream;
-  const float* spec = (const float*)spectra;
-  if (nchan <= 8) return launch_cells(p, spec, (int)nchan, cube, weights, stream);
-
-  // the W map (if asked for) is written by the workgroups of the first slab
-  const double hR = std::pow(std::sin(0.5 * p->support_rad), 2);
-  const double inv2 = 1.0 / (2.0 * p->sigma_rad * p->sigma_rad);
-  const int64_t slabs = (nchan + kChanPerWG - 1) / kChanPerWG;
-  if (slabs > 65535) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
-  dim3 grid((unsigned)(p->ntx * p->nty), (unsigned)slabs);
-  const bool vec4 = (nchan % 4 == 0) && (((uintptr_t)spec & 15) == 0);
-  float* wmap = weights;
-  if (vec4)
-    k_gather_mfma_f32<true><<<grid, 256, 0, stream>>>(p->trig, p->perm, p->ranges, p->nranges,
-                                                      p->maxr, spec, nchan, p->grid, p->ntx, hR,
-                                                      inv2, cube, wmap);
-  else
-    k_gather_mfma_f32<false><<<grid, 256, 0, stream>>>(p->trig, p->perm, p->ranges, p->nranges,
-                                                       p->maxr, spec, nchan, p->grid, p->ntx, hR,
-                                                       inv2, cube, wmap);
-  HCG_LAUNCH_CHECK("k_gather_mfma_f32");
-  return HCG_OK;
+  switch (dtype) {
+    case HCG_F32:
+      if (nchan <= 8) return launch_cells(p, (const float*)spectra, (int)nchan, cube, weights, stream);
+      return launch_mfma<kF32>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
+    case HCG_BF16:
+      return launch_mfma<kBF16>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
+    case HCG_BF16_SPLIT:
+      return launch_mfma<kBF16Split>(p, spectra,
+                                     (const char*)spectra + (size_t)2 * p->n * nchan, nullptr,
+                                     nchan, cube, weights, stream);
+    case HCG_F16_SCALED:
+      return launch_mfma<kF16S>(p, spectra, nullptr, chan_scale, nchan, cube, weights, stream);
+    case HCG_FP8E4M3_SCALED:
+      return launch_mfma<kFP8S>(p, spectra, nullptr, chan_scale, nchan, cube, weights, stream);
+  }
+  return fail(HCG_E_UNSUPPORTED, "hcg_grid: dtype %d", (int)dtype);
 }
 
 extern "C" hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats,

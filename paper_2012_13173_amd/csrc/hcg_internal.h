@@ -92,6 +92,51 @@ __device__ inline uint32_t lower_bound_u32(const uint32_t* __restrict__ keys, ui
   return lo;
 }
 
+// ---------------------------------------------------------------------------
+// Element encodings of the low-precision forms (round to nearest even).
+// ---------------------------------------------------------------------------
+// float -> bfloat16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint32_t f32_to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0u;
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ uint32_t f32_to_f16(float x) {
+  const _Float16 h = (_Float16)x;  // round to nearest even
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+// float -> OCP FP8 E4M3 (bias 7, no infinities, max 448, 0x7F = NaN), round
+// to nearest even, saturating at 448.
+__device__ __forceinline__ uint32_t f32_to_e4m3(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t a = u & 0x7FFFFFFFu;
+  if (a > 0x7F800000u) return sign | 0x7Fu;
+  const float fa = __uint_as_float(a);
+  if (fa < 0.015625f) {  // below 2^-6: subnormal steps of 2^-9
+    const uint32_t m = (uint32_t)rintf(fa * 512.0f);  // 0 .. 8 (8 = smallest normal)
+    return sign | m;
+  }
+  // keep 3 mantissa bits with round to nearest even
+  const uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
+  const int e = (int)(r >> 23) - 127;
+  const uint32_t m = (r >> 20) & 7u;
+  if (e > 8 || (e == 8 && m == 7u)) return sign | 0x7Eu;  // saturate to 448
+  return sign | ((uint32_t)(e + 7) << 3) | m;
+}
+__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  const float v = (e == 0) ? (float)m * 0.001953125f
+                           : __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return (c & 0x80u) ? -v : v;
+}
+
 }  // namespace hcg
 
 // The plan object behind hcg_plan_t.  Every device array lives in one arena.

@@ -63,11 +63,13 @@ __device__ __noinline__ uint32_t ang2pix_ring(int ns_i, double lon_deg, double l
   return (uint32_t)(12 * ns * ns - 2 * ir * (ir + 1) + ip);
 }
 
-// stat[0] = min pixel, stat[1] = max pixel, stat[2] = count of bad inputs
+// stat[0] = min pixel, stat[1] = max pixel, stat[2] = count of bad inputs.
+// Grid-stride over the samples; one set of atomics per block.
 __global__ void __launch_bounds__(256) k_ang2pix(const double* __restrict__ lon,
                                                  const double* __restrict__ lat, int64_t n,
                                                  int ns, uint32_t* __restrict__ pix,
                                                  uint32_t* __restrict__ stat) {
+  __shared__ uint32_t s_red[3][4];
   uint32_t vmin = 0xFFFFFFFFu, vmax = 0u, bad = 0u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -88,7 +90,19 @@ __global__ void __launch_bounds__(256) k_ang2pix(const double* __restrict__ lon,
     vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
     bad += (uint32_t)__shfl_xor((int)bad, off);
   }
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    s_red[0][wave] = vmin;
+    s_red[1][wave] = vmax;
+    s_red[2][wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      vmin = min(vmin, s_red[0][w]);
+      vmax = max(vmax, s_red[1][w]);
+      bad += s_red[2][w];
+    }
     atomicMin(&stat[0], vmin);
     atomicMax(&stat[1], vmax);
     if (bad) atomicAdd(&stat[2], bad);
@@ -100,7 +114,7 @@ hcg_status launch_ang2pix(const double* lon, const double* lat, int64_t n, int n
   const uint32_t init[4] = {0xFFFFFFFFu, 0u, 0u, 0u};
   HCG_HIP(hipMemcpyAsync(stat, init, sizeof(init), hipMemcpyHostToDevice, stream));
   if (n == 0) return HCG_OK;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 64);
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
   k_ang2pix<<<(unsigned)blocks, 256, 0, stream>>>(lon, lat, n, nside, pix, stat);
   HCG_LAUNCH_CHECK("k_ang2pix");
   return HCG_OK;
@@ -343,25 +357,77 @@ __global__ void k_ring_csr(const uint32_t* __restrict__ keys, int64_t n, int ns,
 // pixel spacing of its pixel centre in longitude), turned into a pixel range
 // and then into a range of sorted positions by binary search inside the ring.
 // ---------------------------------------------------------------------------
-struct RangeSink {
-  uint2* out;
-  uint32_t count, maxr, total;
-  bool overflow;
-  __device__ void add(uint32_t a, uint32_t b) {
-    if (b <= a) return;
-    total += b - a;
-    if (count > 0 && out[count - 1].y == a) { out[count - 1].y = b; return; }
-    if (count >= maxr) { overflow = true; return; }
-    out[count++] = make_uint2(a, b);
-  }
+// Ranges of ring i for the tile: up to two [a, b) pieces, in key order.
+struct RingRanges {
+  uint32_t a0, b0, a1, b1;
 };
 
-__global__ void __launch_bounds__(64) k_tile_ranges(
+__device__ RingRanges ring_ranges(int i, const uint32_t* __restrict__ keys,
+                                  const uint32_t* __restrict__ csr, int ns, int ring_first,
+                                  uint32_t pix_base, double lon_a, double lon_b, double lat_a,
+                                  double lat_b, double Rs, double hR, double cos_g) {
+  RingRanges out{0u, 0u, 0u, 0u};
+  const double zt = hpx_ring_z(ns, i - 1), zb = hpx_ring_z(ns, i + 1);
+  const double d_hi = asin(fmin(1.0, zt)), d_lo = asin(fmax(-1.0, zb));
+  const double dmin = fmax(0.0, fmax(d_lo - lat_b, lat_a - d_hi));
+  if (dmin > Rs) return out;
+  const double sd = sin(0.5 * dmin);
+  const double hrem = hR - sd * sd;
+  if (hrem < 0.0) return out;
+  const uint32_t ra = csr[i - ring_first], rb = csr[i - ring_first + 1];
+  if (rb <= ra) return out;
+  const double cos_n = cos(fmax(fabs(d_lo), fabs(d_hi)));
+  const double denom = cos_g * cos_n;
+  bool whole = !(denom > 1e-300) || hrem >= denom;
+  double dal = 0.0;
+  if (!whole) {
+    dal = 2.0 * asin(sqrt(hrem / denom));
+    whole = (lon_b - lon_a) + 2.0 * dal >= 2.0 * kPi;
+  }
+  const int64_t npix = hpx_ring_npix(ns, i);
+  const int64_t start = hpx_ring_start(ns, i);
+  int64_t j_lo = 0, j_hi = 0;
+  if (!whole) {
+    const double shift = (i < ns || i > 3 * ns) ? 0.5 : 0.5 * (double)((i - ns + 1) & 1);
+    const double width = 2.0 * kPi / (double)npix;
+    const double x_lo = (lon_a - dal - 0.5 * width) / width - shift;
+    const double x_hi = (lon_b + dal + 0.5 * width) / width - shift;
+    j_lo = (int64_t)ceil(x_lo - 1e-7);
+    j_hi = (int64_t)floor(x_hi + 1e-7);
+    whole = (j_hi - j_lo + 1) >= npix;
+  }
+  if (whole) {
+    out.a0 = ra;
+    out.b0 = rb;
+    return out;
+  }
+  if (j_hi < j_lo) return out;
+  int64_t jl = j_lo % npix;
+  if (jl < 0) jl += npix;
+  int64_t jh = j_hi % npix;
+  if (jh < 0) jh += npix;
+  const int64_t base = (int64_t)pix_base;
+  if (jl <= jh) {
+    out.a0 = lower_bound_u32(keys, ra, rb, start + jl - base);
+    out.b0 = lower_bound_u32(keys, out.a0, rb, start + jh + 1 - base);
+  } else {  // wraps through longitude 0 of this ring: two pieces, in key order
+    out.a0 = ra;
+    out.b0 = lower_bound_u32(keys, ra, rb, start + jh + 1 - base);
+    out.a1 = lower_bound_u32(keys, out.b0, rb, start + jl - base);
+    out.b1 = rb;
+  }
+  return out;
+}
+
+// One wave per tile; lane r handles ring i_lo + r (+64, ...).  Ranges are
+// written in ring order, two slots at most per ring.
+__global__ void __launch_bounds__(256) k_tile_ranges(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ csr, int ns, int ring_first,
     int ring_last, uint32_t pix_base, GridGeom g, int ntx, int nty, double support_rad, int maxr,
     uint2* __restrict__ ranges, uint32_t* __restrict__ nranges, uint32_t* __restrict__ ncand,
     uint32_t* __restrict__ flags) {
-  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (tile >= ntx * nty) return;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ix0 = tx * kTileX, ix1 = min(g.nx, ix0 + kTileX) - 1;
@@ -382,57 +448,37 @@ __global__ void __launch_bounds__(64) k_tile_ranges(
   const double z_bot = sin(fmax(-half_pi, lat_a - Rs));
   const int i_lo = max(ring_first, (int)floor(hpx_ring_of_z(ns, z_top)) - 2);
   const int i_hi = min(ring_last, (int)ceil(hpx_ring_of_z(ns, z_bot)) + 2);
-
-  RangeSink sink{ranges + (int64_t)tile * maxr, 0u, (uint32_t)maxr, 0u, false};
-  for (int i = i_lo; i <= i_hi; ++i) {
-    const double zt = hpx_ring_z(ns, i - 1), zb = hpx_ring_z(ns, i + 1);
-    const double d_hi = asin(fmin(1.0, zt)), d_lo = asin(fmax(-1.0, zb));
-    const double dmin = fmax(0.0, fmax(d_lo - lat_b, lat_a - d_hi));
-    if (dmin > Rs) continue;
-    const double sd = sin(0.5 * dmin);
-    const double hrem = hR - sd * sd;
-    if (hrem < 0.0) continue;
-    const double cos_n = cos(fmax(fabs(d_lo), fabs(d_hi)));
-    const double denom = cos_g * cos_n;
-    const uint32_t ra = csr[i - ring_first], rb = csr[i - ring_first + 1];
-    if (rb <= ra) continue;
-    bool whole = !(denom > 1e-300) || hrem >= denom;
-    double dal = 0.0;
-    if (!whole) {
-      dal = 2.0 * asin(sqrt(hrem / denom));
-      whole = (lon_b - lon_a) + 2.0 * dal >= 2.0 * kPi;
+  uint2* out = ranges + (int64_t)tile * maxr;
+  uint32_t count = 0, total = 0;
+  bool overflow = false;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int base = i_lo; base <= i_hi; base += 64) {
+    const int i = base + lane;
+    RingRanges rr{0u, 0u, 0u, 0u};
+    if (i <= i_hi)
+      rr = ring_ranges(i, keys, csr, ns, ring_first, pix_base, lon_a, lon_b, lat_a, lat_b, Rs,
+                       hR, cos_g);
+    const bool h0 = rr.b0 > rr.a0, h1 = rr.b1 > rr.a1;
+    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+    const uint32_t off = count + (uint32_t)__popcll(m0 & lt_mask) + (uint32_t)__popcll(m1 & lt_mask);
+    uint32_t slot = off;
+    if (h0) {
+      if (slot < (uint32_t)maxr) out[slot] = make_uint2(rr.a0, rr.b0); else overflow = true;
+      ++slot;
     }
-    const int64_t npix = hpx_ring_npix(ns, i);
-    const int64_t start = hpx_ring_start(ns, i);
-    int64_t j_lo = 0, j_hi = 0;
-    if (!whole) {
-      const double shift = (i < ns || i > 3 * ns) ? 0.5 : 0.5 * (double)((i - ns + 1) & 1);
-      const double width = 2.0 * kPi / (double)npix;
-      const double x_lo = (lon_a - dal - 0.5 * width) / width - shift;
-      const double x_hi = (lon_b + dal + 0.5 * width) / width - shift;
-      j_lo = (int64_t)ceil(x_lo - 1e-7);
-      j_hi = (int64_t)floor(x_hi + 1e-7);
-      whole = (j_hi - j_lo + 1) >= npix;
+    if (h1) {
+      if (slot < (uint32_t)maxr) out[slot] = make_uint2(rr.a1, rr.b1); else overflow = true;
     }
-    if (whole) { sink.add(ra, rb); continue; }
-    if (j_hi < j_lo) continue;
-    int64_t jl = j_lo % npix; if (jl < 0) jl += npix;
-    int64_t jh = j_hi % npix; if (jh < 0) jh += npix;
-    const int64_t base = (int64_t)pix_base;
-    if (jl <= jh) {
-      const uint32_t a = lower_bound_u32(keys, ra, rb, start + jl - base);
-      const uint32_t b = lower_bound_u32(keys, a, rb, start + jh + 1 - base);
-      sink.add(a, b);
-    } else {  // wraps through longitude 0 of this ring: two pieces, in key order
-      const uint32_t b0 = lower_bound_u32(keys, ra, rb, start + jh + 1 - base);
-      sink.add(ra, b0);
-      const uint32_t a1 = lower_bound_u32(keys, b0, rb, start + jl - base);
-      sink.add(a1, rb);
-    }
+    uint32_t len = (h0 ? rr.b0 - rr.a0 : 0u) + (h1 ? rr.b1 - rr.a1 : 0u);
+    for (int o = 32; o > 0; o >>= 1) len += (uint32_t)__shfl_xor((int)len, o);
+    total += len;
+    count += (uint32_t)(__popcll(m0) + __popcll(m1));
   }
-  nranges[tile] = sink.count;
-  ncand[tile] = sink.total;
-  if (sink.overflow) atomicOr(&flags[0], 1u);
+  if (__ballot(overflow) && lane == 0) atomicOr(&flags[0], 1u);
+  if (lane == 0) {
+    nranges[tile] = min(count, (uint32_t)maxr);
+    ncand[tile] = total;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -638,7 +684,7 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
       p->keys, n, nside, ring_first, nrings, pix_base, p->csr);
   HCG_LAUNCH_CHECK("k_ring_csr");
   HCG_HIP(hipMemsetAsync(p->flags, 0, 16, stream));
-  k_tile_ranges<<<(unsigned)((ntiles + 63) / 64), 64, 0, stream>>>(
+  k_tile_ranges<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
       p->keys, p->csr, nside, ring_first, ring_last, pix_base, p->grid, ntx, nty, R, maxr,
       p->ranges, p->nranges, p->ncand, p->flags);
   HCG_LAUNCH_CHECK("k_tile_ranges");

@@ -120,6 +120,9 @@ def test_grid_argument_errors():
     vp = ctypes.c_void_p
     assert lib.hcg_grid(plan.handle, None, 4, 0, None, vp(cube.data_ptr()), None, None) == hcg.HCG_E_ARG
     assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 0, 0, None, vp(cube.data_ptr()), None, None) == hcg.HCG_E_ARG
-    assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, 1, None, vp(cube.data_ptr()), None, None) == hcg.HCG_E_UNSUPPORTED
+    assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, 7, None, vp(cube.data_ptr()), None, None) == hcg.HCG_E_UNSUPPORTED
+    # chan_scale is required by the scaled forms and refused by the others
+    assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, hcg.HCG_F16_SCALED, None, vp(cube.data_ptr()), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, hcg.HCG_F32, vp(spec.data_ptr()), vp(cube.data_ptr()), None, None) == hcg.HCG_E_ARG
     plan.destroy()
     assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, 0, None, vp(cube.data_ptr()), None, None) in (hcg.HCG_E_ARG, hcg.HCG_E_STATE)
