@@ -256,6 +256,76 @@ hcg_status hcg_ang2pix(const double* lon_deg, const double* lat_deg, int64_t n, 
 hcg_status hcg_sort_keys(const uint32_t* keys_in, int64_t n, int32_t key_bits, uint32_t* keys_out,
                          uint32_t* perm_out, void* hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent maps of uneven size in one persistent launch.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hcg_batch_s* hcg_batch_t;
+
+/* One field of a batch: the arguments of hcg_plan. */
+typedef struct {
+  const double* lon_deg; /* device float64 [n] */
+  const double* lat_deg; /* device float64 [n] */
+  int64_t n;
+  hcg_grid_desc grid;
+  double fwhm_deg;
+  double support_deg;
+} hcg_field_desc;
+
+/* The data of one field for hcg_grid_batch (FP32 spectra). */
+typedef struct {
+  const float* spectra; /* device float32 [n][nchan], input sample order */
+  int64_t nchan;        /* >= 1 */
+  float* cube;          /* device float32 [nchan][ny][nx] */
+  float* weights;       /* device float32 [ny][nx] or NULL */
+} hcg_field_data;
+
+/*
+ * hcg_plan_batch -- one plan per field (the steps of hcg_plan for each).
+ *   fields  host array [nfields] (pointers inside are device pointers).
+ *   opts    host pointer or NULL.  opts->chan_tile selects the channel slab
+ *           of the persistent kernel: 0 = autotune on the first
+ *           hcg_grid_batch call, 256 or 512 = fixed (items ordered by cost);
+ *           nside and tile fields apply to every field as in hcg_plan.
+ * Synchronous.  Errors as hcg_plan, with the failing field named in the
+ * message; nothing leaks on failure.
+ */
+hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_desc* fields,
+                          const hcg_opts* opts, void* hip_stream);
+
+/*
+ * hcg_grid_batch -- Eq. (1) for every field of the batch in one launch.
+ *   data  host array [nfields] in the order given to hcg_plan_batch.
+ * Every (field, tile, channel slab) is a work item; a persistent kernel of
+ * two workgroups per CU pops the items, ordered largest-cost first, from a
+ * shared counter.  The first call may run the batch several times to
+ * autotune (same results every time); it then captures the launch in a
+ * hipGraph that later calls replay.  Pointers and channel counts may change
+ * between calls (the device tables are rewritten before the replay).
+ * Asynchronous on hip_stream after the first call (which synchronises).
+ * Errors: HCG_E_ARG (NULL pointers, nchan < 1), HCG_E_STATE (not a live
+ * batch), HCG_E_NOMEM, HCG_E_DEVICE.  Calls on one batch must not overlap.
+ */
+hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* data, void* hip_stream);
+
+/* Waits for the device, then frees the batch and its plans.  NULL is a
+ * no-op; a handle that is not a live batch gives HCG_E_STATE. */
+hcg_status hcg_destroy_batch(hcg_batch_t batch);
+
+typedef struct {
+  int32_t nfields;
+  int32_t chan_slab;         /* channels per work item for C > 8 (256 or 512) */
+  int32_t cost_order;        /* 1: items by decreasing cost; 0: by field, tile */
+  int32_t tuned;             /* 1 once the configuration is fixed */
+  int32_t graph_captured;    /* 1 once the launch is captured */
+  int32_t persistent_blocks; /* workgroups of the persistent kernel */
+  int64_t items;             /* work items of the last build */
+  double tune_ms[4];         /* autotuner timings: (256, cost), (512, cost),
+                                (256, natural), (512, natural); 0 if skipped */
+} hcg_batch_info;
+
+hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info);
+
 #ifdef __cplusplus
 }
 #endif

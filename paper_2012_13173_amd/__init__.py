@@ -6,7 +6,8 @@ device memory and streams.  The binding raises if the compiled library is
 missing; there is no fallback implementation.
 
 Names mirror the C ABI: ``hcg_plan``, ``hcg_grid``, ``hcg_destroy``,
-``hcg_ang2pix``, ``hcg_sort_keys``, ``hcg_get_plan_info``, ``hcg_export``,
+``hcg_quantize``, ``hcg_plan_batch``, ``hcg_grid_batch``, ``hcg_ang2pix``,
+``hcg_sort_keys``, ``hcg_get_plan_info``, ``hcg_export``,
 ``hcg_get_plan_stats``.
 """
 from __future__ import annotations
@@ -59,9 +60,28 @@ class PlanStatsC(ctypes.Structure):
                 ("cells", ctypes.c_int64)]
 
 
+class FieldDescC(ctypes.Structure):
+    _fields_ = [("lon_deg", ctypes.c_void_p), ("lat_deg", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("grid", GridDescC), ("fwhm_deg", ctypes.c_double),
+                ("support_deg", ctypes.c_double)]
+
+
+class FieldDataC(ctypes.Structure):
+    _fields_ = [("spectra", ctypes.c_void_p), ("nchan", ctypes.c_int64),
+                ("cube", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
+class BatchInfoC(ctypes.Structure):
+    _fields_ = [("nfields", ctypes.c_int32), ("chan_slab", ctypes.c_int32),
+                ("cost_order", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("graph_captured", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
+                ("items", ctypes.c_int64), ("tune_ms", ctypes.c_double * 4)]
+
+
 EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_plan_info",
             "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
-            "hcg_sort_keys", "hcg_quantize"]
+            "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
+            "hcg_destroy_batch", "hcg_get_batch_info"]
 
 _lib = None
 
@@ -88,6 +108,11 @@ def load(path: str = LIB_PATH):
     lib.hcg_ang2pix.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.hcg_sort_keys.argtypes = [vp, i64, i32, vp, vp, vp]
     lib.hcg_quantize.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp, vp]
+    lib.hcg_plan_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(FieldDescC),
+                                   ctypes.POINTER(OptsC), vp]
+    lib.hcg_grid_batch.argtypes = [vp, ctypes.POINTER(FieldDataC), vp]
+    lib.hcg_destroy_batch.argtypes = [vp]
+    lib.hcg_get_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfoC)]
     for name in EXPORTED:
         if name != "hcg_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -243,6 +268,68 @@ def hcg_sort_keys(keys: torch.Tensor, key_bits: int, stream=None):
                               _stream(stream))
     _check(st, "hcg_sort_keys")
     return ko, po
+
+
+class Batch:
+    """Owns an hcg_batch_t (one plan per field)."""
+
+    def __init__(self, handle: ctypes.c_void_p, grids):
+        self.handle = handle
+        self.grids = grids
+
+    def info(self) -> dict:
+        out = BatchInfoC()
+        _check(load().hcg_get_batch_info(self.handle, ctypes.byref(out)), "hcg_get_batch_info")
+        d = {k: getattr(out, k) for k, _ in BatchInfoC._fields_}
+        d["tune_ms"] = list(out.tune_ms)
+        return d
+
+    def destroy(self) -> None:
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            _check(load().hcg_destroy_batch(h), "hcg_destroy_batch")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def hcg_plan_batch(fields, chan_tile: int = 0, nside: int = 0, stream=None) -> Batch:
+    """``fields``: sequence of (lon, lat, grid, fwhm_deg, support_deg), lon/lat
+    device float64 tensors (read during the call only)."""
+    arr = (FieldDescC * len(fields))()
+    for i, (lon, lat, grid, fwhm, support) in enumerate(fields):
+        if int(lat.shape[0]) != int(lon.shape[0]):
+            raise ValueError(f"field {i}: lon and lat differ in length")
+        arr[i] = FieldDescC(_dptr(lon, torch.float64, "lon"), _dptr(lat, torch.float64, "lat"),
+                            int(lon.shape[0]), grid_desc(grid), float(fwhm), float(support))
+    opts = OptsC(int(nside), 0, 0, 0, int(chan_tile), 0)
+    handle = ctypes.c_void_p()
+    _check(load().hcg_plan_batch(ctypes.byref(handle), len(fields), arr, ctypes.byref(opts),
+                                 _stream(stream)), "hcg_plan_batch")
+    return Batch(handle, [f[2] for f in fields])
+
+
+def hcg_grid_batch(batch: Batch, spectra, cubes, weights=None, stream=None) -> None:
+    """Grids every field: ``spectra[i]`` [n_i, C_i] float32 into ``cubes[i]``
+    [C_i, ny_i, nx_i] (and ``weights[i]`` [ny_i, nx_i] or None).  The tensors
+    must stay alive until the work has run."""
+    nf = len(batch.grids)
+    if len(spectra) != nf or len(cubes) != nf:
+        raise ValueError(f"need {nf} spectra and cubes")
+    weights = weights if weights is not None else [None] * nf
+    arr = (FieldDataC * nf)()
+    for i in range(nf):
+        g, sp, cb = batch.grids[i], spectra[i], cubes[i]
+        C = int(sp.shape[1])
+        if tuple(cb.shape) != (C, g.ny, g.nx):
+            raise ValueError(f"field {i}: cube must be [{C}, {g.ny}, {g.nx}]")
+        arr[i] = FieldDataC(_dptr(sp, torch.float32, "spectra"), C,
+                            _dptr(cb, torch.float32, "cube"),
+                            _dptr(weights[i], torch.float32, "weights"))
+    _check(load().hcg_grid_batch(batch.handle, arr, _stream(stream)), "hcg_grid_batch")
 
 
 def u32(t: torch.Tensor):

@@ -121,22 +121,6 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 // Output D[i][j]: lane l, register r holds cell 4 (l/16) + r of the block and
 // channel 4 (l % 16) + q of the group.
 // ---------------------------------------------------------------------------
-struct GatherArgs {
-  const double4* trig;
-  const uint32_t* perm;
-  const uint2* ranges;
-  const uint32_t* nranges;
-  int maxr;
-  const void* spec;     // [n][C] in the form's storage type
-  const void* spec_lo;  // low plane for the split form
-  const float* scale;   // [C] per-channel scale for the scaled forms
-  int64_t C;
-  GridGeom g;
-  int ntx, ntiles, tiles_per_xcd;
-  double hR, inv_two_sig2;
-  float* cube;
-  float* wmap;
-};
 
 template <int kForm>
 struct FormTraits;
@@ -170,26 +154,31 @@ __device__ __forceinline__ uint32_t elem16(uint2 d, int q) {
   return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// LDS of one workgroup of the gather (shared by the per-plan kernel and the
+// persistent batch kernel).
+struct GatherSmem {
+  uint2 rng[kMaxRangesLimit];
+  uint32_t pre[kMaxRangesLimit + 1];
+  double4 trig[kKB];
+  uint32_t row[kKB];
+  uint4 Araw[1024];
+  uint32_t nz[4];
+  double Wt[kTileCells];
+};
+
+// One (tile, channel slab) of the contraction; all 256 threads take part.
 template <int kForm, int kQW, bool kVec>
-__global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
+__device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int slab,
+                                            GatherSmem& sm) {
   constexpr int kK = FormTraits<kForm>::kK;
   constexpr int kNS = kKB / kK;  // k-steps per staged block
-  __shared__ uint2 s_rng[kMaxRangesLimit];
-  __shared__ uint32_t s_pre[kMaxRangesLimit + 1];
-  __shared__ double4 s_trig[kKB];
-  __shared__ uint32_t s_row[kKB];
-  __shared__ uint4 s_Araw[(kForm == kF32) ? 1024 : (kForm == kBF16Split) ? 1024 : 512];
-  __shared__ uint32_t s_nz[4];
-  __shared__ double s_Wt[kTileCells];
-
-  // XCD-aware order: the hardware deals consecutive workgroups to the eight
-  // XCDs in turn; give each XCD a contiguous run of tiles so that tiles that
-  // share candidate rows run together behind the same L2.
-  const int per_slab = a.tiles_per_xcd * 8;
-  const int slab = blockIdx.x / per_slab;
-  const int local = blockIdx.x - slab * per_slab;
-  const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
-  if (tile >= a.ntiles) return;
+  uint2* s_rng = sm.rng;
+  uint32_t* s_pre = sm.pre;
+  double4* s_trig = sm.trig;
+  uint32_t* s_row = sm.row;
+  uint4* s_Araw = sm.Araw;
+  uint32_t* s_nz = sm.nz;
+  double* s_Wt = sm.Wt;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
@@ -482,6 +471,120 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   }
 }
 
+template <int kForm, int kQW, bool kVec>
+__global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
+  __shared__ GatherSmem sm;
+  // XCD-aware order: the hardware deals consecutive workgroups to the eight
+  // XCDs in turn; give each XCD a contiguous run of tiles so that tiles that
+  // share candidate rows run together behind the same L2.
+  const int per_slab = a.tiles_per_xcd * 8;
+  const int slab = blockIdx.x / per_slab;
+  const int local = blockIdx.x - slab * per_slab;
+  const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
+  if (tile >= a.ntiles) return;
+  gather_tile<kForm, kQW, kVec>(a, tile, slab, sm);
+}
+
+// Few channels (C <= 8) for a 256-thread workgroup: one lane per cell, the
+// four waves take every fourth block of 64 candidates and their FP64 partial
+// sums are added at the end.
+__device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const GridGeom& g = a.g;
+  const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
+  const CellTrig cell = cell_trig(g, ix, iy);
+  const uint32_t total =
+      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
+  const int C = (int)a.C;
+  const float* spec = (const float*)a.spec;
+  double4* wtrig = (double4*)sm.Araw + wave * kKB;                     // [4][64]
+  float* wspec = (float*)((double4*)sm.Araw + 4 * kKB) + wave * kKB * 8;  // [4][64][8]
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  double wsum = 0.0;
+  uint32_t cur = 0;
+  const uint32_t nblk = (total + kKB - 1) / kKB;
+  for (uint32_t b0 = 0; b0 < nblk; b0 += 4) {
+    const uint32_t blk = b0 + wave;
+    const uint32_t q = blk * kKB + lane;
+    if (blk < nblk && q < total) {
+      const uint32_t pos = cand_pos(q, sm.rng, sm.pre, &cur);
+      wtrig[lane] = a.trig[pos];
+      const int64_t row = a.perm[pos];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) wspec[lane * 8 + c] = (c < C) ? spec[row * C + c] : 0.f;
+    } else {
+      const double nan = __builtin_nan("");
+      wtrig[lane] = make_double4(nan, nan, nan, nan);
+    }
+    __syncthreads();
+    if (blk < nblk) {
+      const int kmax = (int)min<uint32_t>(kKB, total - blk * kKB);
+      for (int k = 0; k < kmax; ++k) {
+        const double h = pair_hav(cell, wtrig[k]);
+        if (h <= a.hR) {
+          const double w = exp(-dist2_from_hav(h) * a.inv_two_sig2);
+          wsum += w;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) acc[c] += w * (double)wspec[k * 8 + c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* red = (double*)sm.Araw;  // [9][64]
+  for (int w = 1; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) red[c * 64 + lane] = acc[c];
+      red[8 * 64 + lane] = wsum;
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c] += red[c * 64 + lane];
+      wsum += red[8 * 64 + lane];
+    }
+    __syncthreads();
+  }
+  if (wave != 0 || ix >= g.nx || iy >= g.ny) return;
+  const int64_t G = (int64_t)g.nx * g.ny;
+  const int64_t cellidx = (int64_t)iy * g.nx + ix;
+  if (a.wmap) a.wmap[cellidx] = (float)wsum;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (c < C) a.cube[c * G + cellidx] = (wsum > 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
+}
+
+// Persistent batch kernel (FP32 spectra): every workgroup pops work items
+// (field, tile, channel slab) from a shared counter until the list, ordered
+// by the host, is exhausted.  ctl[0] = next item, ctl[1] = item count.
+__global__ void k_batch_reset(uint32_t* __restrict__ ctl) { ctl[0] = 0u; }
+
+template <int kQW>
+__global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
+                                                         const BatchItem* __restrict__ items,
+                                                         uint32_t* __restrict__ ctl) {
+  __shared__ GatherSmem sm;
+  __shared__ uint32_t s_item;
+  const uint32_t nitems = ctl[1];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    __syncthreads();
+    if (it >= nitems) break;
+    const BatchItem bi = items[it];
+    const GatherArgs a = fields[bi.field];
+    if (a.C <= 8) gather_cells_tile_wg(a, (int)bi.tile, sm);
+    else if (a.vec) gather_tile<kF32, kQW, true>(a, (int)bi.tile, (int)bi.slab, sm);
+    else gather_tile<kF32, 1, false>(a, (int)bi.tile, (int)bi.slab, sm);  // 256-channel slabs
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Few channels (C <= 8) and pair counting: one lane per cell of the 8 x 8
 // tile, candidates staged 64 at a time, FP64 accumulation.
@@ -556,10 +659,6 @@ __global__ void __launch_bounds__(64) k_gather_cells(
     if (c < C) cube[c * G + cellidx] = (wsum > 0.0) ? (float)(accv[c] / wsum) : __builtin_nanf("");
 }
 
-}  // namespace hcg
-
-using namespace hcg;
-
 static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, float* cube,
                                float* wmap, hipStream_t stream) {
   const double hR = std::pow(std::sin(0.5 * p->support_rad), 2);
@@ -603,6 +702,7 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   const size_t esz = (kForm == kF32) ? 4 : (kForm == kFP8S) ? 1 : 2;
   const bool vec = (C % 4 == 0) && ((uintptr_t)spec % (4 * esz) == 0) &&
                    (!spec_lo || (uintptr_t)spec_lo % (4 * esz) == 0);
+  a.vec = vec ? 1 : 0;
   // 512-channel slabs (weights computed once per 512 channels) where the
   // registers allow it, else 256
   const int qw = (C > 256 && vec && kForm != kBF16Split) ? 2 : 1;
@@ -623,6 +723,51 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   HCG_LAUNCH_CHECK("k_gather_mfma");
   return HCG_OK;
 }
+
+GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
+                         float* wmap) {
+  GatherArgs a;
+  memset(&a, 0, sizeof(a));  // padding bytes too: the batch compares tables bytewise
+  a.trig = p->trig;
+  a.perm = p->perm;
+  a.ranges = p->ranges;
+  a.nranges = p->nranges;
+  a.maxr = p->maxr;
+  a.spec = spec;
+  a.spec_lo = nullptr;
+  a.scale = nullptr;
+  a.C = C;
+  a.g = p->grid;
+  a.ntx = p->ntx;
+  a.ntiles = p->ntx * p->nty;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.vec = (C % 4 == 0 && (uintptr_t)spec % 16 == 0) ? 1 : 0;
+  a.hR = std::pow(std::sin(0.5 * p->support_rad), 2);
+  a.inv_two_sig2 = 1.0 / (2.0 * p->sigma_rad * p->sigma_rad);
+  a.cube = cube;
+  a.wmap = wmap;
+  return a;
+}
+
+hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream) {
+  k_batch_reset<<<1, 1, 0, stream>>>(ctl);
+  HCG_LAUNCH_CHECK("k_batch_reset");
+  return HCG_OK;
+}
+
+hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchItem* items, uint32_t* ctl,
+                        int nblocks, hipStream_t stream) {
+  if (qw == 2)
+    k_gather_batch<2><<<nblocks, 256, 0, stream>>>(fields, items, ctl);
+  else
+    k_gather_batch<1><<<nblocks, 256, 0, stream>>>(fields, items, ctl);
+  HCG_LAUNCH_CHECK("k_gather_batch");
+  return HCG_OK;
+}
+
+}  // namespace hcg
+
+using namespace hcg;
 
 extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan,
                                hcg_dtype dtype, const float* chan_scale, float* cube,

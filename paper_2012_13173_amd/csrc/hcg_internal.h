@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
 
 #include "hcg.h"
@@ -176,6 +178,43 @@ void plan_unregister(hcg_plan_s* p);
 hcg_status launch_ang2pix(const double* lon, const double* lat, int64_t n, int nside,
                           uint32_t* pix, uint32_t* stat, hipStream_t stream);
 size_t radix_sort_temp_bytes(int64_t n);
+
+// Arguments of the gather for one plan and one spectra buffer (gather.hip).
+struct GatherArgs {
+  const double4* trig;
+  const uint32_t* perm;
+  const uint2* ranges;
+  const uint32_t* nranges;
+  int maxr;
+  const void* spec;     // [n][C] in the form's storage type
+  const void* spec_lo;  // low plane for the split form
+  const float* scale;   // [C] per-channel scale for the scaled forms
+  int64_t C;
+  GridGeom g;
+  int ntx, ntiles, tiles_per_xcd;
+  int vec;  // rows can be read 4 elements at a time
+  double hR, inv_two_sig2;
+  float* cube;
+  float* wmap;
+};
+
+// The host fills GatherArgs tables that kernels index; the layout is fixed
+// (both compilation passes see these checks).
+static_assert(sizeof(GatherArgs) == 160, "GatherArgs layout changed");
+static_assert(offsetof(GatherArgs, C) == 64 && offsetof(GatherArgs, g) == 72 &&
+                  offsetof(GatherArgs, hR) == 128 && offsetof(GatherArgs, wmap) == 152,
+              "GatherArgs layout changed");
+
+// Batched gather (gather.hip): one work item = (field, tile, channel slab);
+// the persistent kernel reads a device array of GatherArgs (one per field).
+struct BatchItem {
+  uint32_t field, tile, slab, pad;
+};
+GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
+                         float* wmap);
+hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream);
+hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchItem* items, uint32_t* ctl,
+                        int nblocks, hipStream_t stream);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
                              uint32_t* perm_out, void* temp, hipStream_t stream);
 

@@ -1,0 +1,152 @@
+"""GPU tests of the batched form: many maps of uneven size in one persistent,
+graph-captured launch.  Every field must match the FP64 oracle (1e-5) and the
+single-field hcg_grid of the same plan; replays of the captured graph, with
+eager work and synchronisation between them, must each match the eager
+result; changed pointers and channel counts must be picked up; the autotuned
+and the fixed configurations must give the same cubes."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_13173_amd as hcg
+import synth
+from tests.gridcheck import assert_cube_close, assert_weights_close, run_oracle
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _fields():
+    return [
+        synth.small_cube(n=6000, nchan=1, nx=23, ny=17, seed=201, name="c1"),
+        synth.small_cube(n=9000, nchan=3, nx=16, ny=16, seed=202, fwhm_arcmin=2.0,
+                         cell_arcmin=0.6, name="c3"),
+        synth.small_cube(n=12000, nchan=64, nx=31, ny=9, seed=203, fwhm_arcmin=4.5,
+                         cell_arcmin=1.5, name="c64"),
+        synth.small_cube(n=8000, nchan=67, nx=12, ny=29, seed=204, lon_c=0.03, name="wrap"),
+        synth.small_cube(n=10000, nchan=300, nx=20, ny=20, seed=205, lat_c=44.0, name="c300"),
+        synth.small_cube(n=7000, nchan=513, nx=9, ny=11, seed=206, fwhm_arcmin=6.0,
+                         cell_arcmin=2.0, name="c513"),
+        synth.small_cube(n=5000, nchan=1024, nx=17, ny=14, seed=207, name="c1024"),
+    ]
+
+
+def _plan(ws, chan_tile=0):
+    return hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+                               for w in ws], chan_tile=chan_tile)
+
+
+def _outputs(ws):
+    cubes = [torch.full((w.nchan, w.grid.ny, w.grid.nx), -7.0, device=DEV) for w in ws]
+    wts = [torch.full((w.grid.ny, w.grid.nx), -7.0, device=DEV) for w in ws]
+    return cubes, wts
+
+
+def _single(w):
+    plan = hcg.hcg_plan(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+    cube = torch.empty((w.nchan, w.grid.ny, w.grid.nx), device=DEV)
+    W = torch.empty((w.grid.ny, w.grid.nx), device=DEV)
+    hcg.hcg_grid(plan, w.spectra.to(DEV), cube, W)
+    torch.cuda.synchronize()
+    plan.destroy()
+    return cube.cpu().numpy(), W.cpu().numpy()
+
+
+def test_batch_matches_oracle_and_single_calls():
+    ws = _fields()
+    b = _plan(ws)
+    spectra = [w.spectra.to(DEV).contiguous() for w in ws]
+    cubes, wts = _outputs(ws)
+    hcg.hcg_grid_batch(b, spectra, cubes, wts)
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["tuned"] == 1 and info["graph_captured"] == 1 and info["nfields"] == len(ws)
+    for w, cube, W in zip(ws, cubes, wts):
+        V, Wb = cube.cpu().numpy(), W.cpu().numpy()
+        Vr, Wr, _ = run_oracle(w)
+        assert_cube_close(V, Vr, 1e-5, w.name)
+        assert_weights_close(Wb, Wr)
+        Vs, Ws = _single(w)
+        if w.nchan > 8:
+            assert np.array_equal(V, Vs, equal_nan=True), w.name  # same per-channel sums
+        else:
+            np.testing.assert_allclose(V, Vs, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(Wb, Ws, rtol=1e-7)
+    b.destroy()
+
+
+def test_graph_replays_pointer_and_channel_changes():
+    ws = _fields()[2:6]
+    b = _plan(ws)
+    spectra = [w.spectra.to(DEV).contiguous() for w in ws]
+    cubes, wts = _outputs(ws)
+    hcg.hcg_grid_batch(b, spectra, cubes, wts)
+    torch.cuda.synchronize()
+    ref = [c.clone() for c in cubes]
+    for k in range(1, 4):
+        # eager work between replays, then a replay on scaled inputs
+        for sp in spectra:
+            sp.mul_(2.0)
+        for c in cubes:
+            c.fill_(-1.0)
+        torch.cuda.synchronize()
+        hcg.hcg_grid_batch(b, spectra, cubes, wts)
+        torch.cuda.synchronize()
+        for c, r in zip(cubes, ref):
+            torch.testing.assert_close(c, r * (2.0 ** k), rtol=1e-6, atol=1e-6, equal_nan=True)
+    # new output tensors (pointer change) and a channel-count change on field 1
+    cubes2, wts2 = _outputs(ws)
+    spectra2 = list(spectra)
+    spectra2[1] = spectra[1][:, :13].contiguous()
+    cubes2[1] = torch.empty((13, ws[1].grid.ny, ws[1].grid.nx), device=DEV)
+    hcg.hcg_grid_batch(b, spectra2, cubes2, wts2)
+    torch.cuda.synchronize()
+    for i, (c, r) in enumerate(zip(cubes2, ref)):
+        want = r[:13] if i == 1 else r
+        torch.testing.assert_close(c, want * 8.0, rtol=1e-6, atol=1e-6, equal_nan=True)
+    b.destroy()
+
+
+@pytest.mark.parametrize("chan_tile", [256, 512])
+def test_fixed_configurations_agree_with_autotuned(chan_tile):
+    ws = _fields()[3:]
+    spectra = [w.spectra.to(DEV).contiguous() for w in ws]
+    outs = []
+    for ct in (0, chan_tile):
+        b = _plan(ws, chan_tile=ct)
+        cubes, wts = _outputs(ws)
+        hcg.hcg_grid_batch(b, spectra, cubes, wts)
+        torch.cuda.synchronize()
+        outs.append([c.cpu().numpy() for c in cubes])
+        if ct:
+            assert b.info()["chan_slab"] == ct
+        b.destroy()
+    for a, c in zip(*outs):
+        assert np.array_equal(a, c, equal_nan=True)
+
+
+def test_batch_errors():
+    ws = _fields()[:2]
+    lib = hcg.load()
+    h = ctypes.c_void_p()
+    assert lib.hcg_plan_batch(ctypes.byref(h), 0, None, None, None) == hcg.HCG_E_ARG
+    with pytest.raises(hcg.HcgError) as e:
+        hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+                            for w in ws], chan_tile=300)
+    assert e.value.status == hcg.HCG_E_UNSUPPORTED
+    bad_lat = ws[1].lat.to(DEV).clone()
+    bad_lat[5] = 95.0
+    with pytest.raises(hcg.HcgError, match="field 1"):
+        hcg.hcg_plan_batch([(ws[0].lon.to(DEV), ws[0].lat.to(DEV), ws[0].grid, ws[0].fwhm_deg,
+                             ws[0].support_deg),
+                            (ws[1].lon.to(DEV), bad_lat, ws[1].grid, ws[1].fwhm_deg,
+                             ws[1].support_deg)])
+    b = _plan(ws)
+    arr = (hcg.FieldDataC * 2)()
+    assert lib.hcg_grid_batch(b.handle, arr, None) == hcg.HCG_E_ARG
+    handle = b.handle
+    b.destroy()
+    assert lib.hcg_destroy_batch(handle) == hcg.HCG_E_STATE
+    assert lib.hcg_destroy_batch(None) == hcg.HCG_OK
