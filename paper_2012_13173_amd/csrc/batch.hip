@@ -1,17 +1,18 @@
 // Batches of independent maps in one persistent launch.
 //
 // hcg_plan_batch builds one plan per field (same device steps as hcg_plan).
-// hcg_grid_batch turns every (field, tile, channel slab) into a work item,
-// orders the items by estimated cost (candidates x channels, largest first,
-// so that the long items start early and the short ones fill the tail) and
-// runs them all in one launch of a persistent kernel whose workgroups pop
-// items from a shared counter.  The reset of the counter and the launch are
-// captured once in a hipGraph and replayed; the per-field argument table and
-// the item list live in device memory and are rewritten before a replay when
-// pointers or channel counts change.  On the first call an autotuner times
-// the channel slab (256 or 512 channels) and the item order (by cost or by
-// field and tile) and keeps the fastest; the choice can be cached on disk
-// (HCG_TUNE_CACHE=<file>).
+// hcg_grid_batch makes every (field, tile, channel slab) a work item: the
+// fields' item ranges are concatenated in a chosen field order (by estimated
+// cost, candidates x channels, largest first, or as given) and the kernel
+// decodes an item index through a small per-field segment table.  One launch
+// of a persistent kernel runs them all; its workgroups pop items from per-XCD
+// counters over contiguous eighths of the item space and steal from the
+// other eighths at the end.  The counter reset and the launch are captured
+// once in a hipGraph and replayed; the argument and segment tables live in
+// device memory and are rewritten before a replay when pointers or channel
+// counts change.  On the first call an autotuner times the channel slab (256
+// or 512 channels) and the field order and keeps the fastest; the choice can
+// be cached on disk (HCG_TUNE_CACHE=<file>).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -36,9 +37,8 @@ struct hcg_batch_s {
   std::vector<std::vector<uint32_t>> ncand;  // per field, per tile
   hcg_opts opts{};
   GatherArgs* d_fields = nullptr;  // [nfields]
-  BatchItem* d_items = nullptr;
-  size_t items_cap = 0;
-  uint32_t* d_ctl = nullptr;  // [0] next item, [1] item count
+  BatchSeg* d_segs = nullptr;  // [nfields]
+  uint32_t* d_ctl = nullptr;   // kBatchCtl words
   std::vector<GatherArgs> h_fields;
   std::vector<int64_t> built_C;
   std::vector<int> built_vec;
@@ -51,7 +51,6 @@ struct hcg_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_qw = 0;
-  const void* graph_items = nullptr;
 };
 
 namespace {
@@ -70,60 +69,53 @@ void free_batch(hcg_batch_s* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_fields) (void)hipFree(b->d_fields);
-  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_segs) (void)hipFree(b->d_segs);
   if (b->d_ctl) (void)hipFree(b->d_ctl);
   for (hcg_plan_t p : b->plans) (void)hcg_destroy(p);
   b->magic = 0;
   delete b;
 }
 
-// Work items for slab width 256 * qw (256 for fields whose rows cannot be
+// Item segments for slab width 256 * qw (256 for fields whose rows cannot be
 // read four elements at a time; one item per tile for C <= 8).
 hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int cost_order,
                        hipStream_t stream) {
-  struct Costed {
-    double cost;
-    BatchItem it;
-  };
-  std::vector<Costed> items;
-  for (size_t f = 0; f < b->plans.size(); ++f) {
+  const size_t nf = b->plans.size();
+  std::vector<double> cost(nf);
+  std::vector<BatchSeg> seg(nf);
+  for (size_t f = 0; f < nf; ++f) {
     const int64_t C = data[f].nchan;
-    const int vec = b->built_vec[f];
-    const int64_t width = (C <= 8) ? C : (vec ? 256 * qw : 256);
+    const int64_t width = (C <= 8) ? C : (b->built_vec[f] ? 256 * qw : 256);
     const int64_t slabs = (C <= 8) ? 1 : (C + width - 1) / width;
     const std::vector<uint32_t>& nc = b->ncand[f];
-    for (uint32_t t = 0; t < nc.size(); ++t)
-      for (int64_t s = 0; s < slabs; ++s) {
-        const int64_t ch = std::min<int64_t>(width, C - s * width);
-        // candidates x channels, plus the output writes of the tile
-        const double cost = (double)nc[t] * (C <= 8 ? 8.0 : (double)std::max<int64_t>(ch, 64)) +
-                            64.0 * (double)ch;
-        items.push_back({cost, BatchItem{(uint32_t)f, t, (uint32_t)s, 0u}});
-      }
+    double cand = 0.0;
+    for (uint32_t v : nc) cand += v;
+    // candidates x channels, plus the output writes
+    cost[f] = cand * (C <= 8 ? 8.0 : (double)std::max<int64_t>(C, 64)) +
+              64.0 * (double)nc.size() * (double)C;
+    seg[f] = BatchSeg{0u, (uint32_t)nc.size(), (uint32_t)slabs, (uint32_t)f};
   }
+  std::vector<size_t> order(nf);
+  for (size_t f = 0; f < nf; ++f) order[f] = f;
   if (cost_order)
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Costed& x, const Costed& y) { return x.cost > y.cost; });
-  if (items.size() >= (size_t)UINT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
-  std::vector<BatchItem> host(items.size());
-  for (size_t i = 0; i < items.size(); ++i) host[i] = items[i].it;
-  if (host.size() > b->items_cap) {
-    if (b->d_items) HCG_HIP(hipFree(b->d_items));
-    b->d_items = nullptr;
-    b->items_cap = 0;
-    if (hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(host.size(), 1)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(HCG_E_NOMEM, "hcg_grid_batch: cannot allocate the work list");
-    }
-    b->items_cap = host.size();
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+  std::vector<BatchSeg> host(nf);
+  uint64_t base = 0;
+  for (size_t k = 0; k < nf; ++k) {
+    host[k] = seg[order[k]];
+    host[k].base = (uint32_t)base;
+    base += (uint64_t)host[k].ntiles * host[k].slabs;
+    if (base >= 0xFFFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
   }
-  b->nitems = (uint32_t)host.size();
-  if (!host.empty())
-    HCG_HIP(hipMemcpyAsync(b->d_items, host.data(), sizeof(BatchItem) * host.size(),
-                           hipMemcpyHostToDevice, stream));
-  const uint32_t ctl[2] = {0u, b->nitems};
+  b->nitems = (uint32_t)base;
+  HCG_HIP(hipMemcpyAsync(b->d_segs, host.data(), sizeof(BatchSeg) * nf, hipMemcpyHostToDevice,
+                         stream));
+  uint32_t ctl[kBatchCtl] = {0};
+  ctl[8] = b->nitems;
+  ctl[9] = (uint32_t)nf;
   HCG_HIP(hipMemcpyAsync(b->d_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, stream));
-  HCG_HIP(hipStreamSynchronize(stream));  // the host vectors above go out of scope
+  HCG_HIP(hipStreamSynchronize(stream));  // the host arrays above go out of scope
   b->built_qw = qw;
   b->built_order = cost_order;
   return HCG_OK;
@@ -132,7 +124,7 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
 hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
   hcg_status st = launch_batch_reset(b->d_ctl, stream);
   if (st != HCG_OK) return st;
-  return launch_batch(b->qw, b->d_fields, b->d_items, b->d_ctl, b->nblocks, stream);
+  return launch_batch(b->qw, b->d_fields, b->d_segs, b->d_ctl, b->nblocks, stream);
 }
 
 std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {
@@ -227,7 +219,8 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
   }
   b->nblocks = 2 * cus;  // two 256-thread workgroups per CU
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||
-      hipMalloc(&b->d_ctl, 16) != hipSuccess ||
+      hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields) != hipSuccess ||
+      hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl) != hipSuccess ||
       hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     free_batch(b);
@@ -318,7 +311,7 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     st = build_items(b, data, b->qw, b->cost_order, stream);
     if (st != HCG_OK) return st;
   }
-  if (!b->exec || b->graph_qw != b->qw || b->graph_items != b->d_items) {
+  if (!b->exec || b->graph_qw != b->qw) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     HCG_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -330,7 +323,6 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     b->graph = g;
     HCG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->graph_qw = b->qw;
-    b->graph_items = b->d_items;
   }
   HCG_HIP(hipGraphLaunch(b->exec, stream));
   return HCG_OK;

@@ -558,29 +558,61 @@ __device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& 
     if (c < C) a.cube[c * G + cellidx] = (wsum > 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
 }
 
-// Persistent batch kernel (FP32 spectra): every workgroup pops work items
-// (field, tile, channel slab) from a shared counter until the list, ordered
-// by the host, is exhausted.  ctl[0] = next item, ctl[1] = item count.
-__global__ void k_batch_reset(uint32_t* __restrict__ ctl) { ctl[0] = 0u; }
+// Persistent batch kernel (FP32 spectra).  The item space concatenates the
+// fields' (slab, tile) grids in the host's field order; it is cut into eight
+// contiguous segments, one per XCD (the hardware deals workgroups to the XCDs
+// in turn, so workgroup b starts on XCD b % 8).  A workgroup pops items from
+// its own XCD's segment -- neighbouring tiles of one field, sharing candidate
+// rows in that XCD's L2 -- and, once it is empty, from the others.
+// ctl: [0..7] next item of each segment, [8] item count, [9] segment count.
+__device__ __forceinline__ uint32_t batch_seg_begin(uint32_t total, int x) {
+  return (uint32_t)(((uint64_t)total * (uint32_t)x) / kBatchXcds);
+}
+
+__global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
+  const uint32_t total = ctl[8];
+  for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
+}
 
 template <int kQW>
 __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
-                                                         const BatchItem* __restrict__ items,
+                                                         const BatchSeg* __restrict__ segs,
                                                          uint32_t* __restrict__ ctl) {
   __shared__ GatherSmem sm;
   __shared__ uint32_t s_item;
-  const uint32_t nitems = ctl[1];
+  const uint32_t total = ctl[8];
+  const uint32_t nseg = ctl[9];
+  const int home = (int)(blockIdx.x % kBatchXcds);
+  int k = 0;  // segments visited so far (thread 0 only)
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1u);
+    if (threadIdx.x == 0) {
+      uint32_t it = 0xFFFFFFFFu;
+      while (k < kBatchXcds) {
+        const int x = (home + k) % kBatchXcds;
+        const uint32_t i = atomicAdd(&ctl[x], 1u);
+        if (i < batch_seg_begin(total, x + 1)) { it = i; break; }
+        ++k;
+      }
+      s_item = it;
+    }
     __syncthreads();
-    const uint32_t it = s_item;
+    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
-    if (it >= nitems) break;
-    const BatchItem bi = items[it];
-    const GatherArgs a = fields[bi.field];
-    if (a.C <= 8) gather_cells_tile_wg(a, (int)bi.tile, sm);
-    else if (a.vec) gather_tile<kF32, kQW, true>(a, (int)bi.tile, (int)bi.slab, sm);
-    else gather_tile<kF32, 1, false>(a, (int)bi.tile, (int)bi.slab, sm);  // 256-channel slabs
+    if (it == 0xFFFFFFFFu) break;
+    // the last segment whose base is <= it
+    uint32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    const uint32_t local = it - sg.base;
+    const uint32_t slab = local / sg.ntiles;
+    const uint32_t tile = local - slab * sg.ntiles;
+    const GatherArgs a = fields[sg.field];
+    if (a.C <= 8) gather_cells_tile_wg(a, (int)tile, sm);
+    else if (a.vec) gather_tile<kF32, kQW, true>(a, (int)tile, (int)slab, sm);
+    else gather_tile<kF32, 1, false>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
     __syncthreads();
   }
 }
@@ -755,12 +787,12 @@ hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream) {
   return HCG_OK;
 }
 
-hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchItem* items, uint32_t* ctl,
+hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
                         int nblocks, hipStream_t stream) {
   if (qw == 2)
-    k_gather_batch<2><<<nblocks, 256, 0, stream>>>(fields, items, ctl);
+    k_gather_batch<2><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
   else
-    k_gather_batch<1><<<nblocks, 256, 0, stream>>>(fields, items, ctl);
+    k_gather_batch<1><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
   HCG_LAUNCH_CHECK("k_gather_batch");
   return HCG_OK;
 }

@@ -205,15 +205,20 @@ static_assert(offsetof(GatherArgs, C) == 64 && offsetof(GatherArgs, g) == 72 &&
                   offsetof(GatherArgs, hR) == 128 && offsetof(GatherArgs, wmap) == 152,
               "GatherArgs layout changed");
 
-// Batched gather (gather.hip): one work item = (field, tile, channel slab);
-// the persistent kernel reads a device array of GatherArgs (one per field).
-struct BatchItem {
-  uint32_t field, tile, slab, pad;
+// Batched gather (gather.hip): one work item = (field, tile, channel slab).
+// Field f owns the items [base, base + ntiles * slabs) of the item space,
+// item base + s * ntiles + t being slab s of tile t.  Segments are listed in
+// increasing base.  The persistent kernel reads device arrays of GatherArgs
+// (one per field) and BatchSeg, and a control block of kBatchCtl words.
+struct BatchSeg {
+  uint32_t base, ntiles, slabs, field;
 };
+constexpr int kBatchXcds = 8;
+constexpr int kBatchCtl = 16;
 GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
                          float* wmap);
 hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream);
-hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchItem* items, uint32_t* ctl,
+hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
                         int nblocks, hipStream_t stream);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
                              uint32_t* perm_out, void* temp, hipStream_t stream);

@@ -278,3 +278,53 @@ def small_cube(n=20_000, nchan=67, nx=45, ny=37, cell_arcmin=0.75, fwhm_arcmin=3
     fwhm = fwhm_arcmin * ARCMIN
     return Workload(name, lon, lat, spec, grid, fwhm, 3.0 * fwhm * FWHM_TO_SIGMA,
                     nside if nside else nside_for(fwhm), src)
+
+
+def batch_field_params(nfields=64, seed=SEED0 + 3):
+    """Per-field draws of the batched configuration: sample count log-uniform
+    in [1e4, 2e6], channels in {1, 64, 512, 2048}, square grid side uniform in
+    [100, 1500] cells, kernel FWHM uniform in [2', 6'], cell = FWHM / 3,
+    centre RA uniform in [0, 360), Dec uniform in [-20, 20]."""
+    g = _gen(seed, "cpu")
+    u = torch.rand((nfields, 6), generator=g, dtype=torch.float64)
+    chans = (1, 64, 512, 2048)
+    out = []
+    for f in range(nfields):
+        n = int(round(math.exp(math.log(1e4) + (math.log(2e6) - math.log(1e4)) * float(u[f, 0]))))
+        C = chans[min(3, int(4 * float(u[f, 1])))]
+        side = 100 + min(1400, int(1401 * float(u[f, 2])))
+        fwhm = 2.0 + 4.0 * float(u[f, 3])  # arcmin
+        out.append({"n": n, "nchan": C, "side": side, "fwhm_arcmin": fwhm,
+                    "cell_arcmin": fwhm / 3.0, "lon_c": 360.0 * float(u[f, 4]),
+                    "lat_c": -20.0 + 40.0 * float(u[f, 5])})
+    return out
+
+
+def batch_fields(device="cpu", nfields=64, seed=SEED0 + 3, params=None):
+    """The batched configuration: ``nfields`` independent fields of uniform
+    random positions over their grid, N(0,1) spectra plus 4 lines (or 3 point
+    sources for one channel), support 3 sigma, nside by the sigma/2 rule."""
+    params = params if params is not None else batch_field_params(nfields, seed)
+    ws = []
+    for f, p in enumerate(params):
+        cell = p["cell_arcmin"] * ARCMIN
+        side_deg = p["side"] * cell
+        # coordinate extent of the grid in longitude shrinks the sky span at
+        # high |Dec|; keep the field inside the grid's coordinate box
+        lon, lat = uniform_positions(p["n"], p["lon_c"], p["lat_c"], side_deg, side_deg,
+                                     seed + 1000 + f, device)
+        gg = _gen(seed + 2000 + f, device)
+        spec = torch.randn((p["n"], p["nchan"]), generator=gg, dtype=torch.float32, device=device)
+        fwhm = p["fwhm_arcmin"] * ARCMIN
+        if p["nchan"] > 1:
+            src = add_lines(spec, lon, lat, 4, p["lon_c"], p["lat_c"], side_deg, side_deg,
+                            2.0 * fwhm, seed + 3000 + f)
+        else:
+            vals = torch.zeros(p["n"], dtype=torch.float64, device=device)
+            src = add_point_sources(vals, lon, lat, 3, 10.0, fwhm, p["lon_c"], p["lat_c"],
+                                    side_deg, side_deg, seed + 3000 + f, device)
+            spec += vals.to(torch.float32)[:, None]
+        grid = GridDesc(p["side"], p["side"], p["lon_c"], p["lat_c"], cell, cell)
+        ws.append(Workload(f"field{f:02d}", lon, lat, spec, grid, fwhm,
+                           3.0 * fwhm * FWHM_TO_SIGMA, nside_for(fwhm), src))
+    return ws
