@@ -4,7 +4,7 @@
 //
 //   k_ang2pix        HEALPix ring-scheme pixel of every sample (Section 3.2)
 //   k_radix_*        stable LSD radix sort of (pixel, sample) (Section 3.3 I)
-//   k_permute_trig   sorted half-angle trigonometry of every sample
+//   k_permute_xyz    sorted unit vector of every sample
 //   k_ring_csr       start of every ring in the sorted order (Section 3.3 III)
 //   k_tile_ranges    per tile of output cells, the sorted-sample ranges that
 //                    can lie within the support (Section 3.4 steps i-iv)
@@ -319,19 +319,20 @@ __global__ void __launch_bounds__(256) k_rel_keys(const uint32_t* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// a3: sorted coordinates as half-angle trigonometry (FP64).
+// a3: sorted coordinates as unit vectors (FP64): the gather measures the
+// great-circle distance through the chord between two of them.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_permute_trig(const double* __restrict__ lon,
-                                                      const double* __restrict__ lat,
-                                                      const uint32_t* __restrict__ perm, int64_t n,
-                                                      double4* __restrict__ trig) {
+__global__ void __launch_bounds__(256) k_permute_xyz(const double* __restrict__ lon,
+                                                     const double* __restrict__ lat,
+                                                     const uint32_t* __restrict__ perm, int64_t n,
+                                                     double4* __restrict__ xyz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t s = perm[i];
-  double sd, cd, sa, ca;
-  sincos(0.5 * lat[s] * kDeg2Rad, &sd, &cd);
-  sincos(0.5 * lon[s] * kDeg2Rad, &sa, &ca);
-  trig[i] = make_double4(sd, cd, sa, ca);
+  double sb, cb, sl, cl;
+  sincos(lat[s] * kDeg2Rad, &sb, &cb);
+  sincos(lon[s] * kDeg2Rad, &sl, &cl);
+  xyz[i] = make_double4(cb * cl, cb * sl, sb, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,7 +574,7 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   hcg_opts o = {};
   if (opts) o = *opts;
   if ((o.tile_x && o.tile_x != kTileX) || (o.tile_y && o.tile_y != kTileY))
-    return fail(HCG_E_UNSUPPORTED, "hcg_plan: only 8 x 8 cell tiles are built");
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan: only 16 x 16 cell tiles are built");
   if (o.coarsen || o.chan_tile || o.flags)
     return fail(HCG_E_UNSUPPORTED, "hcg_plan: coarsen, chan_tile and flags must be 0");
   const double sigma = fwhm_deg * kDeg2Rad / (2.0 * std::sqrt(2.0 * std::log(2.0)));
@@ -616,9 +617,11 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   // plan arena
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
-  const size_t o_trig = take(sizeof(double4) * n);
+  // xyz and perm carry one sentinel entry at n (NaN vector, row 0): the
+  // gather reads it for the padding of its last candidate block
+  const size_t o_xyz = take(sizeof(double4) * (n + 1));
   const size_t o_keys = take(sizeof(uint32_t) * n);
-  const size_t o_perm = take(sizeof(uint32_t) * n);
+  const size_t o_perm = take(sizeof(uint32_t) * (n + 1));
   const size_t o_csr = take(sizeof(uint32_t) * (nrings + 1));
   const size_t o_rng = take(sizeof(uint2) * (size_t)ntiles * maxr);
   const size_t o_nr = take(sizeof(uint32_t) * ntiles);
@@ -657,7 +660,7 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   p->nty = nty;
   p->maxr = maxr;
   p->arena_bytes = arena_bytes;
-  p->trig = (double4*)(A + o_trig);
+  p->xyz = (double4*)(A + o_xyz);
   p->keys = (uint32_t*)(A + o_keys);
   p->perm = (uint32_t*)(A + o_perm);
   p->csr = (uint32_t*)(A + o_csr);
@@ -677,9 +680,11 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   HCG_LAUNCH_CHECK("k_rel_keys");
   st = launch_radix_sort(rel, n, key_bits == 0 ? 1 : key_bits, p->keys, p->perm, temp.p, stream);
   if (st != HCG_OK) return st;
-  k_permute_trig<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(lon_deg, lat_deg, p->perm, n,
-                                                                 p->trig);
-  HCG_LAUNCH_CHECK("k_permute_trig");
+  k_permute_xyz<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(lon_deg, lat_deg, p->perm, n,
+                                                                p->xyz);
+  HCG_LAUNCH_CHECK("k_permute_xyz");
+  HCG_HIP(hipMemsetAsync(p->xyz + n, 0xFF, sizeof(double4), stream));  // all-ones: NaN
+  HCG_HIP(hipMemsetAsync(p->perm + n, 0, sizeof(uint32_t), stream));
   k_ring_csr<<<(unsigned)((nrings + 1 + 255) / 256), 256, 0, stream>>>(
       p->keys, n, nside, ring_first, nrings, pix_base, p->csr);
   HCG_LAUNCH_CHECK("k_ring_csr");
