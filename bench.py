@@ -93,9 +93,9 @@ def cpu_baseline(w, cubes, budget_s=15.0, patch=32, max_patches=40, seed=7):
 
 
 def run_batch(args):
-    """64 independent fields of uneven size: one batched launch (hipGraph
-    replay, autotuned) against 64 separate plan + grid calls on the same
-    buffers."""
+    """64 independent fields of uneven size: one batched launch (persistent
+    kernel, hipGraph replay, autotuned) against 64 separate plan + grid calls
+    on the same buffers."""
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     ws = synth.batch_fields(device=dev)
@@ -162,8 +162,8 @@ def run_batch(args):
         p.destroy()
     ms_bat = timed(batched, args.steps)
     log(f"batched plan+grid: {ms_bat:.1f} ms; grid only: batched {ms_grid_b:.1f} ms vs "
-        f"separate {ms_grid_sep:.1f} ms; autotuner {info['tune_ms']} -> per-XCD queues "
-        f"{info['xcd_split']}, cost order {info['cost_order']}; identical to separate: {same}")
+        f"separate {ms_grid_sep:.1f} ms; autotuner {info['tune_ms']} -> slab "
+        f"{info['chan_slab']}, cost order {info['cost_order']}; identical to separate: {same}")
     out = {
         "metric": "sample*channel updates/s, FP32 gather vs BF16-MFMA at <=1e-3 rel err",
         "value": tot_in / (ms_bat * 1e-3), "unit": "sample*channel updates/s", "n_gpus": 1,
@@ -176,9 +176,9 @@ def run_batch(args):
         "separate_calls_ms_per_step": ms_sep,
         "batched_grid_ms": ms_grid_b, "separate_grid_ms": ms_grid_sep,
         "speedup_batched_vs_separate": ms_sep / ms_bat,
-        "autotune": {"tune_ms": info["tune_ms"], "xcd_split": info["xcd_split"],
+        "autotune": {"tune_ms": info["tune_ms"], "chan_slab": info["chan_slab"],
                      "cost_order": info["cost_order"], "items": info["items"],
-                     "batch_fields": info["batch_fields"]},
+                     "persistent_blocks": info["persistent_blocks"]},
         "batched_equals_separate_for_C_gt_8": same,
     }
     print(json.dumps(out), flush=True)

@@ -92,7 +92,7 @@ typedef struct {
  *   nside     HEALPix resolution (power of two, 1 .. 16384).  Auto: the
  *             smallest nside whose mean pixel size is <= sigma/2 (the
  *             hpx_max_resolution ~ sigma_kernel/2 rule of Section 3.6 (iii)).
- *   tile_x/y  output-cell tile; only 16 x 16 (or 0) is accepted.
+ *   tile_x/y  output-cell tile; only 8 x 8 (or 0) is accepted.
  *   coarsen, chan_tile, flags: reserved, must be 0. */
 typedef struct {
   int32_t nside;
@@ -257,7 +257,7 @@ hcg_status hcg_sort_keys(const uint32_t* keys_in, int64_t n, int32_t key_bits, u
                          uint32_t* perm_out, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
-/* Batches: many independent maps of uneven size in one launch.  */
+/* Batches: many independent maps of uneven size in one persistent launch.  */
 /* ------------------------------------------------------------------------ */
 
 typedef struct hcg_batch_s* hcg_batch_t;
@@ -283,11 +283,10 @@ typedef struct {
 /*
  * hcg_plan_batch -- one plan per field (the steps of hcg_plan for each).
  *   fields  host array [nfields] (pointers inside are device pointers).
- *   opts    host pointer or NULL.  opts->chan_tile: 0 = autotune the work
- *           order and mapping on the first hcg_grid_batch call; 256 = fixed
- *           (items ordered by cost, XCD split).  Work items always cover 256
- *           channels.  nside and tile fields apply to every field as in
- *           hcg_plan.
+ *   opts    host pointer or NULL.  opts->chan_tile selects the channel slab
+ *           of the persistent kernel: 0 = autotune on the first
+ *           hcg_grid_batch call, 256 or 512 = fixed (items ordered by cost);
+ *           nside and tile fields apply to every field as in hcg_plan.
  * Synchronous.  Errors as hcg_plan, with the failing field named in the
  * message; nothing leaks on failure.
  */
@@ -297,15 +296,11 @@ hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_des
 /*
  * hcg_grid_batch -- Eq. (1) for every field of the batch in one launch.
  *   data  host array [nfields] in the order given to hcg_plan_batch.
- * Every (field, 16 x 16 tile, 256-channel slab) is a work item; one kernel
- * launch runs the items of all fields (one workgroup each; the hardware
- * dispatcher balances fields of unequal cost), with each XCD taking a
- * contiguous eighth of the item space or in plain order.  Fields with
- * nchan <= 8, rows not 16-byte aligned or nchan % 4 != 0, or supports of
- * 5.7 degrees and more are gridded by their own launch after it.  The first
- * call may run the batch several times to autotune the field order (by cost
- * or as given) and the mapping (same results every time); it then captures
- * the launches in a hipGraph that later calls replay.  Pointers and channel counts may change
+ * Every (field, tile, channel slab) is a work item; a persistent kernel of
+ * two workgroups per CU pops the items, ordered largest-cost first, from a
+ * shared counter.  The first call may run the batch several times to
+ * autotune (same results every time); it then captures the launch in a
+ * hipGraph that later calls replay.  Pointers and channel counts may change
  * between calls (the device tables are rewritten before the replay).
  * Asynchronous on hip_stream after the first call (which synchronises).
  * Errors: HCG_E_ARG (NULL pointers, nchan < 1), HCG_E_STATE (not a live
@@ -319,17 +314,14 @@ hcg_status hcg_destroy_batch(hcg_batch_t batch);
 
 typedef struct {
   int32_t nfields;
-  int32_t xcd_split;         /* 1: each XCD takes a contiguous eighth of the
-                                items; 0: plain order */
+  int32_t chan_slab;         /* channels per work item for C > 8 (256 or 512) */
   int32_t cost_order;        /* 1: items by decreasing cost; 0: by field, tile */
   int32_t tuned;             /* 1 once the configuration is fixed */
   int32_t graph_captured;    /* 1 once the launch is captured */
-  int32_t batch_fields;      /* fields in the one batch launch (the others
-                                are launched on their own) */
+  int32_t persistent_blocks; /* workgroups of the persistent kernel */
   int64_t items;             /* work items of the last build */
-  double tune_ms[4];         /* autotuner timings: (XCD split, cost), (plain,
-                                cost), (XCD split, natural), (plain, natural);
-                                0 if skipped */
+  double tune_ms[4];         /* autotuner timings: (256, cost), (512, cost),
+                                (256, natural), (512, natural); 0 if skipped */
 } hcg_batch_info;
 
 hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info);

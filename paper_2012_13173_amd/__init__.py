@@ -72,9 +72,9 @@ class FieldDataC(ctypes.Structure):
 
 
 class BatchInfoC(ctypes.Structure):
-    _fields_ = [("nfields", ctypes.c_int32), ("xcd_split", ctypes.c_int32),
+    _fields_ = [("nfields", ctypes.c_int32), ("chan_slab", ctypes.c_int32),
                 ("cost_order", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("graph_captured", ctypes.c_int32), ("batch_fields", ctypes.c_int32),
+                ("graph_captured", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
                 ("items", ctypes.c_int64), ("tune_ms", ctypes.c_double * 4)]
 
 

@@ -1,20 +1,18 @@
-// Batches of independent maps in one launch.
+// Batches of independent maps in one persistent launch.
 //
 // hcg_plan_batch builds one plan per field (same device steps as hcg_plan).
-// hcg_grid_batch makes every (field, 16 x 16 tile, 256-channel slab) a work
-// item: the fields' item ranges are concatenated in a chosen field order (by
-// estimated cost, candidates x channels, largest first, or as given) and the
-// kernel decodes an item index through a small per-field segment table.  One
-// launch covers the items of every field, one workgroup per item; the
-// dispatcher hands workgroups to CUs as they free up, which balances fields
-// of unequal cost.  Fields with few channels (C <= 8), rows that cannot be
-// read four elements at a time, or wide supports are launched on their own
-// after it.  The launches are captured once in a hipGraph and replayed; the
-// argument and segment tables live in device memory and are rewritten before
-// a replay when pointers or channel counts change.  On the first call an
-// autotuner times the field order and the workgroup-to-item mapping
-// (contiguous eighths of the item space per XCD, or plain order) and keeps
-// the fastest; the choice can be cached on disk (HCG_TUNE_CACHE=<file>).
+// hcg_grid_batch makes every (field, tile, channel slab) a work item: the
+// fields' item ranges are concatenated in a chosen field order (by estimated
+// cost, candidates x channels, largest first, or as given) and the kernel
+// decodes an item index through a small per-field segment table.  One launch
+// of a persistent kernel runs them all; its workgroups pop items from per-XCD
+// counters over contiguous eighths of the item space and steal from the
+// other eighths at the end.  The counter reset and the launch are captured
+// once in a hipGraph and replayed; the argument and segment tables live in
+// device memory and are rewritten before a replay when pointers or channel
+// counts change.  On the first call an autotuner times the channel slab (256
+// or 512 channels) and the field order and keeps the fastest; the choice can
+// be cached on disk (HCG_TUNE_CACHE=<file>).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -34,22 +32,25 @@ constexpr uint64_t kBatchMagic = 0x48434742'41544331ull;  // "HCGBATC1"
 struct hcg_batch_s {
   uint64_t magic = kBatchMagic;
   int device = 0;
+  int nblocks = 0;
   std::vector<hcg_plan_t> plans;
   std::vector<std::vector<uint32_t>> ncand;  // per field, per tile
   hcg_opts opts{};
   GatherArgs* d_fields = nullptr;  // [nfields]
   BatchSeg* d_segs = nullptr;  // [nfields]
+  uint32_t* d_ctl = nullptr;   // kBatchCtl words
   std::vector<GatherArgs> h_fields;
   std::vector<int64_t> built_C;
   std::vector<int> built_vec;
-  int built_split = -1, built_order = -1;
-  uint32_t nitems = 0, nseg = 0;
-  int xcd_split = 1, cost_order = 1;
+  int built_qw = 0, built_order = -1;
+  uint32_t nitems = 0;
+  int qw = 0, cost_order = 1;
   bool tuned = false;
   double tune_ms[4] = {0, 0, 0, 0};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int graph_qw = 0;
 };
 
 namespace {
@@ -69,22 +70,22 @@ void free_batch(hcg_batch_s* b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_fields) (void)hipFree(b->d_fields);
   if (b->d_segs) (void)hipFree(b->d_segs);
+  if (b->d_ctl) (void)hipFree(b->d_ctl);
   for (hcg_plan_t p : b->plans) (void)hcg_destroy(p);
   b->magic = 0;
   delete b;
 }
 
-// Item segments: one item per (tile, 256-channel slab); one item per tile for
-// C <= 8.  Fields the batch kernel does not take (batch_takes) get no items:
-// they are launched on their own.  xcd_split: see the batch kernel.
-hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int xcd_split,
-                       int cost_order, hipStream_t stream) {
+// Item segments for slab width 256 * qw (256 for fields whose rows cannot be
+// read four elements at a time; one item per tile for C <= 8).
+hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int cost_order,
+                       hipStream_t stream) {
   const size_t nf = b->plans.size();
   std::vector<double> cost(nf);
   std::vector<BatchSeg> seg(nf);
   for (size_t f = 0; f < nf; ++f) {
     const int64_t C = data[f].nchan;
-    const int64_t width = (C <= 8) ? C : 256;
+    const int64_t width = (C <= 8) ? C : (b->built_vec[f] ? 256 * qw : 256);
     const int64_t slabs = (C <= 8) ? 1 : (C + width - 1) / width;
     const std::vector<uint32_t>& nc = b->ncand[f];
     double cand = 0.0;
@@ -94,43 +95,36 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int xcd_split
               64.0 * (double)nc.size() * (double)C;
     seg[f] = BatchSeg{0u, (uint32_t)nc.size(), (uint32_t)slabs, (uint32_t)f};
   }
-  std::vector<size_t> order;
-  for (size_t f = 0; f < nf; ++f)
-    if (batch_takes(b->h_fields[f])) order.push_back(f);
-  const size_t nseg = order.size();
+  std::vector<size_t> order(nf);
+  for (size_t f = 0; f < nf; ++f) order[f] = f;
   if (cost_order)
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-  std::vector<BatchSeg> host(nseg);
+  std::vector<BatchSeg> host(nf);
   uint64_t base = 0;
-  for (size_t k = 0; k < nseg; ++k) {
+  for (size_t k = 0; k < nf; ++k) {
     host[k] = seg[order[k]];
     host[k].base = (uint32_t)base;
     base += (uint64_t)host[k].ntiles * host[k].slabs;
     if (base >= 0xFFFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
   }
   b->nitems = (uint32_t)base;
-  if (nseg)
-    HCG_HIP(hipMemcpyAsync(b->d_segs, host.data(), sizeof(BatchSeg) * nseg,
-                           hipMemcpyHostToDevice, stream));
-  b->nseg = (uint32_t)nseg;
-  HCG_HIP(hipStreamSynchronize(stream));  // the host array above goes out of scope
-  b->built_split = xcd_split;
+  HCG_HIP(hipMemcpyAsync(b->d_segs, host.data(), sizeof(BatchSeg) * nf, hipMemcpyHostToDevice,
+                         stream));
+  uint32_t ctl[kBatchCtl] = {0};
+  ctl[8] = b->nitems;
+  ctl[9] = (uint32_t)nf;
+  HCG_HIP(hipMemcpyAsync(b->d_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, stream));
+  HCG_HIP(hipStreamSynchronize(stream));  // the host arrays above go out of scope
+  b->built_qw = qw;
   b->built_order = cost_order;
   return HCG_OK;
 }
 
-// The batch kernel, then the fields it does not take, one launch each (their
-// arguments are passed by value: a change of them needs a new graph).
 hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
-  hcg_status st = launch_batch(b->d_fields, b->d_segs, b->nseg, b->nitems, b->built_split, stream);
+  hcg_status st = launch_batch_reset(b->d_ctl, stream);
   if (st != HCG_OK) return st;
-  for (const GatherArgs& a : b->h_fields) {
-    if (batch_takes(a)) continue;
-    st = launch_f32(a, stream);
-    if (st != HCG_OK) return st;
-  }
-  return HCG_OK;
+  return launch_batch(b->qw, b->d_fields, b->d_segs, b->d_ctl, b->nblocks, stream);
 }
 
 std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {
@@ -154,7 +148,7 @@ std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {
   return buf;
 }
 
-bool tune_cache_lookup(const std::string& sig, int* split, int* order) {
+bool tune_cache_lookup(const std::string& sig, int* qw, int* order) {
   const char* path = getenv("HCG_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE* f = fopen(path, "r");
@@ -163,17 +157,17 @@ bool tune_cache_lookup(const std::string& sig, int* split, int* order) {
   int q, o;
   bool found = false;
   while (fscanf(f, "%63s %d %d", s, &q, &o) == 3)
-    if (sig == s && (q == 0 || q == 1) && (o == 0 || o == 1)) { *split = q; *order = o; found = true; }
+    if (sig == s && (q == 1 || q == 2) && (o == 0 || o == 1)) { *qw = q; *order = o; found = true; }
   fclose(f);
   return found;
 }
 
-void tune_cache_store(const std::string& sig, int split, int order) {
+void tune_cache_store(const std::string& sig, int qw, int order) {
   const char* path = getenv("HCG_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d\n", sig.c_str(), split, order);
+  fprintf(f, "%s %d %d\n", sig.c_str(), qw, order);
   fclose(f);
 }
 
@@ -187,8 +181,8 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
   if (nfields < 1 || !fields) return fail(HCG_E_ARG, "hcg_plan_batch: need at least one field");
   hcg_opts o{};
   if (opts) o = *opts;
-  if (o.chan_tile != 0 && o.chan_tile != 256)
-    return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: chan_tile must be 0 or 256");
+  if (o.chan_tile != 0 && o.chan_tile != 256 && o.chan_tile != 512)
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: chan_tile must be 0, 256 or 512");
   if (o.coarsen || o.flags) return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: coarsen and flags must be 0");
   hcg_status st = check_device_arch();
   if (st != HCG_OK) return st;
@@ -217,12 +211,16 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
       return fail(HCG_E_DEVICE, "hcg_plan_batch: reading candidate counts failed");
     }
   }
-  if (hipGetDevice(&b->device) != hipSuccess) {
+  int cus = 0;
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
     free_batch(b);
     return fail(HCG_E_DEVICE, "hcg_plan_batch: device query failed");
   }
+  b->nblocks = 2 * cus;  // two 256-thread workgroups per CU
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||
       hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields) != hipSuccess ||
+      hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl) != hipSuccess ||
       hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     free_batch(b);
@@ -259,13 +257,6 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
       layout_changed = true;
   }
   if (memcmp(fresh.data(), b->h_fields.data(), sizeof(GatherArgs) * nf) != 0) {
-    for (size_t f = 0; f < nf && b->exec; ++f) {
-      if ((batch_takes(fresh[f]) && batch_takes(b->h_fields[f])) ||
-          memcmp(&fresh[f], &b->h_fields[f], sizeof(GatherArgs)) == 0)
-        continue;
-      (void)hipGraphExecDestroy(b->exec);  // arguments of a separate launch changed
-      b->exec = nullptr;
-    }
     b->h_fields = fresh;
     HCG_HIP(hipMemcpyAsync(b->d_fields, b->h_fields.data(), sizeof(GatherArgs) * nf,
                            hipMemcpyHostToDevice, stream));
@@ -274,21 +265,21 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     b->built_C.resize(nf);
     b->built_vec = vecs;
     for (size_t f = 0; f < nf; ++f) b->built_C[f] = data[f].nchan;
-    b->built_split = -1;  // force a rebuild
+    b->built_qw = 0;  // force a rebuild
   }
   hcg_status st;
   if (!b->tuned) {
     if (b->opts.chan_tile) {
-      b->xcd_split = 1;
+      b->qw = b->opts.chan_tile / 256;
       b->cost_order = 1;
     } else {
       const std::string sig = batch_signature(b, data);
       int q = 0, o = 0;
       if (tune_cache_lookup(sig, &q, &o)) {
-        b->xcd_split = q;
+        b->qw = q;
         b->cost_order = o;
       } else {
-        const int cfg[4][2] = {{1, 1}, {0, 1}, {1, 0}, {0, 0}};
+        const int cfg[4][2] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}};
         double best = 1e300;
         hipEvent_t e0, e1;
         HCG_HIP(hipEventCreate(&e0));
@@ -296,6 +287,7 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
         for (int k = 0; k < 4; ++k) {
           st = build_items(b, data, cfg[k][0], cfg[k][1], stream);
           if (st != HCG_OK) return st;
+          b->qw = cfg[k][0];
           HCG_HIP(hipEventRecord(e0, stream));
           st = launch_direct(b, stream);
           if (st != HCG_OK) return st;
@@ -308,18 +300,18 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        b->xcd_split = q;
+        b->qw = q;
         b->cost_order = o;
         tune_cache_store(sig, q, o);
       }
     }
     b->tuned = true;
   }
-  if (b->built_split != b->xcd_split || b->built_order != b->cost_order) {
-    st = build_items(b, data, b->xcd_split, b->cost_order, stream);
+  if (b->built_qw != b->qw || b->built_order != b->cost_order) {
+    st = build_items(b, data, b->qw, b->cost_order, stream);
     if (st != HCG_OK) return st;
   }
-  if (!b->exec) {
+  if (!b->exec || b->graph_qw != b->qw) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     HCG_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -330,6 +322,7 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     if (ec != hipSuccess) return fail(HCG_E_DEVICE, "hcg_grid_batch: graph capture failed: %s", hipGetErrorString(ec));
     b->graph = g;
     HCG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_qw = b->qw;
   }
   HCG_HIP(hipGraphLaunch(b->exec, stream));
   return HCG_OK;
@@ -354,12 +347,12 @@ extern "C" hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info
   if (!batch || !info) return fail(HCG_E_ARG, "hcg_get_batch_info: NULL pointer");
   if (!batch_is_live(batch)) return fail(HCG_E_STATE, "hcg_get_batch_info: not a live batch");
   info->nfields = (int32_t)batch->plans.size();
-  info->xcd_split = batch->xcd_split;
+  info->chan_slab = 256 * batch->qw;
   info->cost_order = batch->cost_order;
   info->tuned = batch->tuned ? 1 : 0;
   info->graph_captured = batch->exec ? 1 : 0;
   info->items = batch->nitems;
-  info->batch_fields = (int32_t)batch->nseg;
+  info->persistent_blocks = batch->nblocks;
   for (int k = 0; k < 4; ++k) info->tune_ms[k] = batch->tune_ms[k];
   return HCG_OK;
 }

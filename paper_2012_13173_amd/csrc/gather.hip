@@ -2,22 +2,22 @@
 // every output cell and channel, gather-side (Section 2.2: each cell pulls
 // the samples within its support, so no two workgroups write the same cell).
 //
-// Work decomposition: one workgroup (8 waves) per 16 x 16 tile of output
-// cells and 256-channel slab.  The tile's candidate samples come from the
-// plan's sorted-sample ranges and are staged in blocks of 64:
-//   1. weights: FP64 chord distance between unit vectors of cell and sample,
-//      exact support test (chord <= 2 sin(R/2), i.e. d <= R), FP64 exponent
-//      of the Gaussian, evaluated with exp2f, rounded to the operand type of
-//      the form; FP64 sums of the weights per cell;
-//   2. accumulation: the block is a dense contraction
-//      U[cells x channels] += Wt[cells x 64] . S[64 x channels] on the matrix
-//      cores with FP32 accumulation -- FP32 operands (v_mfma_f32_16x16x4_f32)
-//      or BF16 / FP16 / FP8 operands (16x16x32) -- skipping every 16-cell x
-//      k-step sub-block whose weights are all zero; for a few FP32 channels
-//      each thread owns one cell and accumulates in FP64;
-//   3. epilogue: V = U / W~ (W~ the sum of the weights actually multiplied),
-//      times the channel scale for the scaled forms, NaN where no sample is
-//      within the support; the W map is the FP64 sum of the weights.
+// Work decomposition: one workgroup per 8 x 8 tile of output cells (and per
+// 256- or 512-channel slab for many channels).  The tile's candidate samples
+// come from the plan's sorted-sample ranges and are staged in blocks of 64:
+//   1. weights: FP64 haversine distance of every (cell, candidate) pair of
+//      the block, exact support test, FP64 Gaussian weight, rounded to the
+//      operand type of the form; FP64 sums of the weights per cell;
+//   2. accumulation: for many channels the block is a dense contraction
+//      U[cells x channels] += Wt[cells x 64] . S[64 x channels] done on the
+//      matrix cores with FP32 accumulation -- FP32 operands
+//      (v_mfma_f32_16x16x4_f32) or BF16 / FP16 / FP8 operands (16x16x32),
+//      skipping every 16-cell x k-step sub-block whose weights are all zero;
+//      for a few FP32 channels each lane owns one cell and accumulates in
+//      FP64;
+//   3. epilogue: V = U / W~ (W~ the sum of the weights actually multiplied,
+//      times the channel scale for the scaled forms), NaN where no sample is
+//      within the support; W map = FP64 sum of the unrounded weights.
 #include <cmath>
 #include <vector>
 
@@ -26,25 +26,17 @@
 namespace hcg {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-constexpr int kKB = 64;          // candidates staged per block
-constexpr int kCB = 16;          // 4 x 4 cell blocks per 16 x 16 tile
-constexpr int kWGThreads = 512;  // 8 waves
-constexpr int kSlab = 256;       // channels per workgroup (4 groups of 64)
+constexpr int kKB = 64;             // candidates staged per block
 
-// ---------------------------------------------------------------------------
-// Geometry
-// ---------------------------------------------------------------------------
+// Unit vector of cell (ix, iy); NaN outside the grid (never within R).
 struct CellVec {
   double x, y, z;
 };
 
-// Unit vector of cell (ix, iy); NaN outside the grid (never within R).
 __device__ __forceinline__ CellVec cell_vec(const GridGeom& g, int ix, int iy) {
   CellVec c;
-  if (ix >= g.nx || iy >= g.ny || ix < 0 || iy < 0) {
+  if (ix >= g.nx || iy >= g.ny) {
     c.x = c.y = c.z = __builtin_nan("");
     return c;
   }
@@ -62,35 +54,80 @@ __device__ __forceinline__ double chord2(const CellVec& c, const double4& v) {
   const double dx = v.x - c.x, dy = v.y - c.y, dz = v.z - c.z;
   return dx * dx + dy * dy + dz * dz;
 }
-__device__ __forceinline__ double chord2(const CellVec& c, const double2& xy, double z) {
-  const double dx = xy.x - c.x, dy = xy.y - c.y, dz = z - c.z;
-  return dx * dx + dy * dy + dz * dz;
+
+// Squared great-circle distance from the squared chord c2:
+// d^2 = 4 asin^2(chord / 2) = 2 sum_n c2^n / (n^2 binom(2n, n))
+//     = c2 (1 + c2/12 + c2^2/90 + c2^3/560 + c2^4/3150 + c2^5/16632 + ...);
+// six terms leave a relative error below 2e-17 for c2 < 1e-2 (d < 5.7 deg),
+// the arcsine beyond.
+__device__ __forceinline__ double dist2_from_chord2(double c2) {
+  if (c2 < 1e-2)
+    return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
+           c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
+  const double d = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
+  return d * d;
 }
 
-
-// Weight of a pair inside the support.  d^2 = 4 asin^2(chord / 2)
-// = 2 sum_n c2^n / (n^2 binom(2n, n)) = c2 (1 + c2/12 + c2^2/90 + c2^3/560
-// + c2^4/3150 + c2^5/16632 + ...): for c2 < 1e-2 (d < 5.7 deg) six terms
-// leave a relative error below 2e-17.  Wider supports (kWide) take the
-// arcsine beyond that.  The exponent -d^2 log2(e) / (2 sigma^2) is formed
-// in FP64 and evaluated with exp2f.
-constexpr double kSeriesMax = 1e-2;
-
-template <bool kWide>
+// FP32 weight of a pair inside the support: the exponent -d^2 log2(e) /
+// (2 sigma^2) is formed in FP64 and evaluated with exp2f.
 __device__ __forceinline__ float pair_weight(double c2, double wscale) {
-  double d2;
-  if (!kWide || c2 < kSeriesMax) {
-    d2 = c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
-              c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
-  } else {
-    const double d = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
-    d2 = d * d;
+  return exp2f((float)(dist2_from_chord2(c2) * wscale));
+}
+
+// bit q (q < 8) of the result: any of bits 4q .. 4q + 3 of x
+__device__ __forceinline__ uint32_t any_of_nibbles(uint32_t x) {
+  x |= x >> 1;
+  x |= x >> 2;
+  x &= 0x11111111u;
+  x = (x | (x >> 3)) & 0x03030303u;
+  x = (x | (x >> 6)) & 0x000F000Fu;
+  return (x | (x >> 12)) & 0xFFu;
+}
+// bit q (q < 4) of the result: any of bits 8q .. 8q + 7 of x
+__device__ __forceinline__ uint32_t any_of_bytes(uint32_t x) {
+  x |= x >> 1;
+  x |= x >> 2;
+  x |= x >> 4;
+  x &= 0x01010101u;
+  x = (x | (x >> 7)) & 0x00030003u;
+  return (x | (x >> 14)) & 0xFu;
+}
+
+// Centres and coarse thresholds of the four 4 x 4 cell blocks of tile (tx,
+// ty); called by threads 0..63 (block t / 16, cell t % 16).  The centre is
+// the normalised mean of the block's cells inside the grid; a candidate can
+// only be within R of a cell of the block if it is within R + h of the
+// centre (h: the largest centre-to-cell distance; triangle inequality), so
+// the threshold is the squared chord of R + h, with slack for rounding.  A
+// block without cells gets threshold -1 (never marked).
+__device__ void block_centres(const GatherArgs& a, int tx, int ty, int t, double4* ctr) {
+  const GridGeom& g = a.g;
+  const int cb = t >> 4, i = t & 15;
+  const int x = tx * kTileX + (cb & 1) * 4 + (i & 3), y = ty * kTileY + (cb >> 1) * 4 + (i >> 2);
+  const bool valid = x < g.nx && y < g.ny;
+  const CellVec v = cell_vec(g, x, y);
+  double sx = valid ? v.x : 0.0, sy = valid ? v.y : 0.0, sz = valid ? v.z : 0.0;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+    sz += __shfl_xor(sz, o);
   }
-  return exp2f((float)(d2 * wscale));
+  const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
+  const CellVec c{sx / nrm, sy / nrm, sz / nrm};
+  double hc2 = valid ? chord2(c, make_double4(v.x, v.y, v.z, 0.0)) : 0.0;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) hc2 = fmax(hc2, __shfl_xor(hc2, o));
+  const double R = 2.0 * asin(fmin(0.5 * sqrt(a.c2R), 1.0));
+  const double h = 2.0 * asin(fmin(0.5 * sqrt(hc2), 1.0));
+  const double sh = sin(0.5 * fmin(R + h, kPi));
+  double thr = 4.0 * sh * sh * (1.0 + 1e-9) + 1e-15;
+  if (!(nrm > 0.0)) thr = -1.0;
+  if (i == 0) ctr[cb] = make_double4(c.x, c.y, c.z, thr);
 }
 
 // Loads the tile's candidate ranges into LDS with exclusive prefix sums;
-// returns the total candidate count.  All threads of the block take part.
+// returns the total candidate count.  blockDim.x threads take part.
 __device__ uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32_t nr, uint2* s_rng,
                                  uint32_t* s_pre) {
   const int nt = blockDim.x;
@@ -122,10 +159,43 @@ __device__ __forceinline__ uint32_t cand_pos(uint32_t q, const uint2* s_rng, con
 // ---------------------------------------------------------------------------
 enum Form : int { kF32 = 0, kBF16 = 1, kBF16Split = 2, kF16S = 3, kFP8S = 4 };
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Many channels: matrix-core contraction per staged block of 64 candidates.
+//
+// Workgroup = 4 waves, tile = 8 x 8 cells = four 4 x 4 cell blocks (MFMA M =
+// 16 cells), channel slab = 4 waves x 64 QW channels.  Per block:
+//  - weights: wave w computes the FP64 weights of cell block w for the 64
+//    candidates (one cell per lane), rounds them to the operand type and
+//    writes them to LDS in the A-operand layout; one bit per (cell block,
+//    k-step) marks a non-zero sub-block;
+//  - contraction: wave w streams its channels of the block's candidate rows
+//    from HBM into B operands and issues the MFMAs of the non-zero
+//    sub-blocks for all four cell blocks.
+// Operand layouts (lane l, i = l % 16, g = l / 16):
+//   FP32  v_mfma_f32_16x16x4_f32: A = w(cell i, cand 4s + g), B = spectrum of
+//         cand 4s + g at channel 4i + q (MFMA q of a 64-channel group);
+//   16-bit / FP8 16x16x32: A = w(cell i, cands 32s + 8g .. +7) packed, B = the
+//         same 8 candidates at channel 4i + q, repacked from 8-byte (16-bit)
+//         or 4-byte (FP8) row loads.
+// Output D[i][j]: lane l, register r holds cell 4 (l/16) + r of the block and
+// channel 4 (l % 16) + q of the group.
+// ---------------------------------------------------------------------------
+
 template <int kForm>
-struct FormTraits {
-  static constexpr int kK = (kForm == kF32) ? 4 : 32;  // candidates per MFMA k-step
-};
+struct FormTraits;
+template <>
+struct FormTraits<kF32> { static constexpr int kK = 4; };
+template <>
+struct FormTraits<kBF16> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kBF16Split> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kF16S> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kFP8S> { static constexpr int kK = 32; };
 
 template <int kForm>
 __device__ __forceinline__ uint32_t enc_w(float w) {
@@ -146,570 +216,336 @@ __device__ __forceinline__ uint32_t elem16(uint2 d, int q) {
   return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
-// LDS of one workgroup (shared by the per-plan kernels and the batch kernel).
-// Staged candidate blocks are double-buffered (coordinates, A fragments) or
-// triple-buffered (rows, read by the spectrum loads one block ahead).
+// LDS of one workgroup of the gather (shared by the per-plan kernel and the
+// persistent batch kernel).
 struct GatherSmem {
   uint2 rng[kMaxRangesLimit];
   uint32_t pre[kMaxRangesLimit + 1];
-  double2 xy[2][kKB];    // staged coordinates: x, y
-  double2 zw[2][kKB];    // z, 0
-  double4 ctr[kCB];      // cell-block centre (unit vector), coarse squared chord
-  uint32_t row[3][kKB];
-  uint32_t nzm[2][kCB];  // non-zero k-steps of each cell block
-  // A fragments, per buffer: FP32 [16 cb][16 k-steps][64 lanes] float;
-  // BF16 / FP16 [16 cb][2 k-steps][64] uint4 (+ the low plane of the split
-  // form behind it); FP8 [16][2][64] uint2.  Also the staging area of the
-  // few-channel path.
-  uint4 A[2][kCB * 16 * 64 / 4];
+  double4 xyz[kKB];
+  double4 ctr[4];  // cell-block centres and coarse thresholds
+  uint32_t row[kKB];
+  uint4 Araw[1024];
+  uint32_t nz[4];
   double Wt[kTileCells];
 };
-static_assert(sizeof(GatherSmem::A) >= 2 * 2 * 256 * sizeof(double4),
-              "the few-channel path stages two parts of 16 KB in A");
-static_assert(sizeof(GatherSmem) <= 160 * 1024, "LDS of one workgroup");
 
-// bit q (q < 8) of the result: any of bits 4q .. 4q + 3 of x
-__device__ __forceinline__ uint32_t any_of_nibbles(uint32_t x) {
-  x |= x >> 1;
-  x |= x >> 2;
-  x &= 0x11111111u;
-  x = (x | (x >> 3)) & 0x03030303u;
-  x = (x | (x >> 6)) & 0x000F000Fu;
-  return (x | (x >> 12)) & 0xFFu;
-}
-// bit q (q < 4) of the result: any of bits 8q .. 8q + 7 of x
-__device__ __forceinline__ uint32_t any_of_bytes(uint32_t x) {
-  x |= x >> 1;
-  x |= x >> 2;
-  x |= x >> 4;
-  x &= 0x01010101u;
-  x = (x | (x >> 7)) & 0x00030003u;
-  return (x | (x >> 14)) & 0xFu;
-}
-
-// ---------------------------------------------------------------------------
-// Many channels: one (16 x 16 tile, 256-channel slab) on the matrix cores.
-//
-// The tile's 256 cells form sixteen 4 x 4 cell blocks (cb); a staged block of
-// 64 candidates forms k-steps of 4 (FP32) or 32 (BF16 / FP16 / FP8)
-// candidates.  An A fragment is one (cb, k-step): lane l of it holds cell
-// l % 16 and candidate l / 16 (FP32) or candidates 8 (l / 16) .. +7.
-//
-// Weights: wave w owns cell blocks 2w and 2w + 1.  A coarse test first marks
-// the fragments that can hold a pair within R: a candidate can only be within
-// R of some cell of a block if it is within R + h of the block's centre (h:
-// the block's largest centre-to-cell distance; triangle inequality).  Only
-// those fragments are evaluated exactly (FP64 chord, exact support test,
-// weight), lane by lane straight into the A layout; a fragment found all zero
-// is dropped.  The fragment lists are wave-uniform.
-// Contraction: wave w covers cell blocks 8 (w % 2) .. +7 and the 64 channels
-// 64 (w / 2) .. +63 of the slab; lane l streams channels 4 (l % 16) .. +3
-// (column j of MFMA q is channel 4 j + q of the group), skipping the
-// fragments that are not marked.
-// Output D[i][j]: lane l, register r holds cell 4 (l / 16) + r of the block.
-//
-// Software pipeline over the blocks, one barrier per block: while a wave runs
-// the products of block b it evaluates its fragments of block b + 1 between
-// the matrix instructions, and its spectrum loads run ahead across the block
-// boundary; coordinates and rows of block b + 2 are staged meanwhile.
-// ---------------------------------------------------------------------------
-// kVec: 1 = rows read 4 elements at a time, 0 = one at a time, 2 = as a.vec
-// says (FP32 only).  kWide: the support reaches c2 >= kSeriesMax.
-template <int kForm, int kVec, bool kWide>
+// One (tile, channel slab) of the contraction; all 256 threads take part.
+template <int kForm, int kQW, bool kVec>
 __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int slab,
                                             GatherSmem& sm) {
   constexpr int kK = FormTraits<kForm>::kK;
   constexpr int kNS = kKB / kK;  // k-steps per staged block
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  uint2* s_rng = sm.rng;
+  uint32_t* s_pre = sm.pre;
+  double4* s_xyz = sm.xyz;
+  uint32_t* s_row = sm.row;
+  uint4* s_Araw = sm.Araw;
+  uint32_t* s_nz = sm.nz;
+  double* s_Wt = sm.Wt;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const GridGeom& g = a.g;
   const int64_t C = a.C;
   const int64_t G = (int64_t)g.nx * g.ny;
 
-  // weight role: cell blocks cbA = 2 wave, cbB = cbA + 1; lane l: cell l % 16
-  const int li = lane & 15;
-  const int cbA = 2 * wave, cbB = cbA + 1;
-  auto cell_x = [&](int cb) { return tx * kTileX + (cb & 3) * 4 + (li & 3); };
-  auto cell_y = [&](int cb) { return ty * kTileY + (cb >> 2) * 4 + (li >> 2); };
-  const CellVec cellA = cell_vec(g, cell_x(cbA), cell_y(cbA));
-  const CellVec cellB = cell_vec(g, cell_x(cbB), cell_y(cbB));
-  // contraction role
-  const int cg = wave & 1;
-  const int64_t my_ch = (int64_t)slab * kSlab + (wave >> 1) * 64 + 4 * (lane & 15);
-  const bool ch_ok = my_ch + 3 < C;  // the vector loads (C % 4 == 0 there)
+  const int ci = lane & 15;
+  const int my_x = tx * kTileX + (wave & 1) * 4 + (ci & 3);
+  const int my_y = ty * kTileY + (wave >> 1) * 4 + (ci >> 2);
+  const CellVec cell = cell_vec(g, my_x, my_y);
 
   const uint32_t total =
-      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
-  const uint32_t nb = (total + kKB - 1) / kKB;
+      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre);
+  if (tid < 64) block_centres(a, tx, ty, tid, sm.ctr);
 
-  floatx4 acc[8][4];
+  floatx4 acc[4][4 * kQW];
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
+  for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // FP64 sums of the weights of this lane's cell in cbA / cbB (its share of
-  // the candidates), as evaluated and as multiplied (rounded forms)
-  double wsA = 0.0, wsB = 0.0, wtA = 0.0, wtB = 0.0;
+    for (int q = 0; q < 4 * kQW; ++q) acc[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  double wsum = 0.0;   // FP64 sum of the unrounded weights (this lane's share)
+  double wtsum = 0.0;  // FP64 sum of the weights as used in the products
   uint32_t cur = 0;
+  const int64_t c_w = (int64_t)slab * (256 * kQW) + wave * (64 * kQW);
+  const int64_t my_ch = c_w + 4 * (lane & 15);  // + 64 h + q
 
-  // Coordinates and rows of block blk, read by wave 0 into registers
-  // (stage_load: unconditional loads; past the last candidate the plan's
-  // sentinel entry, NaN vector and row 0) and written to LDS after the
-  // block's products (stage_store), so that the wait for them does not drain
-  // the spectrum loads in flight.
-  const bool stager = wave == 0;
-  double4 st_v = make_double4(0.0, 0.0, 0.0, 0.0);
-  uint32_t st_r = 0u;
-  auto stage_load = [&](uint32_t blk) {
-    if (stager) {
-      const uint32_t q = blk * kKB + lane;
-      const uint32_t pos = (q < total) ? cand_pos(q, sm.rng, sm.pre, &cur) : a.sentinel;
-      st_v = a.xyz[pos];
-      st_r = a.perm[pos];
-    }
-  };
-  auto stage_store = [&](uint32_t blk, int rbuf) {
-    if (stager) {
-      sm.xy[blk & 1][lane] = make_double2(st_v.x, st_v.y);
-      sm.zw[blk & 1][lane] = make_double2(st_v.z, st_v.w);
-      sm.row[rbuf][lane] = st_r;
-    }
-  };
+  float* sA32 = (float*)s_Araw;                // [4][16][64]
+  uint4* sA16 = s_Araw;                        // [4][kNS][64] (+ lo plane after)
+  uint2* sA8 = (uint2*)s_Araw;                 // [4][kNS][64]
 
-  // Cell-block centres and coarse thresholds (threads 0..255: block t / 16,
-  // cell t % 16).  Cells outside the grid do not count; a block without
-  // cells gets threshold -1 (never marked).
-  if (tid < kTileCells) {
-    const int cb = tid >> 4, i = tid & 15;
-    const int x = tx * kTileX + (cb & 3) * 4 + (i & 3), y = ty * kTileY + (cb >> 2) * 4 + (i >> 2);
-    const bool valid = x < g.nx && y < g.ny;
-    const CellVec v = cell_vec(g, x, y);
-    double sx = valid ? v.x : 0.0, sy = valid ? v.y : 0.0, sz = valid ? v.z : 0.0;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      sx += __shfl_xor(sx, o);
-      sy += __shfl_xor(sy, o);
-      sz += __shfl_xor(sz, o);
+  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
+    if (tid < kKB) {
+      const uint32_t q = q0 + tid;
+      if (q < total) {
+        const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
+        s_xyz[tid] = a.xyz[pos];
+        s_row[tid] = a.perm[pos];
+      } else {
+        const double nan = __builtin_nan("");
+        s_xyz[tid] = make_double4(nan, nan, nan, nan);
+        s_row[tid] = 0u;
+      }
     }
-    const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
-    const CellVec c{sx / nrm, sy / nrm, sz / nrm};
-    double hc2 = valid ? chord2(c, make_double4(v.x, v.y, v.z, 0.0)) : 0.0;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) hc2 = fmax(hc2, __shfl_xor(hc2, o));
-    const double R = 2.0 * asin(fmin(0.5 * sqrt(a.c2R), 1.0));
-    const double h = 2.0 * asin(fmin(0.5 * sqrt(hc2), 1.0));
-    const double ang = R + h;
-    const double sh = sin(0.5 * fmin(ang, kPi));
-    double thr = 4.0 * sh * sh * (1.0 + 1e-9) + 1e-15;  // slack for rounding
-    if (!(nrm > 0.0)) thr = -1.0;
-    if (i == 0) sm.ctr[cb] = make_double4(c.x, c.y, c.z, thr);
-  }
+    __syncthreads();
 
-  // Coarse marks of the wave's two blocks for the candidates in buffer buf.
-  // Lane l tests candidates l % 32 and l % 32 + 32 against block cbA (l < 32)
-  // or cbB.  F32: bit s of m = k-step s; other forms: bit s of m = k-step s,
-  // bit 4 s + j of gm = its 8-candidate group j.
-  auto coarse = [&](int buf, uint32_t& mA, uint32_t& mB, uint32_t& gA, uint32_t& gB) {
-    const double4 c = sm.ctr[cbA + (lane >> 5)];
-    const CellVec cc{c.x, c.y, c.z};
-    const int j = lane & 31;
-    const double c2a = chord2(cc, sm.xy[buf][j], sm.zw[buf][j].x);
-    const double c2b = chord2(cc, sm.xy[buf][j + 32], sm.zw[buf][j + 32].x);
-    const uint64_t b1 = __ballot(c2a <= c.w), b2 = __ballot(c2b <= c.w);
-    const uint32_t a1 = (uint32_t)b1, a2 = (uint32_t)b2;
-    const uint32_t h1 = (uint32_t)(b1 >> 32), h2 = (uint32_t)(b2 >> 32);
-    if constexpr (kForm == kF32) {
-      mA = any_of_nibbles(a1) | (any_of_nibbles(a2) << 8);
-      mB = any_of_nibbles(h1) | (any_of_nibbles(h2) << 8);
-      gA = gB = 0u;
-    } else {
-      gA = any_of_bytes(a1) | (any_of_bytes(a2) << 4);
-      gB = any_of_bytes(h1) | (any_of_bytes(h2) << 4);
-      mA = ((gA & 15u) ? 1u : 0u) | ((gA >> 4) ? 2u : 0u);
-      mB = ((gB & 15u) ? 1u : 0u) | ((gB >> 4) ? 2u : 0u);
-    }
-  };
-
-  // Exact weights of fragment (cb, ks) of the block in buffer buf; returns
-  // whether any weight is non-zero.
-  auto frag = [&](int buf, int cb, int ks, const CellVec& cv, uint32_t gm, double& ws,
-                  double& wt) -> bool {
-    if constexpr (kForm == kF32) {
-      const int k = 4 * ks + (lane >> 4);
-      const double c2 = chord2(cv, sm.xy[buf][k], sm.zw[buf][k].x);
-      float wf = 0.f;
-      if (c2 <= a.c2R) wf = pair_weight<kWide>(c2, a.wscale);
-      ws += (double)wf;
-      ((float*)sm.A[buf])[(cb * 16 + ks) * 64 + lane] = wf;
-      return __ballot(wf != 0.f) != 0ull;
-    } else {
-      const int grp = lane >> 4;
-      uint32_t hi[8], lo[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) hi[t] = lo[t] = 0u;
-      if ((gm >> (4 * ks + grp)) & 1u) {
-        const int k0 = 32 * ks + 8 * grp;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const double c2 = chord2(cv, sm.xy[buf][k0 + t], sm.zw[buf][k0 + t].x);
-          if (c2 <= a.c2R) {
-            const float wf = pair_weight<kWide>(c2, a.wscale);
-            hi[t] = enc_w<kForm>(wf);
-            double eff = (double)dec_w<kForm>(hi[t]);
-            if (kForm == kBF16Split) {
-              lo[t] = f32_to_bf16(wf - dec_w<kForm>(hi[t]));
-              eff += (double)bf16_to_f32(lo[t]);
-            }
-            ws += (double)wf;
-            wt += eff;
-          }
+    // ---- weights of cell block `wave`, in the A-operand layout.  A coarse
+    // test against the block's centre (lane l: candidate l) marks the
+    // fragments (k-steps) that can hold a pair within R; only those are
+    // evaluated exactly.  Unmarked fragments are never multiplied.
+    uint32_t nzbits = 0;
+    {
+      const double4 c = sm.ctr[wave];
+      const double c2c = chord2(CellVec{c.x, c.y, c.z}, s_xyz[lane]);
+      const uint64_t bm = __ballot(c2c <= c.w);
+      const uint32_t lo = (uint32_t)bm, hi = (uint32_t)(bm >> 32);
+      if (kForm == kF32) {
+        uint32_t pm = any_of_nibbles(lo) | (any_of_nibbles(hi) << 8);
+        while (pm) {
+          const int ks = __builtin_ctz(pm);
+          pm &= pm - 1u;
+          const double c2 = chord2(cell, s_xyz[4 * ks + (lane >> 4)]);
+          float wf = 0.f;
+          if (c2 <= a.c2R) wf = pair_weight(c2, a.wscale);
+          wsum += (double)wf;
+          sA32[(wave * kNS + ks) * 64 + lane] = wf;
+          if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
         }
-      }
-      const int slot = (cb * 2 + ks) * 64 + lane;
-      uint32_t any;
-      if (kForm == kFP8S) {
-        const uint2 v = make_uint2(hi[0] | (hi[1] << 8) | (hi[2] << 16) | (hi[3] << 24),
-                                   hi[4] | (hi[5] << 8) | (hi[6] << 16) | (hi[7] << 24));
-        ((uint2*)sm.A[buf])[slot] = v;
-        any = v.x | v.y;
       } else {
-        const uint4 v = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16),
-                                   hi[4] | (hi[5] << 16), hi[6] | (hi[7] << 16));
-        sm.A[buf][slot] = v;
-        any = v.x | v.y | v.z | v.w;
-        if (kForm == kBF16Split) {
-          const uint4 u = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
-                                     lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
-          sm.A[buf][kCB * 2 * 64 + slot] = u;
-          any |= u.x | u.y | u.z | u.w;
-        }
-      }
-      return __ballot(any != 0u) != 0ull;
-    }
-  };
-
-  // The wave's fragment lists of the block being weighted, one bit per
-  // (block, k-step): bit ks for cbA, bit kNS + ks for cbB; pending (pm) and
-  // kept (rm: marked and not found all zero).  Wave-uniform.
-  uint32_t pm = 0u, rm = 0u, gA = 0u, gB = 0u;
-  auto start_block = [&](int buf) {
-    uint32_t mA, mB;
-    coarse(buf, mA, mB, gA, gB);
-    pm = rm = mA | (mB << kNS);
-  };
-  auto one_frag = [&](int buf) {
-    if (pm) {
-      const int bit = __builtin_ctz(pm);
-      pm &= pm - 1u;
-      const bool isB = bit >= kNS;
-      const int ks = isB ? bit - kNS : bit;
-      double dws = 0.0, dwt = 0.0;
-      const bool nz = isB ? frag(buf, cbB, ks, cellB, gB, dws, dwt)
-                          : frag(buf, cbA, ks, cellA, gA, dws, dwt);
-      if (!nz) rm &= ~(1u << bit);
-      if (isB) {
-        wsB += dws;
-        wtB += dwt;
-      } else {
-        wsA += dws;
-        wtA += dwt;
-      }
-    }
-  };
-  auto finish_block = [&](int buf) {
-    while (pm) one_frag(buf);
-    if (lane == 0) {
-      sm.nzm[buf][cbA] = rm & ((1u << kNS) - 1u);
-      sm.nzm[buf][cbB] = rm >> kNS;
-    }
-  };
-
-  // prologue: centres, blocks 0 and 1 staged, weights of block 0
-  if (nb > 0) {
-    stage_load(0);
-    stage_store(0, 0);
-    stage_load(1);
-    stage_store(1, 1);
-  }
-  __syncthreads();
-  if (nb > 0) {
-    start_block(0);
-    finish_block(0);
-  }
-  __syncthreads();
-
-  if constexpr (kForm == kF32) {
-    const float* spec = (const float*)a.spec;
-    constexpr int kDepth = 4;
-    static_assert(kNS % kDepth == 0, "the load window must divide the k-steps");
-    // Every load is issued unconditionally, so that the waits for them can
-    // be counted exactly.  A channel past C reads a clamped address instead;
-    // its value only reaches MFMA columns that are never stored (column j of
-    // the product depends on column j of B alone).
-    auto load = [&](int rbuf, int ks) -> floatx4 {
-      const int64_t row = sm.row[rbuf][4 * ks + (lane >> 4)];
-      const float* src = spec + row * C;
-      floatx4 v;
-      if (kVec == 1 || (kVec == 2 && (a.vec & 1))) {
-        v = *(const floatx4*)(src + (ch_ok ? my_ch : 0));
-      } else {
-        v.x = src[min(my_ch + 0, C - 1)];
-        v.y = src[min(my_ch + 1, C - 1)];
-        v.z = src[min(my_ch + 2, C - 1)];
-        v.w = src[min(my_ch + 3, C - 1)];
-      }
-      return v;
-    };
-    floatx4 bw[kDepth];
-    if (nb > 0) {
-#pragma unroll
-      for (int d = 0; d < kDepth; ++d) bw[d] = load(0, d);
-    }
-    int rb = 0;  // row buffer of block b (b mod 3)
-    for (uint32_t b = 0; b < nb; ++b) {
-      const int cb_ = b & 1, nx_ = cb_ ^ 1;
-      const int rn = (rb == 2) ? 0 : rb + 1, rn2 = (rn == 2) ? 0 : rn + 1;
-      stage_load(b + 2);
-      start_block(nx_);  // block b + 1 (an empty block after the last one)
-      uint32_t nzc[8];   // wave-uniform: kept in scalar registers
-#pragma unroll
-      for (int c = 0; c < 8; ++c) nzc[c] = __builtin_amdgcn_readfirstlane(sm.nzm[cb_][8 * cg + c]);
-      const float* sA = (const float*)sm.A[cb_] + (8 * cg * 16) * 64 + lane;
-      // the k-steps in quads of kDepth (a runtime loop: the code of the
-      // whole block would not fit the instruction cache)
-#pragma unroll 1
-      for (int qd = 0; qd < kNS / kDepth; ++qd) {
-        // the window runs on into block b + 1 (empty past the last block)
-        const bool last = qd + 1 == kNS / kDepth;
-        const int lrb = last ? rn : rb;
-        const int lks = last ? 0 : kDepth * (qd + 1);
-#pragma unroll
-        for (int j = 0; j < kDepth; ++j) {
-          const int ks = kDepth * qd + j;
-          const floatx4 bv = bw[j];
-          bw[j] = load(lrb, lks + j);
-          one_frag(nx_);
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            if ((nzc[c] >> ks) & 1u) {
-              const float av = sA[(c * 16 + ks) * 64];
-              acc[c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.x, acc[c][0], 0, 0, 0);
-              acc[c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.y, acc[c][1], 0, 0, 0);
-              acc[c][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.z, acc[c][2], 0, 0, 0);
-              acc[c][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.w, acc[c][3], 0, 0, 0);
+        // bit 4 s + j: 8-candidate group j of k-step s
+        const uint32_t gm = any_of_bytes(lo) | (any_of_bytes(hi) << 4);
+        uint32_t pm = ((gm & 15u) ? 1u : 0u) | ((gm >> 4) ? 2u : 0u);
+        const int grp = lane >> 4;
+        while (pm) {
+          const int ks = __builtin_ctz(pm);
+          pm &= pm - 1u;
+          // codes packed as they are made: 16-bit forms two per word, FP8 four
+          uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+          if ((gm >> (4 * ks + grp)) & 1u) {
+            const int k0 = kK * ks + 8 * grp;
+            for (int t = 0; t < 8; ++t) {
+              const double c2 = chord2(cell, s_xyz[k0 + t]);
+              uint32_t h = 0u, l = 0u;
+              if (c2 <= a.c2R) {
+                const float wf = pair_weight(c2, a.wscale);
+                h = enc_w<kForm>(wf);
+                double eff = (double)dec_w<kForm>(h);
+                if (kForm == kBF16Split) {
+                  l = f32_to_bf16(wf - dec_w<kForm>(h));
+                  eff += (double)bf16_to_f32(l);
+                }
+                wsum += (double)wf;
+                wtsum += eff;
+              }
+              if (kForm == kFP8S) {
+                hw[t >> 2] |= h << (8 * (t & 3));
+              } else {
+                hw[t >> 1] |= h << (16 * (t & 1));
+                if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
+              }
             }
           }
-          // keep each k-step's loads, weights and products together (register
-          // pressure: the scheduler would otherwise hoist the next k-steps')
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-      finish_block(nx_);
-      stage_store(b + 2, rn2);
-      rb = rn;
-      __syncthreads();
-    }
-  } else {
-    // B fragments of one k-step: 8 candidate rows x 4 channels per lane
-    constexpr bool kSplit = (kForm == kBF16Split);
-    // k-steps loaded ahead (0: at use; the split and element-wise forms
-    // have no registers to spare for a window)
-    constexpr int kDepth = (kForm == kFP8S) ? 2 : (kSplit || kVec != 1) ? 0 : 1;
-    struct Frag {
-      uint32_t x[8], y[8];    // FP8: x only (4 bytes per row); 16-bit: 8 bytes per row
-      uint32_t lx[8], ly[8];  // low plane of the split form
-    };
-    auto load = [&](int rbuf, int ks, Frag& f) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int64_t row = sm.row[rbuf][kK * ks + 8 * (lane >> 4) + t];
-        // unconditional loads, clamped past C (as in the FP32 path)
-        if (kForm == kFP8S) {
-          const uint8_t* src = (const uint8_t*)a.spec + row * C;
-          if (kVec == 1) {
-            f.x[t] = *(const uint32_t*)(src + (ch_ok ? my_ch : 0));
+          uint32_t any;
+          if (kForm == kFP8S) {
+            sA8[(wave * kNS + ks) * 64 + lane] = make_uint2(hw[0], hw[1]);
+            any = hw[0] | hw[1];
           } else {
-            uint32_t v = 0u;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v |= (uint32_t)src[min(my_ch + e, C - 1)] << (8 * e);
-            f.x[t] = v;
-          }
-        } else {
-#pragma unroll
-          for (int plane = 0; plane < (kSplit ? 2 : 1); ++plane) {
-            const uint16_t* src = (const uint16_t*)(plane ? a.spec_lo : a.spec) + row * C;
-            uint2 d;
-            if (kVec == 1) {
-              d = *(const uint2*)(src + (ch_ok ? my_ch : 0));
-            } else {
-              uint32_t e[4];
-#pragma unroll
-              for (int j = 0; j < 4; ++j) e[j] = src[min(my_ch + j, C - 1)];
-              d = make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
+            sA16[(wave * kNS + ks) * 64 + lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            any = hw[0] | hw[1] | hw[2] | hw[3];
+            if (kForm == kBF16Split) {
+              sA16[(4 * kNS + wave * kNS + ks) * 64 + lane] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+              any |= lw[0] | lw[1] | lw[2] | lw[3];
             }
-            if (plane) { f.lx[t] = d.x; f.ly[t] = d.y; }
-            else { f.x[t] = d.x; f.y[t] = d.y; }
           }
+          if (__ballot(any != 0u)) nzbits |= 1u << ks;
         }
       }
-    };
-    Frag bw[kDepth > 0 ? kDepth : 1];
-    if (nb > 0) {
-#pragma unroll
-      for (int d = 0; d < kDepth; ++d) load(0, d, bw[d]);
     }
-    int rb = 0;
-    for (uint32_t b = 0; b < nb; ++b) {
-      const int cb_ = b & 1, nx_ = cb_ ^ 1;
-      const int rn = (rb == 2) ? 0 : rb + 1, rn2 = (rn == 2) ? 0 : rn + 1;
-      stage_load(b + 2);
-      start_block(nx_);
-      uint32_t nzc[8];
+    if (lane == 0) s_nz[wave] = nzbits;
+    __syncthreads();
+
+    // ---- contraction over the block
+    const uint32_t nzc[4] = {s_nz[0], s_nz[1], s_nz[2], s_nz[3]};
+    if (kForm == kF32) {
+      const float* spec = (const float*)a.spec;
+      constexpr int kDepth = 4;
+      floatx4 b[kDepth][kQW];
+      auto load = [&](int ks, floatx4* dst) {
+        const int64_t row = s_row[4 * ks + (lane >> 4)];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) nzc[c] = __builtin_amdgcn_readfirstlane(sm.nzm[cb_][8 * cg + c]);
+        for (int h = 0; h < kQW; ++h) {
+          const int64_t ch = my_ch + 64 * h;
+          const float* src = spec + row * C + ch;
+          if (kVec) {
+            dst[h] = (ch + 3 < C) ? *(const floatx4*)src : floatx4{0.f, 0.f, 0.f, 0.f};
+          } else {
+            dst[h].x = (ch + 0 < C) ? src[0] : 0.f;
+            dst[h].y = (ch + 1 < C) ? src[1] : 0.f;
+            dst[h].z = (ch + 2 < C) ? src[2] : 0.f;
+            dst[h].w = (ch + 3 < C) ? src[3] : 0.f;
+          }
+        }
+      };
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) load(d, b[d]);
 #pragma unroll
       for (int ks = 0; ks < kNS; ++ks) {
-        Frag f;
-        if constexpr (kDepth == 0) {
-          load(rb, ks, f);
-        } else {
-          f = bw[ks % kDepth];
-          if (ks + kDepth < kNS) load(rb, ks + kDepth, bw[ks % kDepth]);
-          else load(rn, ks + kDepth - kNS, bw[ks % kDepth]);
-        }
-        one_frag(nx_);
-        uint32_t any = 0;
+        floatx4 cb_b[kQW];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) any |= nzc[c];
-        if (!((any >> ks) & 1u)) continue;
-        // repack: the 8 rows of channel q into the B operand of MFMA q
-        uint32_t fb[4][4], fbl[4][4];
+        for (int h = 0; h < kQW; ++h) cb_b[h] = b[ks % kDepth][h];
+        if (ks + kDepth < kNS) load(ks + kDepth, b[ks % kDepth]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (kForm == kFP8S) {
-            fb[q][0] = ((f.x[0] >> (8 * q)) & 0xFFu) | (((f.x[1] >> (8 * q)) & 0xFFu) << 8) |
-                       (((f.x[2] >> (8 * q)) & 0xFFu) << 16) | (((f.x[3] >> (8 * q)) & 0xFFu) << 24);
-            fb[q][1] = ((f.x[4] >> (8 * q)) & 0xFFu) | (((f.x[5] >> (8 * q)) & 0xFFu) << 8) |
-                       (((f.x[6] >> (8 * q)) & 0xFFu) << 16) | (((f.x[7] >> (8 * q)) & 0xFFu) << 24);
-          } else {
+        for (int cb = 0; cb < 4; ++cb) {
+          if ((nzc[cb] >> ks) & 1u) {
+            const float av = sA32[(cb * kNS + ks) * 64 + lane];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              fb[q][m] = elem16(make_uint2(f.x[2 * m], f.y[2 * m]), q) |
-                         (elem16(make_uint2(f.x[2 * m + 1], f.y[2 * m + 1]), q) << 16);
-              if (kSplit)
-                fbl[q][m] = elem16(make_uint2(f.lx[2 * m], f.ly[2 * m]), q) |
-                            (elem16(make_uint2(f.lx[2 * m + 1], f.ly[2 * m + 1]), q) << 16);
+            for (int h = 0; h < kQW; ++h) {
+              acc[cb][4 * h + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].x, acc[cb][4 * h + 0], 0, 0, 0);
+              acc[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].y, acc[cb][4 * h + 1], 0, 0, 0);
+              acc[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].z, acc[cb][4 * h + 2], 0, 0, 0);
+              acc[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].w, acc[cb][4 * h + 3], 0, 0, 0);
             }
           }
         }
+      }
+    } else {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          if (!((nzc[c] >> ks) & 1u)) continue;
-          const int slot = ((8 * cg + c) * 2 + ks) * 64 + lane;
+      for (int ks = 0; ks < kNS; ++ks) {
+        const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
+        if (!((any >> ks) & 1u)) continue;
+        // one 64-channel group at a time: B fragments of 8 candidates (rows)
+        // x 4 channels, then the MFMAs of every non-zero cell block
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            floatx4& acq = acc[c][q];
-            if (kForm == kFP8S) {
-              const uint2 av = ((const uint2*)sm.A[cb_])[slot];
-              const long A = (long)(((uint64_t)av.y << 32) | av.x);
-              const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
-              acq = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, acq, 0, 0, 0);
-            } else {
-              const uint4 av = sm.A[cb_][slot];
-              const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
-              if (kForm == kF16S) {
-                acq = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
-                                                            __builtin_bit_cast(halfx8, bv), acq, 0, 0, 0);
+        for (int h = 0; h < kQW; ++h) {
+          const int64_t ch = my_ch + 64 * h;
+          uint32_t fb[4][4];   // [q][dword] (16-bit) or [q][0..1] (FP8)
+          uint32_t fbl[4][4];  // low plane (split form)
+          if (kForm == kFP8S) {
+            const uint8_t* spec = (const uint8_t*)a.spec;
+            uint32_t d[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
+              const uint8_t* src = spec + row * C + ch;
+              if (kVec) {
+                d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
               } else {
-                acq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                             __builtin_bit_cast(bf16x8, bv), acq, 0, 0, 0);
-                if (kSplit) {
-                  const uint4 al = sm.A[cb_][kCB * 2 * 64 + slot];
-                  const uint4 bl = make_uint4(fbl[q][0], fbl[q][1], fbl[q][2], fbl[q][3]);
-                  acq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                               __builtin_bit_cast(bf16x8, bl), acq, 0, 0, 0);
-                  acq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
-                                                               __builtin_bit_cast(bf16x8, bv), acq, 0, 0, 0);
+                d[t] = 0u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (ch + e < C) d[t] |= (uint32_t)src[e] << (8 * e);
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              fb[q][0] = ((d[0] >> (8 * q)) & 0xFFu) | (((d[1] >> (8 * q)) & 0xFFu) << 8) |
+                         (((d[2] >> (8 * q)) & 0xFFu) << 16) | (((d[3] >> (8 * q)) & 0xFFu) << 24);
+              fb[q][1] = ((d[4] >> (8 * q)) & 0xFFu) | (((d[5] >> (8 * q)) & 0xFFu) << 8) |
+                         (((d[6] >> (8 * q)) & 0xFFu) << 16) | (((d[7] >> (8 * q)) & 0xFFu) << 24);
+            }
+          } else {
+#pragma unroll
+            for (int plane = 0; plane < (kForm == kBF16Split ? 2 : 1); ++plane) {
+              const uint16_t* spec = (const uint16_t*)(plane ? a.spec_lo : a.spec);
+              uint2 d[8];
+#pragma unroll
+              for (int t = 0; t < 8; ++t) {
+                const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
+                const uint16_t* src = spec + row * C + ch;
+                if (kVec) {
+                  d[t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+                } else {
+                  const uint32_t e0 = (ch + 0 < C) ? src[0] : 0u, e1 = (ch + 1 < C) ? src[1] : 0u;
+                  const uint32_t e2 = (ch + 2 < C) ? src[2] : 0u, e3 = (ch + 3 < C) ? src[3] : 0u;
+                  d[t] = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                  const uint32_t v = elem16(d[2 * m], q) | (elem16(d[2 * m + 1], q) << 16);
+                  if (plane) fbl[q][m] = v; else fb[q][m] = v;
+                }
+            }
+          }
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            if (!((nzc[cb] >> ks) & 1u)) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              floatx4& c = acc[cb][4 * h + q];
+              if (kForm == kFP8S) {
+                const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
+                const long A = (long)(((uint64_t)av.y << 32) | av.x);
+                const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
+              } else {
+                const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
+                const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
+                if (kForm == kF16S) {
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
+                                                            __builtin_bit_cast(halfx8, bv), c, 0, 0, 0);
+                } else {
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                             __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
+                  if (kForm == kBF16Split) {
+                    const uint4 al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
+                    const uint4 bl = make_uint4(fbl[q][0], fbl[q][1], fbl[q][2], fbl[q][3]);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                               __builtin_bit_cast(bf16x8, bl), c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
+                                                               __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
+                  }
                 }
               }
             }
           }
         }
       }
-      finish_block(nx_);
-      stage_store(b + 2, rn2);
-      rb = rn;
-      __syncthreads();
     }
+    __syncthreads();
   }
 
-  // weight sums of each cell: add the four candidate subsets (lanes l,
-  // l + 16, l + 32, l + 48)
-  if (kForm == kF32) {
-    wtA = wsA;
-    wtB = wsB;
-  }
-#pragma unroll
-  for (int o = 16; o < 64; o <<= 1) {
-    wsA += __shfl_xor(wsA, o);
-    wsB += __shfl_xor(wsB, o);
-    wtA += __shfl_xor(wtA, o);
-    wtB += __shfl_xor(wtB, o);
-  }
+  // weight sums of cell block `wave`: reduce the four lanes sharing a cell
+  if (kForm == kF32) wtsum = wsum;  // the FP32 form multiplies the weights as they are
+  wsum += __shfl_xor(wsum, 16);
+  wsum += __shfl_xor(wsum, 32);
+  wtsum += __shfl_xor(wtsum, 16);
+  wtsum += __shfl_xor(wtsum, 32);
   if (lane < 16) {
-    sm.Wt[cbA * 16 + li] = wtA;
-    sm.Wt[cbB * 16 + li] = wtB;
-    if (a.wmap && slab == 0) {
-      const int xa = cell_x(cbA), ya = cell_y(cbA), xb = cell_x(cbB), yb = cell_y(cbB);
-      if (xa < g.nx && ya < g.ny) a.wmap[(int64_t)ya * g.nx + xa] = (float)wsA;
-      if (xb < g.nx && yb < g.ny) a.wmap[(int64_t)yb * g.nx + xb] = (float)wsB;
-    }
+    s_Wt[wave * 16 + lane] = wtsum;
+    if (a.wmap && slab == 0 && my_x < g.nx && my_y < g.ny)
+      a.wmap[(int64_t)my_y * g.nx + my_x] = (float)wsum;
   }
   __syncthreads();
 
-  // V = U / W~ (x the channel scale), NaN where no pair is within R.  The four
-  // cells r = 0..3 of a lane are consecutive in x: one 16-byte store per
-  // channel where the rows allow it (bit 1 of a.vec), else one per cell.
   const float qnan = __builtin_nanf("");
-  const bool vst = (a.vec & 2) != 0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int cb = 8 * cg + c;
-    const int y = ty * kTileY + (cb >> 2) * 4 + (lane >> 4);
-    const int x0 = tx * kTileX + (cb & 3) * 4;
-    if (y >= g.ny || x0 >= g.nx) continue;
-    float inv[4];
-    bool has[4];
+  for (int cb = 0; cb < 4; ++cb) {
+    const int y = ty * kTileY + (cb >> 1) * 4 + (lane >> 4);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const double wt = sm.Wt[cb * 16 + 4 * (lane >> 4) + r];
-      has[r] = wt > 0.0;
-      inv[r] = has[r] ? (float)(1.0 / wt) : 0.f;
-    }
-    float* row = a.cube + (int64_t)y * g.nx + x0;
+      const int x = tx * kTileX + (cb & 1) * 4 + r;
+      if (x >= g.nx || y >= g.ny) continue;
+      const double wt = s_Wt[cb * 16 + 4 * (lane >> 4) + r];
+      const float inv = (wt > 0.0) ? (float)(1.0 / wt) : 0.f;
+      const int64_t cellidx = (int64_t)y * g.nx + x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t ch = my_ch + q;
-      if (ch >= C) continue;
-      const float sc = (kForm == kF16S || kForm == kFP8S) ? a.scale[ch] : 1.f;
-      float v[4];
+      for (int h = 0; h < kQW; ++h)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = has[r] ? acc[c][q][r] * inv[r] * sc : qnan;
-      float* dst = row + ch * G;
-      if (vst && x0 + 3 < g.nx) {
-        *(floatx4*)dst = floatx4{v[0], v[1], v[2], v[3]};
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (x0 + r < g.nx) dst[r] = v[r];
-      }
+        for (int q = 0; q < 4; ++q) {
+          const int64_t ch = my_ch + 64 * h + q;
+          if (ch >= C) continue;
+          float v = acc[cb][4 * h + q][r] * inv;
+          if (kForm == kF16S || kForm == kFP8S) v *= a.scale[ch];
+          a.cube[ch * G + cellidx] = (wt > 0.0) ? v : qnan;
+        }
     }
   }
 }
 
-template <int kForm, int kVec, bool kWide>
-__global__ void __launch_bounds__(kWGThreads, 1) k_gather_mfma(const GatherArgs a) {
+template <int kForm, int kQW, bool kVec>
+__global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   __shared__ GatherSmem sm;
   // XCD-aware order: the hardware deals consecutive workgroups to the eight
   // XCDs in turn; give each XCD a contiguous run of tiles so that tiles that
@@ -719,94 +555,74 @@ __global__ void __launch_bounds__(kWGThreads, 1) k_gather_mfma(const GatherArgs 
   const int local = blockIdx.x - slab * per_slab;
   const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
   if (tile >= a.ntiles) return;
-  gather_tile<kForm, kVec, kWide>(a, tile, slab, sm);
+  gather_tile<kForm, kQW, kVec>(a, tile, slab, sm);
 }
 
-// ---------------------------------------------------------------------------
-// Few channels (C <= 8, FP32) and pair counting: one thread per cell of the
-// 16 x 16 tile (256 threads); with a 512-thread workgroup the two halves take
-// alternate blocks of 256 candidates and their FP64 sums are added.
-// ---------------------------------------------------------------------------
-// stage: nparts x 16 KB of LDS (candidate vectors, then their spectra);
-// with two parts also the 18 KB of the final reduction.
-template <bool kCount>
-__device__ void cells_tile(const GatherArgs& a, int tile, uint2* s_rng, uint32_t* s_pre,
-                           double4* stage, unsigned long long* pair_count) {
-  constexpr int kBlk = 256;
-  const int tid = threadIdx.x;
-  const int part = tid >> 8, nparts = blockDim.x >> 8;
-  const int ci = tid & 255;
+// Few channels (C <= 8) for a 256-thread workgroup: one lane per cell, the
+// four waves take every fourth block of 64 candidates and their FP64 partial
+// sums are added at the end.
+__device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const GridGeom& g = a.g;
-  const int ix = tx * kTileX + (ci & 15), iy = ty * kTileY + (ci >> 4);
+  const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
   const CellVec cell = cell_vec(g, ix, iy);
   const uint32_t total =
-      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre);
+      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
   const int C = (int)a.C;
   const float* spec = (const float*)a.spec;
-  double4* sx = stage + part * kBlk;                                   // [nparts][256] double4
-  float* sspec = (float*)(stage + nparts * kBlk) + part * kBlk * 8;    // [nparts][256][8] float
+  double4* wxyz = (double4*)sm.Araw + wave * kKB;                      // [4][64]
+  float* wspec = (float*)((double4*)sm.Araw + 4 * kKB) + wave * kKB * 8;  // [4][64][8]
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
   double wsum = 0.0;
-  unsigned long long npair = 0;
   uint32_t cur = 0;
-  const uint32_t nblk = (total + kBlk - 1) / kBlk;
-  for (uint32_t b0 = 0; b0 < nblk; b0 += nparts) {
-    const uint32_t blk = b0 + part;
-    const uint32_t q = blk * kBlk + ci;
+  const uint32_t nblk = (total + kKB - 1) / kKB;
+  for (uint32_t b0 = 0; b0 < nblk; b0 += 4) {
+    const uint32_t blk = b0 + wave;
+    const uint32_t q = blk * kKB + lane;
     if (blk < nblk && q < total) {
-      const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
-      sx[ci] = a.xyz[pos];
-      if (!kCount) {
-        const int64_t row = a.perm[pos];
+      const uint32_t pos = cand_pos(q, sm.rng, sm.pre, &cur);
+      wxyz[lane] = a.xyz[pos];
+      const int64_t row = a.perm[pos];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) sspec[ci * 8 + c] = (c < C) ? spec[row * C + c] : 0.f;
-      }
+      for (int c = 0; c < 8; ++c) wspec[lane * 8 + c] = (c < C) ? spec[row * C + c] : 0.f;
     } else {
       const double nan = __builtin_nan("");
-      sx[ci] = make_double4(nan, nan, nan, nan);
+      wxyz[lane] = make_double4(nan, nan, nan, nan);
     }
     __syncthreads();
     if (blk < nblk) {
-      const int kmax = (int)min<uint32_t>(kBlk, total - blk * kBlk);
+      const int kmax = (int)min<uint32_t>(kKB, total - blk * kKB);
       for (int k = 0; k < kmax; ++k) {
-        const double c2 = chord2(cell, sx[k]);
+        const double c2 = chord2(cell, wxyz[k]);
         if (c2 <= a.c2R) {
-          if (kCount) {
-            ++npair;
-          } else {
-            const double w = (double)pair_weight<true>(c2, a.wscale);
-            wsum += w;
+          const double w = exp2(dist2_from_chord2(c2) * a.wscale);
+          wsum += w;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c] += w * (double)sspec[k * 8 + c];
-          }
+          for (int c = 0; c < 8; ++c) acc[c] += w * (double)wspec[k * 8 + c];
         }
       }
     }
     __syncthreads();
   }
-  if (kCount) {
-    for (int off = 32; off > 0; off >>= 1) npair += __shfl_xor(npair, off);
-    if ((tid & 63) == 0 && npair) atomicAdd(pair_count, npair);
-    return;
-  }
-  if (nparts > 1) {
-    double* red = (double*)stage;  // [9][256]
-    if (part == 1) {
+  double* red = (double*)sm.Araw;  // [9][64]
+  for (int w = 1; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) red[c * 256 + ci] = acc[c];
-      red[8 * 256 + ci] = wsum;
+      for (int c = 0; c < 8; ++c) red[c * 64 + lane] = acc[c];
+      red[8 * 64 + lane] = wsum;
     }
     __syncthreads();
-    if (part == 0) {
+    if (wave == 0) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] += red[c * 256 + ci];
-      wsum += red[8 * 256 + ci];
+      for (int c = 0; c < 8; ++c) acc[c] += red[c * 64 + lane];
+      wsum += red[8 * 64 + lane];
     }
+    __syncthreads();
   }
-  if (part != 0 || ix >= g.nx || iy >= g.ny) return;
+  if (wave != 0 || ix >= g.nx || iy >= g.ny) return;
   const int64_t G = (int64_t)g.nx * g.ny;
   const int64_t cellidx = (int64_t)iy * g.nx + ix;
   if (a.wmap) a.wmap[cellidx] = (float)wsum;
@@ -815,129 +631,163 @@ __device__ void cells_tile(const GatherArgs& a, int tile, uint2* s_rng, uint32_t
     if (c < C) a.cube[c * G + cellidx] = (wsum > 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
 }
 
-struct CellsSmem {
-  uint2 rng[kMaxRangesLimit];
-  uint32_t pre[kMaxRangesLimit + 1];
-  double4 stage[2 * 256];
-};
-
-template <bool kCount>
-__global__ void __launch_bounds__(256) k_gather_cells(const GatherArgs a,
-                                                      unsigned long long* __restrict__ pair_count) {
-  __shared__ CellsSmem sm;
-  cells_tile<kCount>(a, (int)blockIdx.x, sm.rng, sm.pre, sm.stage, pair_count);
+// Persistent batch kernel (FP32 spectra).  The item space concatenates the
+// fields' (slab, tile) grids in the host's field order; it is cut into eight
+// contiguous segments, one per XCD (the hardware deals workgroups to the XCDs
+// in turn, so workgroup b starts on XCD b % 8).  A workgroup pops items from
+// its own XCD's segment -- neighbouring tiles of one field, sharing candidate
+// rows in that XCD's L2 -- and, once it is empty, from the others.
+// ctl: [0..7] next item of each segment, [8] item count, [9] segment count.
+__device__ __forceinline__ uint32_t batch_seg_begin(uint32_t total, int x) {
+  return (uint32_t)(((uint64_t)total * (uint32_t)x) / kBatchXcds);
 }
 
-// ---------------------------------------------------------------------------
-// Batch kernel (FP32 spectra, rows read 4 elements at a time, supports below
-// the series bound).  The item space concatenates the fields' (slab, tile)
-// grids in the host's field order; workgroup b takes one item.  With the XCD
-// split, the hardware's round-robin of workgroups over the eight XCDs is
-// undone: XCD x (workgroups b with b % 8 == x) takes the contiguous x-th
-// eighth of the item space, so that neighbouring tiles of one field, which
-// share candidate rows, run behind the same L2.  The dispatcher hands out
-// workgroups as CUs free up, which balances fields of unequal cost.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWGThreads, 1) k_gather_batch(const GatherArgs* __restrict__ fields,
-                                                                const BatchSeg* __restrict__ segs,
-                                                                uint32_t nseg, uint32_t nitems,
-                                                                int xcd_split) {
+__global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
+  const uint32_t total = ctl[8];
+  for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
+}
+
+template <int kQW>
+__global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
+                                                         const BatchSeg* __restrict__ segs,
+                                                         uint32_t* __restrict__ ctl) {
   __shared__ GatherSmem sm;
-  const uint32_t per_xcd = (nitems + kBatchXcds - 1) / kBatchXcds;
-  const uint32_t it = xcd_split ? (blockIdx.x % kBatchXcds) * per_xcd + blockIdx.x / kBatchXcds
-                                : blockIdx.x;
-  if (it >= nitems) return;
-  // the last segment whose base is <= it (values made wave-uniform: scalar
-  // registers, not vector ones)
-  uint32_t lo = 0, hi = nseg - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (__builtin_amdgcn_readfirstlane(segs[mid].base) <= it) lo = mid; else hi = mid - 1;
+  __shared__ uint32_t s_item;
+  const uint32_t total = ctl[8];
+  const uint32_t nseg = ctl[9];
+  const int home = (int)(blockIdx.x % kBatchXcds);
+  int k = 0;  // segments visited so far (thread 0 only)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t it = 0xFFFFFFFFu;
+      while (k < kBatchXcds) {
+        const int x = (home + k) % kBatchXcds;
+        const uint32_t i = atomicAdd(&ctl[x], 1u);
+        if (i < batch_seg_begin(total, x + 1)) { it = i; break; }
+        ++k;
+      }
+      s_item = it;
+    }
+    __syncthreads();
+    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it == 0xFFFFFFFFu) break;
+    // the last segment whose base is <= it
+    uint32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    const uint32_t local = it - sg.base;
+    const uint32_t slab = local / sg.ntiles;
+    const uint32_t tile = local - slab * sg.ntiles;
+    const GatherArgs a = fields[sg.field];
+    if (a.C <= 8) gather_cells_tile_wg(a, (int)tile, sm);
+    else if (a.vec) gather_tile<kF32, kQW, true>(a, (int)tile, (int)slab, sm);
+    else gather_tile<kF32, 1, false>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
+    __syncthreads();
   }
-  const uint32_t base = __builtin_amdgcn_readfirstlane(segs[lo].base);
-  const uint32_t ntiles = __builtin_amdgcn_readfirstlane(segs[lo].ntiles);
-  const uint32_t field = __builtin_amdgcn_readfirstlane(segs[lo].field);
-  const uint32_t local = it - base;
-  const uint32_t slab = local / ntiles;
-  const uint32_t tile = local - slab * ntiles;
-  GatherArgs a;
-  {
-    static_assert(sizeof(GatherArgs) % 4 == 0, "copied word by word");
-    const uint32_t* src = (const uint32_t*)(fields + field);
-    uint32_t* dst = (uint32_t*)&a;
+}
+
+// ---------------------------------------------------------------------------
+// Few channels (C <= 8) and pair counting: one lane per cell of the 8 x 8
+// tile, candidates staged 64 at a time, FP64 accumulation.
+// ---------------------------------------------------------------------------
+template <int kCM, bool kCount>
+__global__ void __launch_bounds__(64) k_gather_cells(
+    const double4* __restrict__ xyz, const uint32_t* __restrict__ perm,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ nranges, int maxr,
+    const float* __restrict__ spectra, int C, GridGeom g, int ntx, double c2R,
+    double wscale, float* __restrict__ cube, float* __restrict__ wmap,
+    unsigned long long* __restrict__ pair_count) {
+  __shared__ uint2 s_rng[kMaxRangesLimit];
+  __shared__ uint32_t s_pre[kMaxRangesLimit + 1];
+  __shared__ double4 s_xyz[kKB];
+  __shared__ float s_spec[kKB][kCM > 0 ? kCM : 1];
+
+  const int tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
+  const CellVec cell = cell_vec(g, ix, iy);
+  const uint32_t total = stage_ranges(ranges + (int64_t)tile * maxr, nranges[tile], s_rng, s_pre);
+
+  double accv[kCM > 0 ? kCM : 1];
 #pragma unroll
-    for (int w = 0; w < (int)(sizeof(GatherArgs) / 4); ++w)
-      dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+  for (int c = 0; c < (kCM > 0 ? kCM : 1); ++c) accv[c] = 0.0;
+  double wsum = 0.0;
+  unsigned long long npair = 0;
+  uint32_t cur = 0;
+  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
+    const uint32_t q = q0 + lane;
+    if (q < total) {
+      const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
+      s_xyz[lane] = xyz[pos];
+      if (!kCount) {
+        const int64_t row = perm[pos];
+#pragma unroll
+        for (int c = 0; c < kCM; ++c) s_spec[lane][c] = (c < C) ? spectra[row * C + c] : 0.f;
+      }
+    } else {
+      const double nan = __builtin_nan("");
+      s_xyz[lane] = make_double4(nan, nan, nan, nan);
+    }
+    __syncthreads();
+    const int kmax = (int)min<uint32_t>(kKB, total - q0);
+    for (int k = 0; k < kmax; ++k) {
+      const double c2 = chord2(cell, s_xyz[k]);
+      if (c2 <= c2R) {
+        if (kCount) {
+          ++npair;
+        } else {
+          const double w = exp2(dist2_from_chord2(c2) * wscale);
+          wsum += w;
+#pragma unroll
+          for (int c = 0; c < kCM; ++c) accv[c] += w * (double)s_spec[k][c];
+        }
+      }
+    }
+    __syncthreads();
   }
-  gather_tile<kF32, 1, false>(a, (int)tile, (int)slab, sm);
+  if (kCount) {
+    for (int off = 32; off > 0; off >>= 1) npair += __shfl_xor(npair, off);
+    if (lane == 0) atomicAdd(pair_count, npair);
+    return;
+  }
+  if (ix >= g.nx || iy >= g.ny) return;
+  const int64_t G = (int64_t)g.nx * g.ny;
+  const int64_t cellidx = (int64_t)iy * g.nx + ix;
+  if (wmap) wmap[cellidx] = (float)wsum;
+#pragma unroll
+  for (int c = 0; c < kCM; ++c)
+    if (c < C) cube[c * G + cellidx] = (wsum > 0.0) ? (float)(accv[c] / wsum) : __builtin_nanf("");
 }
 
-// ---------------------------------------------------------------------------
-// Host side
-// ---------------------------------------------------------------------------
-static bool g_vec_rows(int nx, const float* cube) {
-  return nx % 4 == 0 && (uintptr_t)cube % 16 == 0;
-}
-
-static GatherArgs base_args(const hcg_plan_s* p, int64_t C, float* cube, float* wmap) {
-  GatherArgs a;
-  memset(&a, 0, sizeof(a));  // padding bytes too: the batch compares tables bytewise
-  a.xyz = p->xyz;
-  a.perm = p->perm;
-  a.ranges = p->ranges;
-  a.nranges = p->nranges;
-  a.maxr = p->maxr;
-  a.sentinel = (uint32_t)p->n;
-  a.C = C;
-  a.g = p->grid;
-  a.ntx = p->ntx;
-  a.ntiles = p->ntx * p->nty;
-  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+// Squared chord of the support radius, 4 sin^2(R / 2), and the exponent
+// scale -log2(e) / (2 sigma^2) of the weights.
+static double support_chord2(const hcg_plan_s* p) {
   const double s = std::sin(0.5 * p->support_rad);
-  a.c2R = 4.0 * s * s;
-  a.wscale = -1.4426950408889634 / (2.0 * p->sigma_rad * p->sigma_rad);  // -log2(e) / 2 sigma^2
-  a.cube = cube;
-  a.wmap = wmap;
-  // bit 1: every 4-cell group of a cube row starts 16-byte aligned
-  if (g_vec_rows(p->grid.nx, cube)) a.vec |= 2;
-  return a;
+  return 4.0 * s * s;
+}
+static double weight_scale(const hcg_plan_s* p) {
+  return -1.4426950408889634 / (2.0 * p->sigma_rad * p->sigma_rad);
 }
 
-GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
-                         float* wmap) {
-  GatherArgs a = base_args(p, C, cube, wmap);
-  a.spec = spec;
-  if (C % 4 == 0 && (uintptr_t)spec % 16 == 0) a.vec |= 1;
-  return a;
-}
-
-bool batch_takes(const GatherArgs& a) { return a.C > 8 && (a.vec & 1) && a.c2R < kSeriesMax; }
-
-hcg_status launch_f32(const GatherArgs& a, hipStream_t stream) {
-  if (a.C <= 8) {
-    k_gather_cells<false><<<(unsigned)a.ntiles, 256, 0, stream>>>(a, nullptr);
-    HCG_LAUNCH_CHECK("k_gather_cells");
-    return HCG_OK;
-  }
-  const int64_t slabs = (a.C + kSlab - 1) / kSlab;
-  const int64_t blocks = slabs * a.tiles_per_xcd * 8;
-  if (blocks > INT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
-  const bool wide = a.c2R >= kSeriesMax;
-  if ((a.vec & 1) && !wide) k_gather_mfma<kF32, 1, false><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  else if (a.vec & 1) k_gather_mfma<kF32, 1, true><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  else if (!wide) k_gather_mfma<kF32, 0, false><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  else k_gather_mfma<kF32, 0, true><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  HCG_LAUNCH_CHECK("k_gather_mfma");
-  return HCG_OK;
-}
-
-hcg_status launch_batch(const GatherArgs* fields, const BatchSeg* segs, uint32_t nseg,
-                        uint32_t nitems, int xcd_split, hipStream_t stream) {
-  if (nitems == 0) return HCG_OK;
-  const uint32_t per_xcd = (nitems + kBatchXcds - 1) / kBatchXcds;
-  const uint32_t blocks = xcd_split ? per_xcd * kBatchXcds : nitems;
-  k_gather_batch<<<blocks, kWGThreads, 0, stream>>>(fields, segs, nseg, nitems, xcd_split);
-  HCG_LAUNCH_CHECK("k_gather_batch");
+static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, float* cube,
+                               float* wmap, hipStream_t stream) {
+  const double c2R = support_chord2(p), wscale = weight_scale(p);
+  const unsigned ntiles = (unsigned)(p->ntx * p->nty);
+#define HCG_CELLS(CM)                                                                       \
+  k_gather_cells<CM, false><<<ntiles, 64, 0, stream>>>(p->xyz, p->perm, p->ranges,          \
+                                                       p->nranges, p->maxr, spec, C, p->grid, \
+                                                       p->ntx, c2R, wscale, cube, wmap, nullptr)
+  if (C == 1) HCG_CELLS(1);
+  else if (C == 2) HCG_CELLS(2);
+  else if (C <= 4) HCG_CELLS(4);
+  else HCG_CELLS(8);
+#undef HCG_CELLS
+  HCG_LAUNCH_CHECK("k_gather_cells");
   return HCG_OK;
 }
 
@@ -945,23 +795,89 @@ template <int kForm>
 static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void* spec_lo,
                               const float* scale, int64_t C, float* cube, float* wmap,
                               hipStream_t stream) {
-  GatherArgs a = base_args(p, C, cube, wmap);
+  GatherArgs a;
+  a.xyz = p->xyz;
+  a.sentinel = (uint32_t)p->n;
+  a.perm = p->perm;
+  a.ranges = p->ranges;
+  a.nranges = p->nranges;
+  a.maxr = p->maxr;
   a.spec = spec;
   a.spec_lo = spec_lo;
   a.scale = scale;
+  a.C = C;
+  a.g = p->grid;
+  a.ntx = p->ntx;
+  a.ntiles = p->ntx * p->nty;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.c2R = support_chord2(p);
+  a.wscale = weight_scale(p);
+  a.cube = cube;
+  a.wmap = wmap;
   const size_t esz = (kForm == kF32) ? 4 : (kForm == kFP8S) ? 1 : 2;
   const bool vec = (C % 4 == 0) && ((uintptr_t)spec % (4 * esz) == 0) &&
                    (!spec_lo || (uintptr_t)spec_lo % (4 * esz) == 0);
-  if (vec) a.vec |= 1;
-  const int64_t slabs = (C + kSlab - 1) / kSlab;
+  a.vec = vec ? 1 : 0;
+  // 512-channel slabs (weights computed once per 512 channels) where the
+  // registers allow it, else 256
+  const int qw = (C > 256 && vec && kForm != kBF16Split) ? 2 : 1;
+  const int64_t slab_ch = 256 * qw;
+  const int64_t slabs = (C + slab_ch - 1) / slab_ch;
   const int64_t blocks = slabs * a.tiles_per_xcd * 8;
   if (blocks > INT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
-  const bool wide = a.c2R >= kSeriesMax;
-  if (vec && !wide) k_gather_mfma<kForm, 1, false><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  else if (vec) k_gather_mfma<kForm, 1, true><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  else if (!wide) k_gather_mfma<kForm, 0, false><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
-  else k_gather_mfma<kForm, 0, true><<<(unsigned)blocks, kWGThreads, 0, stream>>>(a);
+  const dim3 grid((unsigned)blocks), block(256);
+  if constexpr (kForm != kBF16Split) {
+    if (qw == 2) {
+      k_gather_mfma<kForm, 2, true><<<grid, block, 0, stream>>>(a);
+      HCG_LAUNCH_CHECK("k_gather_mfma");
+      return HCG_OK;
+    }
+  }
+  if (vec) k_gather_mfma<kForm, 1, true><<<grid, block, 0, stream>>>(a);
+  else k_gather_mfma<kForm, 1, false><<<grid, block, 0, stream>>>(a);
   HCG_LAUNCH_CHECK("k_gather_mfma");
+  return HCG_OK;
+}
+
+GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
+                         float* wmap) {
+  GatherArgs a;
+  memset(&a, 0, sizeof(a));  // padding bytes too: the batch compares tables bytewise
+  a.xyz = p->xyz;
+  a.sentinel = (uint32_t)p->n;
+  a.perm = p->perm;
+  a.ranges = p->ranges;
+  a.nranges = p->nranges;
+  a.maxr = p->maxr;
+  a.spec = spec;
+  a.spec_lo = nullptr;
+  a.scale = nullptr;
+  a.C = C;
+  a.g = p->grid;
+  a.ntx = p->ntx;
+  a.ntiles = p->ntx * p->nty;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.vec = (C % 4 == 0 && (uintptr_t)spec % 16 == 0) ? 1 : 0;
+  a.c2R = support_chord2(p);
+  a.wscale = weight_scale(p);
+  a.cube = cube;
+  a.wmap = wmap;
+  return a;
+}
+
+hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream) {
+  k_batch_reset<<<1, 1, 0, stream>>>(ctl);
+  HCG_LAUNCH_CHECK("k_batch_reset");
+  return HCG_OK;
+}
+
+hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
+                        int nblocks, hipStream_t stream) {
+  if (qw == 2)
+    k_gather_batch<2><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  else
+    k_gather_batch<1><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  HCG_LAUNCH_CHECK("k_gather_batch");
   return HCG_OK;
 }
 
@@ -985,7 +901,8 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
   hipStream_t stream = (hipStream_t)hip_stream;
   switch (dtype) {
     case HCG_F32:
-      return launch_f32(make_f32_args(p, (const float*)spectra, nchan, cube, weights), stream);
+      if (nchan <= 8) return launch_cells(p, (const float*)spectra, (int)nchan, cube, weights, stream);
+      return launch_mfma<kF32>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
     case HCG_BF16:
       return launch_mfma<kBF16>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
     case HCG_BF16_SPLIT:
@@ -1014,8 +931,10 @@ extern "C" hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats,
     ~Free() { (void)hipFree(q); }
   } fr{dcount};
   HCG_HIP(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), stream));
-  const GatherArgs a = base_args(p, 1, nullptr, nullptr);
-  k_gather_cells<true><<<ntiles, 256, 0, stream>>>(a, dcount);
+  k_gather_cells<0, true><<<ntiles, 64, 0, stream>>>(p->xyz, p->perm, p->ranges, p->nranges,
+                                                     p->maxr, nullptr, 0, p->grid, p->ntx,
+                                                     support_chord2(p), 0.0,
+                                                     nullptr, nullptr, dcount);
   HCG_LAUNCH_CHECK("k_gather_cells<count>");
   unsigned long long pairs = 0;
   HCG_HIP(hipMemcpyAsync(&pairs, dcount, sizeof(pairs), hipMemcpyDeviceToHost, stream));

@@ -18,9 +18,9 @@ constexpr double kDeg2Rad = 0.017453292519943295;
 constexpr double kPi = 3.141592653589793;
 constexpr uint64_t kPlanMagic = 0x48434750'4c414e31ull;  // "HCGPLAN1"
 
-// Output-cell tile of the gather kernels: 16 x 16 cells, sixteen 4 x 4 blocks.
-constexpr int kTileX = 16;
-constexpr int kTileY = 16;
+// Output-cell tile of the gather kernels: 8 x 8 cells, four 4 x 4 blocks.
+constexpr int kTileX = 8;
+constexpr int kTileY = 8;
 constexpr int kTileCells = kTileX * kTileY;
 constexpr int kMaxRangesLimit = 1024;
 
@@ -194,7 +194,7 @@ struct GatherArgs {
   int64_t C;
   GridGeom g;
   int ntx, ntiles, tiles_per_xcd;
-  int vec;  // bit 0: spectrum rows read 4 elements at a time; bit 1: 16-byte cube stores
+  int vec;  // rows can be read 4 elements at a time
   double c2R;     // squared chord of the support radius, 4 sin^2(R / 2)
   double wscale;  // -log2(e) / (2 sigma^2): the weight is exp2(d^2 wscale)
   float* cube;
@@ -212,21 +212,18 @@ static_assert(offsetof(GatherArgs, sentinel) == 36 && offsetof(GatherArgs, C) ==
 // Batched gather (gather.hip): one work item = (field, tile, channel slab).
 // Field f owns the items [base, base + ntiles * slabs) of the item space,
 // item base + s * ntiles + t being slab s of tile t.  Segments are listed in
-// increasing base.  The batch kernel reads device arrays of GatherArgs (one
-// per field) and BatchSeg.
+// increasing base.  The persistent kernel reads device arrays of GatherArgs
+// (one per field) and BatchSeg, and a control block of kBatchCtl words.
 struct BatchSeg {
   uint32_t base, ntiles, slabs, field;
 };
 constexpr int kBatchXcds = 8;
+constexpr int kBatchCtl = 16;
 GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
                          float* wmap);
-hcg_status launch_batch(const GatherArgs* fields, const BatchSeg* segs, uint32_t nseg,
-                        uint32_t nitems, int xcd_split, hipStream_t stream);
-// Fields the batch kernel takes (C > 8, rows read 4 elements at a time, a
-// support below the series bound); the others are launched on their own
-// with launch_f32.
-bool batch_takes(const GatherArgs& a);
-hcg_status launch_f32(const GatherArgs& a, hipStream_t stream);
+hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream);
+hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
+                        int nblocks, hipStream_t stream);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
                              uint32_t* perm_out, void* temp, hipStream_t stream);
 

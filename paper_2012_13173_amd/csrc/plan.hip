@@ -574,7 +574,7 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   hcg_opts o = {};
   if (opts) o = *opts;
   if ((o.tile_x && o.tile_x != kTileX) || (o.tile_y && o.tile_y != kTileY))
-    return fail(HCG_E_UNSUPPORTED, "hcg_plan: only 16 x 16 cell tiles are built");
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan: only 8 x 8 cell tiles are built");
   if (o.coarsen || o.chan_tile || o.flags)
     return fail(HCG_E_UNSUPPORTED, "hcg_plan: coarsen, chan_tile and flags must be 0");
   const double sigma = fwhm_deg * kDeg2Rad / (2.0 * std::sqrt(2.0 * std::log(2.0)));

@@ -53,7 +53,7 @@ def test_argument_errors_before_device_work():
     assert lib.hcg_plan(ctypes.byref(h), vp(1), vp(1), 10, ctypes.byref(g), float("nan"), 0.05, None, None) == hcg.HCG_E_ARG
     opts = hcg.OptsC(3000, 0, 0, 0, 0, 0)  # not a power of two
     assert lib.hcg_plan(ctypes.byref(h), vp(1), vp(1), 10, ctypes.byref(g), 0.05, 0.05, ctypes.byref(opts), None) == hcg.HCG_E_ARG
-    opts = hcg.OptsC(0, 8, 8, 0, 0, 0)  # tile shape not built
+    opts = hcg.OptsC(0, 16, 16, 0, 0, 0)  # tile shape not built
     assert lib.hcg_plan(ctypes.byref(h), vp(1), vp(1), 10, ctypes.byref(g), 0.05, 0.05, ctypes.byref(opts), None) == hcg.HCG_E_UNSUPPORTED
     # grid / destroy on handles that are not plans
     assert lib.hcg_grid(None, vp(1), 4, hcg.HCG_F32, None, vp(1), None, None) == hcg.HCG_E_ARG

@@ -1,4 +1,4 @@
-"""GPU tests of the batched form: many maps of uneven size in one
+"""GPU tests of the batched form: many maps of uneven size in one persistent,
 graph-captured launch.  Every field must match the FP64 oracle (1e-5) and the
 single-field hcg_grid of the same plan; replays of the captured graph, with
 eager work and synchronisation between them, must each match the eager
@@ -63,8 +63,6 @@ def test_batch_matches_oracle_and_single_calls():
     torch.cuda.synchronize()
     info = b.info()
     assert info["tuned"] == 1 and info["graph_captured"] == 1 and info["nfields"] == len(ws)
-    # C > 8 with rows read 4 channels at a time run in the batch launch
-    assert info["batch_fields"] == sum(1 for w in ws if w.nchan > 8 and w.nchan % 4 == 0)
     for w, cube, W in zip(ws, cubes, wts):
         V, Wb = cube.cpu().numpy(), W.cpu().numpy()
         Vr, Wr, _ = run_oracle(w)
@@ -111,8 +109,8 @@ def test_graph_replays_pointer_and_channel_changes():
     b.destroy()
 
 
-def test_fixed_configuration_agrees_with_autotuned():
-    chan_tile = 256
+@pytest.mark.parametrize("chan_tile", [256, 512])
+def test_fixed_configurations_agree_with_autotuned(chan_tile):
     ws = _fields()[3:]
     spectra = [w.spectra.to(DEV).contiguous() for w in ws]
     outs = []
@@ -122,11 +120,8 @@ def test_fixed_configuration_agrees_with_autotuned():
         hcg.hcg_grid_batch(b, spectra, cubes, wts)
         torch.cuda.synchronize()
         outs.append([c.cpu().numpy() for c in cubes])
-        info = b.info()
         if ct:
-            assert info["xcd_split"] == 1 and info["cost_order"] == 1
-        else:
-            assert info["tuned"] == 1 and all(t > 0 for t in info["tune_ms"])
+            assert b.info()["chan_slab"] == ct
         b.destroy()
     for a, c in zip(*outs):
         assert np.array_equal(a, c, equal_nan=True)
@@ -140,10 +135,6 @@ def test_batch_errors():
     with pytest.raises(hcg.HcgError) as e:
         hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
                             for w in ws], chan_tile=300)
-    assert e.value.status == hcg.HCG_E_UNSUPPORTED
-    with pytest.raises(hcg.HcgError) as e:
-        hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
-                            for w in ws], chan_tile=512)
     assert e.value.status == hcg.HCG_E_UNSUPPORTED
     bad_lat = ws[1].lat.to(DEV).clone()
     bad_lat[5] = 95.0

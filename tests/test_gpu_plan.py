@@ -136,7 +136,6 @@ def test_plan_keys_sort_csr_and_ranges(name, make):
     cells = np.arange(g.ncells)
     nb = oracle.neighbours(lon, lat, g, w.support_deg, cells)
     ntx = info["ntiles_x"]
-    tw, th = info["tile_x"], info["tile_y"]
     missing = 0
     cand_total = 0
     for t in range(info["ntiles_x"] * info["ntiles_y"]):
@@ -146,8 +145,8 @@ def test_plan_keys_sort_csr_and_ranges(name, make):
             assert a < b and b <= w.n
             mask[a:b] = True
         cand_total += int(mask.sum())
-        for iy in range(ty * th, min(g.ny, ty * th + th)):
-            for ix in range(tx * tw, min(g.nx, tx * tw + tw)):
+        for iy in range(ty * 8, min(g.ny, ty * 8 + 8)):
+            for ix in range(tx * 8, min(g.nx, tx * 8 + 8)):
                 need = inv[nb[iy * g.nx + ix]]
                 missing += int((~mask[need]).sum())
     assert missing == 0
