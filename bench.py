@@ -33,6 +33,25 @@ import synth  # noqa: E402
 
 MFMA_FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+GATHER_SRC = os.path.join(ROOT, "paper_2012_13173_amd", "csrc", "gather.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per FP32 gather launch from the committed counter summary
+    (profiles/traffic_<workload>.json: FETCH_SIZE x its copy-kernel factor +
+    WRITE_SIZE), or None if it was taken on another version of the kernel
+    source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(GATHER_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("gather_source_sha256") != sha:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def log(msg):
@@ -284,7 +303,7 @@ def main():
         plan.destroy()
     flops = 2.0 * stats["pairs"] * w.nchan
     achieved = flops / (grid_avg * 1e-3) / 1e12
-    traffic = None
+    traffic = measured_traffic(w.name)
     out = {
         "metric": "sample*channel updates/s, FP32 gather vs BF16-MFMA at <=1e-3 rel err",
         "value": value,
@@ -307,9 +326,13 @@ def main():
         "pair_updates_per_s": stats["pairs"] * w.nchan / (grid_avg * 1e-3),
         "pairs": stats["pairs"],
         "candidates": stats["candidates"],
-        "roofline": {"kernel": "k_gather_mfma_f32", "bound": "mfma", "achieved": achieved,
+        "roofline": {"kernel": "hcg::k_gather_mfma<0, 2, true> (FP32, 512-channel slabs)",
+                     "bound": "mfma", "achieved": achieved,
                      "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + "
+                                     "WRITE_SIZE, see profiles/)",
+                     "traffic_GBps": (traffic / (grid_avg * 1e-3) / 1e9) if traffic else None,
                      "algorithmic_flops_per_launch": flops},
     }
     if not args.no_cpu_baseline:

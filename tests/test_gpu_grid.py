@@ -43,6 +43,9 @@ def test_channel_counts(nchan):
     dict(lat_c=41.8, nx=30, ny=50, cell_arcmin=1.0, name="cap_boundary"),
     dict(lat_c=75.0, lon_c=300.0, nx=24, ny=24, name="polar_cap"),
     dict(lat_c=-60.0, nx=24, ny=9, name="south"),
+    # support 6.4 deg: the distances beyond the chord series (arcsine branch)
+    dict(fwhm_arcmin=300.0, cell_arcmin=60.0, nx=20, ny=20, pad_arcmin=400.0,
+         name="wide_support"),
 ])
 def test_geometry_cases(kw):
     w = synth.small_cube(n=20_000, nchan=20, **kw)
