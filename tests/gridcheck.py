@@ -59,3 +59,50 @@ def assert_weights_close(W_gpu, W_ref, rtol=1e-6):
     W_ref = np.asarray(W_ref, dtype=np.float64)
     assert np.array_equal(W_gpu == 0, W_ref == 0)
     np.testing.assert_allclose(W_gpu, W_ref, rtol=rtol, atol=0)
+
+
+
+def sample_cells(grid, seed, patches=4, patch=16):
+    """Groups of flat cell indices sampling a full-size map: seeded
+    patch x patch patches, the four corners and the ends of the centre row.
+    Each group is small enough in the sky for the oracle to grid alone."""
+    rng = np.random.default_rng(seed)
+    groups = []
+    for _ in range(patches):
+        x0 = int(rng.integers(0, grid.nx - patch + 1))
+        y0 = int(rng.integers(0, grid.ny - patch + 1))
+        ix, iy = np.meshgrid(np.arange(x0, x0 + patch), np.arange(y0, y0 + patch))
+        groups.append((iy * grid.nx + ix).ravel())
+    ny, nx = grid.ny, grid.nx
+    for c in (0, nx - 1, (ny - 1) * nx, ny * nx - 1, (ny // 2) * nx, (ny // 2) * nx + nx - 1):
+        groups.append(np.array([c]))
+    return groups
+
+
+def sampled_oracle(w, cells):
+    """FP64 oracle values (V [ncells, C], W [ncells]) of a compact group of
+    cells, from the samples in a box around it that holds every sample within
+    the support radius (box margins twice the radius, widened by 1/cos(lat)
+    in longitude)."""
+    import math
+    g = w.grid
+    lon = w.lon.cpu().numpy()
+    lat = w.lat.cpu().numpy()
+    iy, ix = np.divmod(cells, g.nx)
+    clon = g.lon0 + (ix - (g.nx - 1) / 2) * g.dlon
+    clat = g.lat0 + (iy - (g.ny - 1) / 2) * g.dlat
+    m = 2.0 * w.support_deg
+    coslat = math.cos(math.radians(min(89.0, max(abs(clat.min()), abs(clat.max())) + m)))
+    sel = np.nonzero((lat >= clat.min() - m) & (lat <= clat.max() + m)
+                     & (lon >= clon.min() - m / coslat) & (lon <= clon.max() + m / coslat))[0]
+    rows = w.spectra.index_select(0, torch.from_numpy(sel).to(w.spectra.device)).cpu().numpy()
+    V, W, _ = oracle.grid_cells(lon[sel], lat[sel], rows, g, w.fwhm_deg, w.support_deg, cells)
+    return V, W
+
+
+def gather_cells(cube, W, cells):
+    """Values of a device cube [C, ny, nx] and W map at flat cell indices:
+    (V [ncells, C], W [ncells]) as float64 numpy arrays."""
+    idx = torch.from_numpy(np.ascontiguousarray(cells, dtype=np.int64)).to(cube.device)
+    V = cube.reshape(cube.shape[0], -1).index_select(1, idx).T.cpu().numpy().astype(np.float64)
+    return V, W.reshape(-1).index_select(0, idx).cpu().numpy().astype(np.float64)

@@ -1,0 +1,80 @@
+"""GPU parity at the full sizes of the benchmark configurations, in the launch
+configuration bench.py times (hcg_plan + hcg_grid on the whole map), checked
+on sampled cells that the FP64 oracle computes one by one: seeded 16 x 16-cell
+patches, the corners and the ends of the centre row.
+
+* drift scan, 9,120,000 samples x 1,024 channels, 600 x 600 cells: FP32 and
+  every low-precision form;
+* drift scan, 1,976,000 samples x 8,192 channels, 400 x 400 cells: FP32,
+  BF16, FP16 x scale, BF16 hi+lo;
+* large cube, 20,064,000 samples x 1,024 channels, 3000 x 3000 cells: FP32
+  and FP8 E4M3 x scale.
+
+Per-channel relative L2 over the sampled cells, tolerances as in
+test_gpu_precision.py (FP32 1e-5); W map elementwise 1e-6."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_13173_amd as hcg
+import synth
+from tests.gridcheck import (assert_cube_close, assert_weights_close, gather_cells,
+                             sample_cells, sampled_oracle)
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL = {hcg.HCG_F32: 1e-5, hcg.HCG_F16_SCALED: 1e-3, hcg.HCG_BF16_SPLIT: 5e-5,
+       hcg.HCG_BF16: 1e-2, hcg.HCG_FP8E4M3_SCALED: 1e-1}
+NAME = {hcg.HCG_F32: "f32", hcg.HCG_F16_SCALED: "f16_scaled", hcg.HCG_BF16_SPLIT: "bf16_split",
+        hcg.HCG_BF16: "bf16", hcg.HCG_FP8E4M3_SCALED: "fp8e4m3_scaled"}
+
+
+def _check(w, forms, seed):
+    g = w.grid
+    print(f"{w.name}: {w.n} samples x {w.nchan} channels", flush=True)
+    groups = sample_cells(g, seed)
+    cells = np.concatenate(groups)
+    ref = [sampled_oracle(w, c) for c in groups]
+    Vr = np.concatenate([v for v, _ in ref])
+    Wr = np.concatenate([x for _, x in ref])
+    plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
+    cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=DEV)
+    W = torch.empty((g.ny, g.nx), dtype=torch.float32, device=DEV)
+    for form in forms:
+        if form == hcg.HCG_F32:
+            hcg.hcg_grid(plan, w.spectra, cube, W)
+        else:
+            enc, scale = hcg.hcg_quantize(w.spectra, form)
+            hcg.hcg_grid(plan, enc, cube, W, dtype=form, chan_scale=scale)
+            del enc
+        torch.cuda.synchronize()
+        V, Wg = gather_cells(cube, W, cells)
+        e = assert_cube_close(V.T, Vr.T, TOL[form], f"{w.name} {NAME[form]}")
+        assert_weights_close(Wg, Wr)
+        print(f"  {NAME[form]:>15s}: {cells.size} cells, max {e.max():.2e} "
+              f"median {np.median(e):.2e}", flush=True)
+    plan.destroy()
+    del cube, W
+    torch.cuda.empty_cache()
+
+
+def test_drift_scan_1024_full_size():
+    w = synth.drift_scan_1024(device=DEV)
+    _check(w, [hcg.HCG_F32, hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT,
+               hcg.HCG_FP8E4M3_SCALED], seed=11)
+    del w
+    torch.cuda.empty_cache()
+
+
+def test_drift_scan_8192_full_size():
+    w = synth.drift_scan_8192(device=DEV)
+    _check(w, [hcg.HCG_F32, hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT], seed=12)
+    del w
+    torch.cuda.empty_cache()
+
+
+def test_large_cube_full_size():
+    w = synth.drift_scan_large(device=DEV)
+    _check(w, [hcg.HCG_F32, hcg.HCG_FP8E4M3_SCALED], seed=14)
+    del w
+    torch.cuda.empty_cache()
