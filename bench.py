@@ -283,7 +283,8 @@ def main():
         plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
         for name, form in (("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
                            ("bf16_split", hcg.HCG_BF16_SPLIT),
-                           ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED)):
+                           ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED),
+                           ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT)):
             enc, scale = hcg.hcg_quantize(w.spectra, form)
             out = torch.empty_like(cube)
             hcg.hcg_grid(plan, enc, out, dtype=form, chan_scale=scale)

@@ -69,7 +69,12 @@ typedef enum {
  *   HCG_F16_SCALED      float16 [n][C] holding x / scale[c]; FP16 weights;
  *                       V is multiplied back by scale[c].
  *   HCG_FP8E4M3_SCALED  OCP FP8 E4M3 [n][C] holding x / scale[c]; FP8 E4M3
- *                       weights; V is multiplied back by scale[c].
+ *                       weights (of 256 w, inside E4M3's normal range); V
+ *                       is multiplied back by scale[c].
+ *   HCG_FP8E4M3_SPLIT   two FP8 E4M3 planes [2][n][C] with one scale per
+ *                       channel: hi = e4m3(x / scale[c]) then lo =
+ *                       e4m3(x / scale[c] - hi); weights split the same way;
+ *                       three products per pair (hi.hi + hi.lo + lo.hi).
  * hcg_quantize produces these encodings (with power-of-two scales) from
  * float32 spectra. */
 typedef enum {
@@ -77,7 +82,8 @@ typedef enum {
   HCG_BF16 = 1,
   HCG_BF16_SPLIT = 2,
   HCG_F16_SCALED = 3,
-  HCG_FP8E4M3_SCALED = 4
+  HCG_FP8E4M3_SCALED = 4,
+  HCG_FP8E4M3_SPLIT = 5
 } hcg_dtype;
 
 /* Linear lon/lat target grid (degrees).  nx, ny >= 1; dlon, dlat finite and
@@ -132,7 +138,7 @@ hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_de
  *
  *   spectra     device [n][nchan] in the sample order given to hcg_plan,
  *               channel-fastest, in the storage type of dtype (two planes
- *               for HCG_BF16_SPLIT).  Values must be finite: a non-finite
+ *               for the split dtypes).  Values must be finite: a non-finite
  *               value reaches every cell of the 4 x 4 cell block that
  *               shares its matrix-core step, not only the cells within R.
  *   nchan       >= 1.
@@ -158,9 +164,11 @@ hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dty
  * hcg_grid (the per-channel scaling of the precision forms).
  *
  *   in          device float [n][nchan].
- *   dtype       HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED or HCG_FP8E4M3_SCALED.
- *   out         device buffer: 2 n nchan bytes (BF16, F16), 4 n nchan bytes
- *               (BF16 split: hi plane then lo plane), n nchan bytes (FP8).
+ *   dtype       HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED, HCG_FP8E4M3_SCALED
+ *               or HCG_FP8E4M3_SPLIT.
+ *   out         device buffer: 2 n nchan bytes (BF16, F16, FP8 split: hi
+ *               plane then lo plane), 4 n nchan bytes (BF16 split: hi plane
+ *               then lo plane), n nchan bytes (FP8).
  *   chan_scale  device float [nchan], written for the scaled forms:
  *               scale[c] = 2^ceil(log2(max_n |x[n][c]| / top)) with top =
  *               2^14 (FP16) or 448 (the largest E4M3 value); 1 for an

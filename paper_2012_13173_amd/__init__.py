@@ -21,7 +21,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhcg.so")
 
 HCG_OK, HCG_E_ARG, HCG_E_NOMEM, HCG_E_DEVICE, HCG_E_UNSUPPORTED, HCG_E_STATE = range(6)
-HCG_F32, HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED, HCG_FP8E4M3_SCALED = range(5)
+(HCG_F32, HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED, HCG_FP8E4M3_SCALED,
+ HCG_FP8E4M3_SPLIT) = range(6)
 HCG_ARR_KEYS, HCG_ARR_PERM, HCG_ARR_RING_CSR, HCG_ARR_TILE_NRANGES, HCG_ARR_TILE_RANGES = range(5)
 STATUS_NAMES = {0: "HCG_OK", 1: "HCG_E_ARG", 2: "HCG_E_NOMEM", 3: "HCG_E_DEVICE",
                 4: "HCG_E_UNSUPPORTED", 5: "HCG_E_STATE"}
@@ -204,12 +205,12 @@ def hcg_plan(lon: torch.Tensor, lat: torch.Tensor, grid, fwhm_deg: float, suppor
 # storage dtype of each form's spectra and the shape prefix of its buffer
 _FORM_STORAGE = {HCG_F32: (torch.float32, ()), HCG_BF16: (torch.bfloat16, ()),
                  HCG_BF16_SPLIT: (torch.bfloat16, (2,)), HCG_F16_SCALED: (torch.float16, ()),
-                 HCG_FP8E4M3_SCALED: (torch.uint8, ())}
+                 HCG_FP8E4M3_SCALED: (torch.uint8, ()), HCG_FP8E4M3_SPLIT: (torch.uint8, (2,))}
 
 
 def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None,
              dtype: int = HCG_F32, chan_scale=None, stream=None) -> None:
-    """Grids ``spectra`` ([n, C], or [2, n, C] for the split form) into
+    """Grids ``spectra`` ([n, C], or [2, n, C] for the split forms) into
     ``cube`` [C, ny, nx] (and ``weights`` [ny, nx])."""
     sdt, prefix = _FORM_STORAGE[dtype]
     if spectra.dim() != 2 + len(prefix) or tuple(spectra.shape[:len(prefix)]) != prefix:
@@ -235,7 +236,7 @@ def hcg_quantize(spectra: torch.Tensor, dtype: int, stream=None):
     n, C = (int(x) for x in spectra.shape)
     sdt, prefix = _FORM_STORAGE[dtype]
     out = torch.empty(prefix + (n, C), dtype=sdt, device=spectra.device)
-    scaled = dtype in (HCG_F16_SCALED, HCG_FP8E4M3_SCALED)
+    scaled = dtype in (HCG_F16_SCALED, HCG_FP8E4M3_SCALED, HCG_FP8E4M3_SPLIT)
     scale = torch.empty(C, dtype=torch.float32, device=spectra.device) if scaled else None
     st = load().hcg_quantize(_dptr(spectra, torch.float32, "spectra"), n, C, int(dtype),
                              ctypes.c_void_p(out.data_ptr()),

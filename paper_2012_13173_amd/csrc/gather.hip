@@ -157,7 +157,15 @@ __device__ __forceinline__ uint32_t cand_pos(uint32_t q, const uint2* s_rng, con
 // ---------------------------------------------------------------------------
 // Storage forms of the spectra and of the weights on the matrix cores.
 // ---------------------------------------------------------------------------
-enum Form : int { kF32 = 0, kBF16 = 1, kBF16Split = 2, kF16S = 3, kFP8S = 4 };
+enum Form : int { kF32 = 0, kBF16 = 1, kBF16Split = 2, kF16S = 3, kFP8S = 4, kFP8Split = 5 };
+
+constexpr bool is_fp8(int f) { return f == kFP8S || f == kFP8Split; }
+constexpr bool is_split(int f) { return f == kBF16Split || f == kFP8Split; }
+
+// The FP8 forms encode 256 w: the weights (0.011 .. 1 at a 3 sigma support)
+// then sit in E4M3's normal range, where the relative rounding step is 2^-3
+// everywhere.  The factor is a power of two and cancels in U / W~.
+constexpr float kW8Scale = 256.f;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
@@ -196,17 +204,19 @@ template <>
 struct FormTraits<kF16S> { static constexpr int kK = 32; };
 template <>
 struct FormTraits<kFP8S> { static constexpr int kK = 32; };
+template <>
+struct FormTraits<kFP8Split> { static constexpr int kK = 32; };
 
 template <int kForm>
 __device__ __forceinline__ uint32_t enc_w(float w) {
   if (kForm == kF16S) return f32_to_f16(w);
-  if (kForm == kFP8S) return f32_to_e4m3(w);
+  if (is_fp8(kForm)) return f32_to_e4m3(w * kW8Scale);
   return f32_to_bf16(w);
 }
 template <int kForm>
 __device__ __forceinline__ float dec_w(uint32_t c) {
   if (kForm == kF16S) return f16_to_f32(c);
-  if (kForm == kFP8S) return e4m3_to_f32(c);
+  if (is_fp8(kForm)) return e4m3_to_f32(c);  // in units of 1 / kW8Scale
   return bf16_to_f32(c);
 }
 
@@ -332,12 +342,16 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                 if (kForm == kBF16Split) {
                   l = f32_to_bf16(wf - dec_w<kForm>(h));
                   eff += (double)bf16_to_f32(l);
+                } else if (kForm == kFP8Split) {
+                  l = f32_to_e4m3(wf * kW8Scale - dec_w<kForm>(h));
+                  eff += (double)e4m3_to_f32(l);
                 }
                 wsum += (double)wf;
                 wtsum += eff;
               }
-              if (kForm == kFP8S) {
+              if (is_fp8(kForm)) {
                 hw[t >> 2] |= h << (8 * (t & 3));
+                if (kForm == kFP8Split) lw[t >> 2] |= l << (8 * (t & 3));
               } else {
                 hw[t >> 1] |= h << (16 * (t & 1));
                 if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
@@ -345,9 +359,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
             }
           }
           uint32_t any;
-          if (kForm == kFP8S) {
+          if (is_fp8(kForm)) {
             sA8[(wave * kNS + ks) * 64 + lane] = make_uint2(hw[0], hw[1]);
             any = hw[0] | hw[1];
+            if (kForm == kFP8Split) {
+              sA8[(4 * kNS + wave * kNS + ks) * 64 + lane] = make_uint2(lw[0], lw[1]);
+              any |= lw[0] | lw[1];
+            }
           } else {
             sA16[(wave * kNS + ks) * 64 + lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             any = hw[0] | hw[1] | hw[2] | hw[3];
@@ -419,28 +437,40 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           const int64_t ch = my_ch + 64 * h;
           uint32_t fb[4][4];   // [q][dword] (16-bit) or [q][0..1] (FP8)
           uint32_t fbl[4][4];  // low plane (split form)
-          if (kForm == kFP8S) {
-            const uint8_t* spec = (const uint8_t*)a.spec;
-            uint32_t d[8];
+          if (is_fp8(kForm)) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
-              const uint8_t* src = spec + row * C + ch;
-              if (kVec) {
-                d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
-              } else {
-                d[t] = 0u;
+            for (int plane = 0; plane < (kForm == kFP8Split ? 2 : 1); ++plane) {
+              const uint8_t* spec = (const uint8_t*)(plane ? a.spec_lo : a.spec);
+              uint32_t d[8];
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                  if (ch + e < C) d[t] |= (uint32_t)src[e] << (8 * e);
+              for (int t = 0; t < 8; ++t) {
+                const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
+                const uint8_t* src = spec + row * C + ch;
+                if (kVec) {
+                  d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
+                } else {
+                  d[t] = 0u;
+#pragma unroll
+                  for (int e = 0; e < 4; ++e)
+                    if (ch + e < C) d[t] |= (uint32_t)src[e] << (8 * e);
+                }
               }
-            }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              fb[q][0] = ((d[0] >> (8 * q)) & 0xFFu) | (((d[1] >> (8 * q)) & 0xFFu) << 8) |
-                         (((d[2] >> (8 * q)) & 0xFFu) << 16) | (((d[3] >> (8 * q)) & 0xFFu) << 24);
-              fb[q][1] = ((d[4] >> (8 * q)) & 0xFFu) | (((d[5] >> (8 * q)) & 0xFFu) << 8) |
-                         (((d[6] >> (8 * q)) & 0xFFu) << 16) | (((d[7] >> (8 * q)) & 0xFFu) << 24);
+              for (int q = 0; q < 4; ++q) {
+                const uint32_t v0 = ((d[0] >> (8 * q)) & 0xFFu) | (((d[1] >> (8 * q)) & 0xFFu) << 8) |
+                                    (((d[2] >> (8 * q)) & 0xFFu) << 16) |
+                                    (((d[3] >> (8 * q)) & 0xFFu) << 24);
+                const uint32_t v1 = ((d[4] >> (8 * q)) & 0xFFu) | (((d[5] >> (8 * q)) & 0xFFu) << 8) |
+                                    (((d[6] >> (8 * q)) & 0xFFu) << 16) |
+                                    (((d[7] >> (8 * q)) & 0xFFu) << 24);
+                if (plane) {
+                  fbl[q][0] = v0;
+                  fbl[q][1] = v1;
+                } else {
+                  fb[q][0] = v0;
+                  fb[q][1] = v1;
+                }
+              }
             }
           } else {
 #pragma unroll
@@ -474,11 +504,19 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               floatx4& c = acc[cb][4 * h + q];
-              if (kForm == kFP8S) {
+              if (is_fp8(kForm)) {
                 const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
                 const long A = (long)(((uint64_t)av.y << 32) | av.x);
                 const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
+                if (kForm == kFP8Split) {
+                  // W_hi S_lo + W_lo S_hi (the W_lo S_lo term is below the budget)
+                  const uint2 al = sA8[(4 * kNS + cb * kNS + ks) * 64 + lane];
+                  const long Al = (long)(((uint64_t)al.y << 32) | al.x);
+                  const long Bl = (long)(((uint64_t)fbl[q][1] << 32) | fbl[q][0]);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, Bl, c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
+                }
               } else {
                 const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
                 const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
@@ -537,7 +575,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           const int64_t ch = my_ch + 64 * h + q;
           if (ch >= C) continue;
           float v = acc[cb][4 * h + q][r] * inv;
-          if (kForm == kF16S || kForm == kFP8S) v *= a.scale[ch];
+          if (kForm == kF16S || is_fp8(kForm)) v *= a.scale[ch];
           a.cube[ch * G + cellidx] = (wt > 0.0) ? v : qnan;
         }
     }
@@ -814,7 +852,7 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   a.wscale = weight_scale(p);
   a.cube = cube;
   a.wmap = wmap;
-  const size_t esz = (kForm == kF32) ? 4 : (kForm == kFP8S) ? 1 : 2;
+  const size_t esz = (kForm == kF32) ? 4 : is_fp8(kForm) ? 1 : 2;
   const bool vec = (C % 4 == 0) && ((uintptr_t)spec % (4 * esz) == 0) &&
                    (!spec_lo || (uintptr_t)spec_lo % (4 * esz) == 0);
   a.vec = vec ? 1 : 0;
@@ -892,8 +930,9 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
   if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid: not a live plan");
   if (!spectra || !cube) return fail(HCG_E_ARG, "hcg_grid: spectra and cube must not be NULL");
   if (nchan < 1) return fail(HCG_E_ARG, "hcg_grid: nchan must be >= 1");
-  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED);
-  if (dtype < HCG_F32 || dtype > HCG_FP8E4M3_SCALED)
+  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED ||
+                       dtype == HCG_FP8E4M3_SPLIT);
+  if (dtype < HCG_F32 || dtype > HCG_FP8E4M3_SPLIT)
     return fail(HCG_E_UNSUPPORTED, "hcg_grid: unknown dtype %d", (int)dtype);
   if (scaled && !chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale is required for this dtype");
   if (!scaled && chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale must be NULL for this dtype");
@@ -913,6 +952,9 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
       return launch_mfma<kF16S>(p, spectra, nullptr, chan_scale, nchan, cube, weights, stream);
     case HCG_FP8E4M3_SCALED:
       return launch_mfma<kFP8S>(p, spectra, nullptr, chan_scale, nchan, cube, weights, stream);
+    case HCG_FP8E4M3_SPLIT:
+      return launch_mfma<kFP8Split>(p, spectra, (const char*)spectra + (size_t)p->n * nchan,
+                                    chan_scale, nchan, cube, weights, stream);
   }
   return fail(HCG_E_UNSUPPORTED, "hcg_grid: dtype %d", (int)dtype);
 }

@@ -1,6 +1,7 @@
 // Encoders for the low-precision storage forms of hcg_grid: float32 spectra
-// [n][C] -> BF16, BF16 hi + lo planes, FP16 or OCP FP8 E4M3 with one
-// power-of-two scale per channel (so that scaling and unscaling are exact).
+// [n][C] -> BF16, BF16 hi + lo planes, FP16, OCP FP8 E4M3 or E4M3 hi + lo
+// planes with one power-of-two scale per channel (so that scaling and
+// unscaling are exact).
 #include <cmath>
 
 #include "hcg_internal.h"
@@ -50,6 +51,11 @@ __global__ void __launch_bounds__(256) k_encode(const float* __restrict__ in, in
       ((uint16_t*)out)[total + i] = (uint16_t)f32_to_bf16(x - bf16_to_f32(hi));
     } else if (kDtype == HCG_F16_SCALED) {
       ((uint16_t*)out)[i] = (uint16_t)f32_to_f16(x / scale[i % C]);
+    } else if (kDtype == HCG_FP8E4M3_SPLIT) {
+      const float y = x / scale[i % C];
+      const uint32_t hi = f32_to_e4m3(y);
+      ((uint8_t*)out)[i] = (uint8_t)hi;
+      ((uint8_t*)out)[total + i] = (uint8_t)f32_to_e4m3(y - e4m3_to_f32(hi));
     } else {
       ((uint8_t*)out)[i] = (uint8_t)f32_to_e4m3(x / scale[i % C]);
     }
@@ -64,7 +70,8 @@ extern "C" hcg_status hcg_quantize(const float* in, int64_t n, int64_t nchan, hc
                                    void* out, float* chan_scale, void* hip_stream) {
   if (n < 0 || nchan < 1) return fail(HCG_E_ARG, "hcg_quantize: bad shape");
   if (n > 0 && (!in || !out)) return fail(HCG_E_ARG, "hcg_quantize: NULL pointer");
-  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED);
+  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED ||
+                       dtype == HCG_FP8E4M3_SPLIT);
   if (dtype != HCG_BF16 && dtype != HCG_BF16_SPLIT && !scaled)
     return fail(HCG_E_ARG, "hcg_quantize: dtype %d is not a low-precision form", (int)dtype);
   if (scaled && !chan_scale) return fail(HCG_E_ARG, "hcg_quantize: chan_scale is required");
@@ -97,6 +104,9 @@ extern "C" hcg_status hcg_quantize(const float* in, int64_t n, int64_t nchan, hc
       break;
     case HCG_F16_SCALED:
       k_encode<HCG_F16_SCALED><<<blocks, 256, 0, stream>>>(in, total, nchan, chan_scale, out);
+      break;
+    case HCG_FP8E4M3_SPLIT:
+      k_encode<HCG_FP8E4M3_SPLIT><<<blocks, 256, 0, stream>>>(in, total, nchan, chan_scale, out);
       break;
     default:
       k_encode<HCG_FP8E4M3_SCALED><<<blocks, 256, 0, stream>>>(in, total, nchan, chan_scale, out);

@@ -7,8 +7,8 @@ patches, the corners and the ends of the centre row.
   every low-precision form;
 * drift scan, 1,976,000 samples x 8,192 channels, 400 x 400 cells: FP32,
   BF16, FP16 x scale, BF16 hi+lo;
-* large cube, 20,064,000 samples x 1,024 channels, 3000 x 3000 cells: FP32
-  and FP8 E4M3 x scale.
+* large cube, 20,064,000 samples x 1,024 channels, 3000 x 3000 cells: FP32,
+  FP8 E4M3 x scale and FP8 E4M3 hi+lo x scale.
 
 Per-channel relative L2 over the sampled cells, tolerances as in
 test_gpu_precision.py (FP32 1e-5); W map elementwise 1e-6."""
@@ -24,9 +24,10 @@ from tests.gridcheck import (assert_cube_close, assert_weights_close, gather_cel
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 TOL = {hcg.HCG_F32: 1e-5, hcg.HCG_F16_SCALED: 1e-3, hcg.HCG_BF16_SPLIT: 5e-5,
-       hcg.HCG_BF16: 1e-2, hcg.HCG_FP8E4M3_SCALED: 1e-1}
+       hcg.HCG_BF16: 1e-2, hcg.HCG_FP8E4M3_SCALED: 1e-1, hcg.HCG_FP8E4M3_SPLIT: 1e-2}
 NAME = {hcg.HCG_F32: "f32", hcg.HCG_F16_SCALED: "f16_scaled", hcg.HCG_BF16_SPLIT: "bf16_split",
-        hcg.HCG_BF16: "bf16", hcg.HCG_FP8E4M3_SCALED: "fp8e4m3_scaled"}
+        hcg.HCG_BF16: "bf16", hcg.HCG_FP8E4M3_SCALED: "fp8e4m3_scaled",
+        hcg.HCG_FP8E4M3_SPLIT: "fp8e4m3_split"}
 
 
 def _check(w, forms, seed):
@@ -61,7 +62,7 @@ def _check(w, forms, seed):
 def test_drift_scan_1024_full_size():
     w = synth.drift_scan_1024(device=DEV)
     _check(w, [hcg.HCG_F32, hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT,
-               hcg.HCG_FP8E4M3_SCALED], seed=11)
+               hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=11)
     del w
     torch.cuda.empty_cache()
 
@@ -75,6 +76,6 @@ def test_drift_scan_8192_full_size():
 
 def test_large_cube_full_size():
     w = synth.drift_scan_large(device=DEV)
-    _check(w, [hcg.HCG_F32, hcg.HCG_FP8E4M3_SCALED], seed=14)
+    _check(w, [hcg.HCG_F32, hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=14)
     del w
     torch.cuda.empty_cache()

@@ -4,7 +4,8 @@ FP64 oracle on the FP32 master spectra, and exactness of hcg_quantize.
 Error budgets follow from the element precision (unit roundoff u, error of a
 weighted mean ~ u/sqrt(3) per rounded factor, two rounded factors per term):
 FP16 x FP16 (u = 2^-11) ~ 4e-4 -> 1e-3; BF16 hi+lo (u ~ 2^-16) ~ 1e-5 ->
-5e-5; plain BF16 (u = 2^-8) ~ 3e-3 and FP8 E4M3 (u = 2^-4) ~ 4e-2 are
+5e-5; FP8 E4M3 hi+lo (u ~ 2^-8, plus the dropped lo.lo product) ~ 2e-3 ->
+1e-2; plain BF16 (u = 2^-8) ~ 3e-3 and FP8 E4M3 (u = 2^-4) ~ 4e-2 are
 reported against looser bounds (1e-2, 1e-1): on noise channels they cannot
 meet 1e-3 / 1e-2."""
 import numpy as np
@@ -24,6 +25,7 @@ FORMS = {
     "bf16_split": (hcg.HCG_BF16_SPLIT, 5e-5),
     "bf16": (hcg.HCG_BF16, 1e-2),
     "fp8e4m3_scaled": (hcg.HCG_FP8E4M3_SCALED, 1e-1),
+    "fp8e4m3_split": (hcg.HCG_FP8E4M3_SPLIT, 1e-2),
 }
 
 
@@ -92,6 +94,15 @@ def test_quantize_matches_reference_roundings():
         scaled_max = (x / scale).abs().amax(0)
         nz = torch.from_numpy(amax > 0).to(DEV)
         assert bool(((scaled_max[nz] <= top) & (scaled_max[nz] > top / 2)).all())
+    # FP8 hi + lo: the scale of the single FP8 form, hi its encoding, lo the
+    # encoding of the remainder
+    q8, s8 = hcg.hcg_quantize(x, hcg.HCG_FP8E4M3_SCALED)
+    sp8, ss8 = hcg.hcg_quantize(x, hcg.HCG_FP8E4M3_SPLIT)
+    assert torch.equal(ss8, s8) and tuple(sp8.shape) == (2, n, C)
+    assert torch.equal(sp8[0], q8)
+    y = x / ss8
+    lo = (y - y.to(torch.float8_e4m3fn).float()).to(torch.float8_e4m3fn)
+    assert torch.equal(sp8[1], lo.view(torch.uint8))
 
 
 def test_grid_rejects_scale_mismatch():
