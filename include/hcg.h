@@ -180,6 +180,48 @@ hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dty
 hcg_status hcg_quantize(const float* in, int64_t n, int64_t nchan, hcg_dtype dtype, void* out,
                         float* chan_scale, void* hip_stream);
 
+/*
+ * Plan-ordered spectra.  The gather reads each candidate sample's spectrum
+ * through the plan's permutation; a low-precision encoding can instead be
+ * written once in the plan's sorted order, as the paper's pre-ordering
+ * (Section 3.3, step I) reorders the raw samples, data and coordinates, by
+ * pixel.  Layout of one plane, with Cp = nchan rounded up to a multiple of
+ * 16: element (sorted position p, channel c) at ((p / 8) Cp + c) 8 + p % 8,
+ * for p < 8 ceil(n / 8) and c < Cp (positions >= n and channels >= nchan
+ * hold zero); the split forms store the hi plane, then the lo plane.  Eight
+ * consecutive sorted samples of one channel are then one 16-byte (16-bit
+ * forms) or 8-byte (FP8) operand of the matrix-core step, and 16 channels
+ * of a group one aligned 256- or 128-byte block.
+ *
+ * hcg_packed_bytes -- bytes of the plan-ordered encoding of nchan channels in
+ *   dtype (a low-precision form): planes x 8 ceil(n / 8) x Cp x element
+ *   size.  Errors: HCG_E_ARG (NULL, nchan < 1, dtype HCG_F32 or unknown),
+ *   HCG_E_STATE.
+ *
+ * hcg_quantize_packed -- encode float32 spectra for a low-precision form, in
+ *   the plan's sorted order.
+ *   in          device float [n][nchan] in the sample order given to
+ *               hcg_plan (n = the plan's sample count).
+ *   out         device buffer of hcg_packed_bytes bytes, 16-byte aligned
+ *               (8-byte for the FP8 forms).
+ *   chan_scale  as for hcg_quantize (same scales, same element codes).
+ *   Asynchronous on hip_stream.  Errors: HCG_E_ARG (NULL pointer, nchan < 1,
+ *   dtype not a low-precision form, chan_scale missing or given wrongly,
+ *   misaligned out), HCG_E_STATE, HCG_E_DEVICE.
+ *
+ * hcg_grid_packed -- hcg_grid on plan-ordered spectra of the same plan
+ *   (from hcg_quantize_packed or written in the same layout); the result is
+ *   the one hcg_grid gives for the input-order encoding, up to the order of
+ *   the FP32 accumulation.  Arguments and errors as for hcg_grid; dtype must
+ *   be a low-precision form and packed suitably aligned (HCG_E_ARG).
+ */
+hcg_status hcg_packed_bytes(hcg_plan_t plan, int64_t nchan, hcg_dtype dtype, int64_t* bytes);
+hcg_status hcg_quantize_packed(hcg_plan_t plan, const float* in, int64_t nchan, hcg_dtype dtype,
+                               void* out, float* chan_scale, void* hip_stream);
+hcg_status hcg_grid_packed(hcg_plan_t plan, const void* packed, int64_t nchan, hcg_dtype dtype,
+                           const float* chan_scale, float* cube, float* weights,
+                           void* hip_stream);
+
 /* hcg_destroy -- wait for the device, then free the plan.  NULL is a no-op
  * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE. */
 hcg_status hcg_destroy(hcg_plan_t plan);

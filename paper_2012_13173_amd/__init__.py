@@ -13,6 +13,7 @@ Names mirror the C ABI: ``hcg_plan``, ``hcg_grid``, ``hcg_destroy``,
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import torch
@@ -82,7 +83,8 @@ class BatchInfoC(ctypes.Structure):
 EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_plan_info",
             "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
             "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
-            "hcg_destroy_batch", "hcg_get_batch_info"]
+            "hcg_destroy_batch", "hcg_get_batch_info", "hcg_quantize_packed", "hcg_grid_packed",
+            "hcg_packed_bytes"]
 
 _lib = None
 
@@ -109,6 +111,9 @@ def load(path: str = LIB_PATH):
     lib.hcg_ang2pix.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.hcg_sort_keys.argtypes = [vp, i64, i32, vp, vp, vp]
     lib.hcg_quantize.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp, vp]
+    lib.hcg_quantize_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp]
+    lib.hcg_grid_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    lib.hcg_packed_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(i64)]
     lib.hcg_plan_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(FieldDescC),
                                    ctypes.POINTER(OptsC), vp]
     lib.hcg_grid_batch.argtypes = [vp, ctypes.POINTER(FieldDataC), vp]
@@ -243,6 +248,61 @@ def hcg_quantize(spectra: torch.Tensor, dtype: int, stream=None):
                              _dptr(scale, torch.float32, "chan_scale"), _stream(stream))
     _check(st, "hcg_quantize")
     return out, scale
+
+
+def _packed_shape(plan: Plan, C: int, dtype: int):
+    sdt, prefix = _FORM_STORAGE[dtype]
+    if dtype == HCG_F32:
+        raise ValueError("plan-ordered spectra are a low-precision form")
+    n = int(plan.info()["n"])
+    planes = prefix[0] if prefix else 1
+    nbytes = ctypes.c_int64()
+    _check(load().hcg_packed_bytes(plan.handle, C, int(dtype), ctypes.byref(nbytes)),
+           "hcg_packed_bytes")
+    shape = (planes, (n + 7) // 8, (C + 15) // 16 * 16, 8)
+    assert nbytes.value == math.prod(shape) * torch.empty((), dtype=sdt).element_size()
+    return sdt, shape, n
+
+
+def hcg_quantize_packed(plan: Plan, spectra: torch.Tensor, dtype: int, stream=None):
+    """Encodes float32 spectra [n, C] (in the sample order given to the plan)
+    for a low-precision form in the plan's sorted order: [planes, ceil(n/8), Cp,
+    8] with Cp = C rounded up to 16, the 8 sorted samples of a group
+    contiguous per channel (zero padding past n and C).
+
+    Returns (encoded tensor, chan_scale or None)."""
+    n, C = (int(x) for x in spectra.shape)
+    sdt, shape, pn = _packed_shape(plan, C, dtype)
+    if n != pn:
+        raise ValueError(f"spectra has {n} rows, the plan {pn} samples")
+    out = torch.empty(shape, dtype=sdt, device=spectra.device)
+    scaled = dtype in (HCG_F16_SCALED, HCG_FP8E4M3_SCALED, HCG_FP8E4M3_SPLIT)
+    scale = torch.empty(C, dtype=torch.float32, device=spectra.device) if scaled else None
+    st = load().hcg_quantize_packed(plan.handle, _dptr(spectra, torch.float32, "spectra"), C,
+                                    int(dtype), ctypes.c_void_p(out.data_ptr()),
+                                    _dptr(scale, torch.float32, "chan_scale"), _stream(stream))
+    _check(st, "hcg_quantize_packed")
+    return out, scale
+
+
+def hcg_grid_packed(plan: Plan, packed: torch.Tensor, cube: torch.Tensor, weights=None,
+                    dtype: int = HCG_F16_SCALED, chan_scale=None, stream=None) -> None:
+    """Grids plan-ordered spectra (from ``hcg_quantize_packed``) into ``cube``
+    [C, ny, nx] (and ``weights`` [ny, nx])."""
+    C = int(cube.shape[0])
+    sdt, shape, _ = _packed_shape(plan, max(C, 1), dtype)
+    if tuple(packed.shape) != shape:
+        raise ValueError(f"packed spectra must be {list(shape)}")
+    g = plan.grid
+    if tuple(cube.shape) != (C, g.ny, g.nx):
+        raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
+    if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
+        raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
+    st = load().hcg_grid_packed(plan.handle, _dptr(packed, sdt, "packed"), C, int(dtype),
+                                _dptr(chan_scale, torch.float32, "chan_scale"),
+                                _dptr(cube, torch.float32, "cube"),
+                                _dptr(weights, torch.float32, "weights"), _stream(stream))
+    _check(st, "hcg_grid_packed")
 
 
 def hcg_destroy(plan: Plan) -> None:

@@ -60,8 +60,11 @@ __device__ __forceinline__ double chord2(const CellVec& c, const double4& v) {
 //     = c2 (1 + c2/12 + c2^2/90 + c2^3/560 + c2^4/3150 + c2^5/16632 + ...);
 // six terms leave a relative error below 2e-17 for c2 < 1e-2 (d < 5.7 deg),
 // the arcsine beyond.
+// kWide = false: the caller guarantees c2 < 1e-2 (a support radius below
+// 5.7 deg), which keeps the arcsine and its registers out of the kernel.
+template <bool kWide = true>
 __device__ __forceinline__ double dist2_from_chord2(double c2) {
-  if (c2 < 1e-2)
+  if (!kWide || c2 < 1e-2)
     return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
            c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
   const double d = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
@@ -70,8 +73,9 @@ __device__ __forceinline__ double dist2_from_chord2(double c2) {
 
 // FP32 weight of a pair inside the support: the exponent -d^2 log2(e) /
 // (2 sigma^2) is formed in FP64 and evaluated with exp2f.
+template <bool kWide>
 __device__ __forceinline__ float pair_weight(double c2, double wscale) {
-  return exp2f((float)(dist2_from_chord2(c2) * wscale));
+  return exp2f((float)(dist2_from_chord2<kWide>(c2) * wscale));
 }
 
 // bit q (q < 8) of the result: any of bits 4q .. 4q + 3 of x
@@ -128,14 +132,27 @@ __device__ void block_centres(const GatherArgs& a, int tx, int ty, int t, double
 
 // Loads the tile's candidate ranges into LDS with exclusive prefix sums;
 // returns the total candidate count.  blockDim.x threads take part.
+// With npad > 0 (the sample count rounded up to a multiple of 8) every range
+// is widened to whole groups of 8 sorted positions, capped at npad, and cut
+// where it would overlap the previous one (the plan's ranges are disjoint
+// and increasing), so that every aligned group of 8 candidates is one group
+// of the plan-ordered spectra.  Samples added this way lie outside the
+// plan's ranges, hence beyond R of every cell of the tile: weight 0.
 __device__ uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32_t nr, uint2* s_rng,
-                                 uint32_t* s_pre) {
+                                 uint32_t* s_pre, uint32_t npad = 0) {
   const int nt = blockDim.x;
   for (uint32_t r = threadIdx.x; r < nr; r += nt) s_rng[r] = ranges[r];
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t acc = 0;
+    uint32_t acc = 0, end = 0;
     for (uint32_t r = 0; r < nr; ++r) {
+      if (npad) {
+        const uint2 v = s_rng[r];
+        const uint32_t lo = max(v.x & ~7u, end);
+        const uint32_t hi = max(lo, min((v.y + 7u) & ~7u, npad));
+        s_rng[r] = make_uint2(lo, hi);
+        end = hi;
+      }
       s_pre[r] = acc;
       acc += s_rng[r].y - s_rng[r].x;
     }
@@ -239,8 +256,27 @@ struct GatherSmem {
   double Wt[kTileCells];
 };
 
+// B operand of one 16-channel MFMA tile from the plan-ordered spectra: 8
+// sorted samples of one channel (16 bytes for the 16-bit forms, 8 for FP8).
+template <int kForm>
+struct PackedB {
+  using T = uint4;
+};
+template <>
+struct PackedB<kFP8S> {
+  using T = uint2;
+};
+template <>
+struct PackedB<kFP8Split> {
+  using T = uint2;
+};
+
 // One (tile, channel slab) of the contraction; all 256 threads take part.
-template <int kForm, int kQW, bool kVec>
+// kPacked: the spectra are plan-ordered, [ceil(n/8)][C][8] elements per plane
+// (hcg_quantize_packed), so a lane's B operand (8 consecutive sorted samples
+// of one channel) is one load and the loads of a block are issued before its
+// weights are computed.
+template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide>
 __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int slab,
                                             GatherSmem& sm) {
   constexpr int kK = FormTraits<kForm>::kK;
@@ -265,7 +301,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   const CellVec cell = cell_vec(g, my_x, my_y);
 
   const uint32_t total =
-      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre);
+      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre,
+                   kPacked ? (a.sentinel + 7u) & ~7u : 0u);
   if (tid < 64) block_centres(a, tx, ty, tid, sm.ctr);
 
   floatx4 acc[4][4 * kQW];
@@ -289,14 +326,46 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       if (q < total) {
         const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
         s_xyz[tid] = a.xyz[pos];
-        s_row[tid] = a.perm[pos];
+        if (!kPacked) s_row[tid] = a.perm[pos];
+        else if ((tid & 7) == 0) s_row[tid >> 3] = pos >> 3;  // group of 8 sorted samples
       } else {
         const double nan = __builtin_nan("");
         s_xyz[tid] = make_double4(nan, nan, nan, nan);
-        s_row[tid] = 0u;
+        if (!kPacked) s_row[tid] = 0u;
+        else if ((tid & 7) == 0) s_row[tid >> 3] = 0u;  // any group: its weights are 0
       }
     }
     __syncthreads();
+
+    // plan-ordered spectra: issue the block's B loads now (the first k-step
+    // only where registers are short), so that they are in flight while the
+    // weights are computed
+    using BT = typename PackedB<kForm>::T;
+    constexpr int kNJ = kPacked ? 4 * kQW : 1;
+    constexpr int kNSP = kPacked ? kNS : 1;
+    constexpr int kEarly = (kQW == 1 || kForm == kFP8S) ? kNSP : 1;
+    BT bq[kNSP][kNJ];
+    BT bql[kNSP][kNJ];
+    // Plan-ordered planes hold Cp = C rounded up to 16 channels, so a
+    // 16-channel tile is read whole; a tile past Cp reads the last tile
+    // instead (a uniform clamp: its products only reach channels >= C, which
+    // are not stored).
+    auto load_b = [&](int ks) {
+      const int64_t Cp = (C + 15) & ~int64_t(15);
+      const int64_t at = (int64_t)s_row[4 * ks + (lane >> 4)] * Cp + (lane & 15);
+      const BT* hi = (const BT*)a.spec + at;
+      const BT* lo = (const BT*)a.spec_lo + at;
+#pragma unroll
+      for (int j = 0; j < kNJ; ++j) {
+        const int64_t cj = min<int64_t>(c_w + 16 * j, Cp - 16);
+        bq[ks][j] = hi[cj];
+        if (is_split(kForm)) bql[ks][j] = lo[cj];
+      }
+    };
+    if constexpr (kPacked) {
+#pragma unroll
+      for (int ks = 0; ks < kEarly; ++ks) load_b(ks);
+    }
 
     // ---- weights of cell block `wave`, in the A-operand layout.  A coarse
     // test against the block's centre (lane l: candidate l) marks the
@@ -315,7 +384,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           pm &= pm - 1u;
           const double c2 = chord2(cell, s_xyz[4 * ks + (lane >> 4)]);
           float wf = 0.f;
-          if (c2 <= a.c2R) wf = pair_weight(c2, a.wscale);
+          if (c2 <= a.c2R) wf = pair_weight<kWide>(c2, a.wscale);
           wsum += (double)wf;
           sA32[(wave * kNS + ks) * 64 + lane] = wf;
           if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
@@ -328,15 +397,19 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         while (pm) {
           const int ks = __builtin_ctz(pm);
           pm &= pm - 1u;
-          // codes packed as they are made: 16-bit forms two per word, FP8 four
-          uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+          // codes go to LDS one element at a time (2-byte or 1-byte
+          // stores), so that no packed words stay live in registers
+          const int slot = (wave * kNS + ks) * 64 + lane;
+          const int slot_lo = 4 * kNS * 64 + slot;
+          uint32_t any = 0u;
           if ((gm >> (4 * ks + grp)) & 1u) {
             const int k0 = kK * ks + 8 * grp;
+#pragma unroll 2
             for (int t = 0; t < 8; ++t) {
               const double c2 = chord2(cell, s_xyz[k0 + t]);
               uint32_t h = 0u, l = 0u;
               if (c2 <= a.c2R) {
-                const float wf = pair_weight(c2, a.wscale);
+                const float wf = pair_weight<kWide>(c2, a.wscale);
                 h = enc_w<kForm>(wf);
                 double eff = (double)dec_w<kForm>(h);
                 if (kForm == kBF16Split) {
@@ -349,29 +422,22 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                 wsum += (double)wf;
                 wtsum += eff;
               }
-              if (is_fp8(kForm)) {
-                hw[t >> 2] |= h << (8 * (t & 3));
-                if (kForm == kFP8Split) lw[t >> 2] |= l << (8 * (t & 3));
+              if constexpr (is_fp8(kForm)) {
+                ((uint8_t*)&sA8[slot])[t] = (uint8_t)h;
+                if (kForm == kFP8Split) ((uint8_t*)&sA8[slot_lo])[t] = (uint8_t)l;
               } else {
-                hw[t >> 1] |= h << (16 * (t & 1));
-                if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
+                ((uint16_t*)&sA16[slot])[t] = (uint16_t)h;
+                if (kForm == kBF16Split) ((uint16_t*)&sA16[slot_lo])[t] = (uint16_t)l;
               }
-            }
-          }
-          uint32_t any;
-          if (is_fp8(kForm)) {
-            sA8[(wave * kNS + ks) * 64 + lane] = make_uint2(hw[0], hw[1]);
-            any = hw[0] | hw[1];
-            if (kForm == kFP8Split) {
-              sA8[(4 * kNS + wave * kNS + ks) * 64 + lane] = make_uint2(lw[0], lw[1]);
-              any |= lw[0] | lw[1];
+              any |= h | l;
             }
           } else {
-            sA16[(wave * kNS + ks) * 64 + lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            any = hw[0] | hw[1] | hw[2] | hw[3];
-            if (kForm == kBF16Split) {
-              sA16[(4 * kNS + wave * kNS + ks) * 64 + lane] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-              any |= lw[0] | lw[1] | lw[2] | lw[3];
+            if constexpr (is_fp8(kForm)) {
+              sA8[slot] = make_uint2(0u, 0u);
+              if (kForm == kFP8Split) sA8[slot_lo] = make_uint2(0u, 0u);
+            } else {
+              sA16[slot] = make_uint4(0u, 0u, 0u, 0u);
+              if (kForm == kBF16Split) sA16[slot_lo] = make_uint4(0u, 0u, 0u, 0u);
             }
           }
           if (__ballot(any != 0u)) nzbits |= 1u << ks;
@@ -421,6 +487,63 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
               acc[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].y, acc[cb][4 * h + 1], 0, 0, 0);
               acc[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].z, acc[cb][4 * h + 2], 0, 0, 0);
               acc[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].w, acc[cb][4 * h + 3], 0, 0, 0);
+            }
+          }
+        }
+      }
+    } else if constexpr (kPacked) {
+#pragma unroll
+      for (int ks = 0; ks < kNS; ++ks) {
+        // the k-steps not loaded early are loaded once the previous k-step's
+        // products are issued (registers); the scheduler may not merge them
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks >= kEarly) load_b(ks);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if (!((nzc[cb] >> ks) & 1u)) continue;
+          if constexpr (is_fp8(kForm)) {
+            const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
+            const long A = (long)(((uint64_t)av.y << 32) | av.x);
+            long Al = 0;
+            if (kForm == kFP8Split) {
+              const uint2 al = sA8[(4 * kNS + cb * kNS + ks) * 64 + lane];
+              Al = (long)(((uint64_t)al.y << 32) | al.x);
+            }
+#pragma unroll
+            for (int j = 0; j < kNJ; ++j) {
+              floatx4& c = acc[cb][j];
+              const long B = (long)(((uint64_t)bq[ks][j].y << 32) | bq[ks][j].x);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
+              if (kForm == kFP8Split) {
+                const long Bl = (long)(((uint64_t)bql[ks][j].y << 32) | bql[ks][j].x);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, Bl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
+              }
+            }
+          } else {
+            const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
+            uint4 al = make_uint4(0u, 0u, 0u, 0u);
+            if (kForm == kBF16Split) al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < kNJ; ++j) {
+              floatx4& c = acc[cb][j];
+              if (kForm == kF16S) {
+                c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
+                                                          __builtin_bit_cast(halfx8, bq[ks][j]),
+                                                          c, 0, 0, 0);
+              } else {
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                           __builtin_bit_cast(bf16x8, bq[ks][j]),
+                                                           c, 0, 0, 0);
+                if (kForm == kBF16Split) {
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                             __builtin_bit_cast(bf16x8, bql[ks][j]),
+                                                             c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
+                                                             __builtin_bit_cast(bf16x8, bq[ks][j]),
+                                                             c, 0, 0, 0);
+                }
+              }
             }
           }
         }
@@ -572,7 +695,9 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       for (int h = 0; h < kQW; ++h)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int64_t ch = my_ch + 64 * h + q;
+          // accumulator 4 h + q: channel 4 (lane % 16) + 64 h + q, or for the
+          // plan-ordered spectra lane % 16 + 16 (4 h + q)
+          const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15) : my_ch + 64 * h + q;
           if (ch >= C) continue;
           float v = acc[cb][4 * h + q][r] * inv;
           if (kForm == kF16S || is_fp8(kForm)) v *= a.scale[ch];
@@ -582,7 +707,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   }
 }
 
-template <int kForm, int kQW, bool kVec>
+template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide>
 __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   __shared__ GatherSmem sm;
   // XCD-aware order: the hardware deals consecutive workgroups to the eight
@@ -593,7 +718,7 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   const int local = blockIdx.x - slab * per_slab;
   const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
   if (tile >= a.ntiles) return;
-  gather_tile<kForm, kQW, kVec>(a, tile, slab, sm);
+  gather_tile<kForm, kQW, kVec, kPacked, kWide>(a, tile, slab, sm);
 }
 
 // Few channels (C <= 8) for a 256-thread workgroup: one lane per cell, the
@@ -722,8 +847,8 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
     const uint32_t tile = local - slab * sg.ntiles;
     const GatherArgs a = fields[sg.field];
     if (a.C <= 8) gather_cells_tile_wg(a, (int)tile, sm);
-    else if (a.vec) gather_tile<kF32, kQW, true>(a, (int)tile, (int)slab, sm);
-    else gather_tile<kF32, 1, false>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
+    else if (a.vec) gather_tile<kF32, kQW, true, false, true>(a, (int)tile, (int)slab, sm);
+    else gather_tile<kF32, 1, false, false, true>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
     __syncthreads();
   }
 }
@@ -829,10 +954,11 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
   return HCG_OK;
 }
 
-template <int kForm>
+template <int kForm, bool kPacked = false>
 static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void* spec_lo,
                               const float* scale, int64_t C, float* cube, float* wmap,
                               hipStream_t stream) {
+  static_assert(!(kPacked && kForm == kF32), "plan-ordered spectra are a low-precision input");
   GatherArgs a;
   a.xyz = p->xyz;
   a.sentinel = (uint32_t)p->n;
@@ -853,8 +979,11 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   a.cube = cube;
   a.wmap = wmap;
   const size_t esz = (kForm == kF32) ? 4 : is_fp8(kForm) ? 1 : 2;
-  const bool vec = (C % 4 == 0) && ((uintptr_t)spec % (4 * esz) == 0) &&
-                   (!spec_lo || (uintptr_t)spec_lo % (4 * esz) == 0);
+  // plan-ordered spectra are read 8 samples of a channel at a time
+  const bool vec = kPacked || ((C % 4 == 0) && ((uintptr_t)spec % (4 * esz) == 0) &&
+                               (!spec_lo || (uintptr_t)spec_lo % (4 * esz) == 0));
+  if (kPacked && ((uintptr_t)spec % (8 * esz) != 0 || (uintptr_t)spec_lo % (8 * esz) != 0))
+    return fail(HCG_E_ARG, "hcg_grid_packed: spectra must be %zu-byte aligned", 8 * esz);
   a.vec = vec ? 1 : 0;
   // 512-channel slabs (weights computed once per 512 channels) where the
   // registers allow it, else 256
@@ -864,15 +993,28 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   const int64_t blocks = slabs * a.tiles_per_xcd * 8;
   if (blocks > INT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
   const dim3 grid((unsigned)blocks), block(256);
+  // supports below 5.7 deg (squared chord < 1e-2) take the kernels without
+  // the arcsine branch of the distance
+  const bool wide = !(a.c2R < 1e-2);
+#define HCG_MFMA(QW, VEC)                                                                \
+  do {                                                                                   \
+    if (wide) k_gather_mfma<kForm, QW, VEC, kPacked, true><<<grid, block, 0, stream>>>(a); \
+    else k_gather_mfma<kForm, QW, VEC, kPacked, false><<<grid, block, 0, stream>>>(a);    \
+  } while (0)
   if constexpr (kForm != kBF16Split) {
     if (qw == 2) {
-      k_gather_mfma<kForm, 2, true><<<grid, block, 0, stream>>>(a);
+      HCG_MFMA(2, true);
       HCG_LAUNCH_CHECK("k_gather_mfma");
       return HCG_OK;
     }
   }
-  if (vec) k_gather_mfma<kForm, 1, true><<<grid, block, 0, stream>>>(a);
-  else k_gather_mfma<kForm, 1, false><<<grid, block, 0, stream>>>(a);
+  if constexpr (kPacked) {
+    HCG_MFMA(1, true);
+  } else {
+    if (vec) HCG_MFMA(1, true);
+    else HCG_MFMA(1, false);
+  }
+#undef HCG_MFMA
   HCG_LAUNCH_CHECK("k_gather_mfma");
   return HCG_OK;
 }
@@ -957,6 +1099,61 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
                                     chan_scale, nchan, cube, weights, stream);
   }
   return fail(HCG_E_UNSUPPORTED, "hcg_grid: dtype %d", (int)dtype);
+}
+
+extern "C" hcg_status hcg_packed_bytes(hcg_plan_t plan, int64_t nchan, hcg_dtype dtype,
+                                       int64_t* bytes) {
+  if (!plan || !bytes) return fail(HCG_E_ARG, "hcg_packed_bytes: NULL pointer");
+  if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_packed_bytes: not a live plan");
+  if (nchan < 1) return fail(HCG_E_ARG, "hcg_packed_bytes: nchan must be >= 1");
+  int64_t esz = 0, planes = 1;
+  switch (dtype) {
+    case HCG_BF16: case HCG_F16_SCALED: esz = 2; break;
+    case HCG_BF16_SPLIT: esz = 2; planes = 2; break;
+    case HCG_FP8E4M3_SCALED: esz = 1; break;
+    case HCG_FP8E4M3_SPLIT: esz = 1; planes = 2; break;
+    default: return fail(HCG_E_ARG, "hcg_packed_bytes: dtype %d is not a low-precision form", (int)dtype);
+  }
+  const int64_t groups = (plan->n + 7) / 8;
+  *bytes = planes * groups * 8 * ((nchan + 15) & ~int64_t(15)) * esz;
+  return HCG_OK;
+}
+
+extern "C" hcg_status hcg_grid_packed(hcg_plan_t plan, const void* packed, int64_t nchan,
+                                      hcg_dtype dtype, const float* chan_scale, float* cube,
+                                      float* weights, void* hip_stream) {
+  if (!plan) return fail(HCG_E_ARG, "hcg_grid_packed: plan is NULL");
+  if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid_packed: not a live plan");
+  if (!packed || !cube) return fail(HCG_E_ARG, "hcg_grid_packed: spectra and cube must not be NULL");
+  if (nchan < 1) return fail(HCG_E_ARG, "hcg_grid_packed: nchan must be >= 1");
+  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED ||
+                       dtype == HCG_FP8E4M3_SPLIT);
+  if (dtype < HCG_BF16 || dtype > HCG_FP8E4M3_SPLIT)
+    return fail(HCG_E_ARG, "hcg_grid_packed: dtype %d is not a low-precision form", (int)dtype);
+  if (scaled && !chan_scale) return fail(HCG_E_ARG, "hcg_grid_packed: chan_scale is required for this dtype");
+  if (!scaled && chan_scale) return fail(HCG_E_ARG, "hcg_grid_packed: chan_scale must be NULL for this dtype");
+  const hcg_plan_s* p = plan;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  // elements per plane: 8 ceil(n / 8) sorted positions x nchan rounded up to 16
+  const size_t plane = (size_t)((p->n + 7) / 8) * 8 * (size_t)((nchan + 15) & ~int64_t(15));
+  const char* sp = (const char*)packed;
+  switch (dtype) {
+    case HCG_BF16:
+      return launch_mfma<kBF16, true>(p, sp, sp, nullptr, nchan, cube, weights, stream);
+    case HCG_BF16_SPLIT:
+      return launch_mfma<kBF16Split, true>(p, sp, sp + 2 * plane, nullptr, nchan, cube, weights,
+                                           stream);
+    case HCG_F16_SCALED:
+      return launch_mfma<kF16S, true>(p, sp, sp, chan_scale, nchan, cube, weights, stream);
+    case HCG_FP8E4M3_SCALED:
+      return launch_mfma<kFP8S, true>(p, sp, sp, chan_scale, nchan, cube, weights, stream);
+    case HCG_FP8E4M3_SPLIT:
+      return launch_mfma<kFP8Split, true>(p, sp, sp + plane, chan_scale, nchan, cube, weights,
+                                          stream);
+    default:
+      break;
+  }
+  return fail(HCG_E_ARG, "hcg_grid_packed: dtype %d", (int)dtype);
 }
 
 extern "C" hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats,

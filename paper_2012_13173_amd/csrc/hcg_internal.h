@@ -155,8 +155,8 @@ struct hcg_plan_s {
   int32_t ntx, nty, maxr;
   void* arena;
   size_t arena_bytes;
-  double4* xyz;        // [n + 1] sorted unit vectors (cos b cos l, cos b sin l, sin b, 0);
-                       // entry n: NaN (sentinel)
+  double4* xyz;        // [n + 8] sorted unit vectors (cos b cos l, cos b sin l, sin b, 0);
+                       // entries n .. n + 7: NaN (sentinels)
   uint32_t* keys;      // [n] sorted pixel - pix_base
   uint32_t* perm;      // [n + 1] input index of each sorted sample; entry n: 0 (sentinel)
   uint32_t* csr;       // [nrings + 1]
@@ -187,7 +187,7 @@ struct GatherArgs {
   const uint2* ranges;
   const uint32_t* nranges;
   int maxr;
-  uint32_t sentinel;    // n: index of the sentinel entry of xyz and perm
+  uint32_t sentinel;    // n: index of the first sentinel entry of xyz and perm
   const void* spec;     // [n][C] in the form's storage type
   const void* spec_lo;  // low plane for the split form
   const float* scale;   // [C] per-channel scale for the scaled forms

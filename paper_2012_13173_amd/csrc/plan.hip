@@ -617,9 +617,10 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   // plan arena
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
-  // xyz and perm carry one sentinel entry at n (NaN vector, row 0): the
-  // gather reads it for the padding of its last candidate block
-  const size_t o_xyz = take(sizeof(double4) * (n + 1));
+  // xyz carries eight sentinel entries from n (NaN vectors) and perm one
+  // (row 0): the gather reads them for candidate lists widened to whole
+  // groups of 8 sorted positions
+  const size_t o_xyz = take(sizeof(double4) * (n + 8));
   const size_t o_keys = take(sizeof(uint32_t) * n);
   const size_t o_perm = take(sizeof(uint32_t) * (n + 1));
   const size_t o_csr = take(sizeof(uint32_t) * (nrings + 1));
@@ -683,7 +684,7 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   k_permute_xyz<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(lon_deg, lat_deg, p->perm, n,
                                                                 p->xyz);
   HCG_LAUNCH_CHECK("k_permute_xyz");
-  HCG_HIP(hipMemsetAsync(p->xyz + n, 0xFF, sizeof(double4), stream));  // all-ones: NaN
+  HCG_HIP(hipMemsetAsync(p->xyz + n, 0xFF, 8 * sizeof(double4), stream));  // all-ones: NaN
   HCG_HIP(hipMemsetAsync(p->perm + n, 0, sizeof(uint32_t), stream));
   k_ring_csr<<<(unsigned)((nrings + 1 + 255) / 256), 256, 0, stream>>>(
       p->keys, n, nside, ring_first, nrings, pix_base, p->csr);

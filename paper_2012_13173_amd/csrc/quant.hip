@@ -62,6 +62,86 @@ __global__ void __launch_bounds__(256) k_encode(const float* __restrict__ in, in
   }
 }
 
+// One element in the storage code of a form (x already divided by its scale
+// for the scaled forms); lo: the code of the remainder for the split forms.
+template <int kDtype>
+__device__ __forceinline__ uint32_t encode_elem(float x, uint32_t* lo) {
+  if (kDtype == HCG_BF16) return f32_to_bf16(x);
+  if (kDtype == HCG_BF16_SPLIT) {
+    const uint32_t hi = f32_to_bf16(x);
+    *lo = f32_to_bf16(x - bf16_to_f32(hi));
+    return hi;
+  }
+  if (kDtype == HCG_F16_SCALED) return f32_to_f16(x);
+  const uint32_t hi = f32_to_e4m3(x);
+  if (kDtype == HCG_FP8E4M3_SPLIT) *lo = f32_to_e4m3(x - e4m3_to_f32(hi));
+  return hi;
+}
+
+// Plan-ordered encoding: element (sorted position p, channel c) of a plane
+// sits at ((p / 8) Cp + c) 8 + p % 8 with Cp = C rounded up to 16, so the 8
+// sorted samples of a group are contiguous for each channel; positions
+// p >= n and channels c >= C (the padding) hold zero.  One thread per
+// (group, channel): 8 row reads through the plan's permutation, one 16-byte
+// (16-bit forms) or 8-byte (FP8) store per plane.
+template <int kDtype>
+__global__ void __launch_bounds__(256) k_encode_packed(const float* __restrict__ in, int64_t n,
+                                                       int64_t C, const uint32_t* __restrict__ perm,
+                                                       const float* __restrict__ scale,
+                                                       void* __restrict__ out, int64_t plane) {
+  constexpr bool k8 = (kDtype == HCG_FP8E4M3_SCALED || kDtype == HCG_FP8E4M3_SPLIT);
+  constexpr bool kSplit = (kDtype == HCG_BF16_SPLIT || kDtype == HCG_FP8E4M3_SPLIT);
+  constexpr bool kScaled = (kDtype == HCG_F16_SCALED || k8);
+  const int64_t groups = (n + 7) / 8;
+  const int64_t Cp = (C + 15) & ~int64_t(15);
+  const int64_t total = groups * Cp;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t grp = i / Cp, c = i - grp * Cp;
+    const float sc = (kScaled && c < C) ? scale[c] : 1.f;
+    uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t pos = grp * 8 + t;
+      if (pos >= n || c >= C) break;
+      const float x = in[(int64_t)perm[pos] * C + c];
+      uint32_t l = 0u;
+      const uint32_t h = encode_elem<kDtype>(kScaled ? x / sc : x, &l);
+      if (k8) {
+        hw[t >> 2] |= h << (8 * (t & 3));
+        lw[t >> 2] |= l << (8 * (t & 3));
+      } else {
+        hw[t >> 1] |= h << (16 * (t & 1));
+        lw[t >> 1] |= l << (16 * (t & 1));
+      }
+    }
+    if (k8) {
+      ((uint2*)out)[i] = make_uint2(hw[0], hw[1]);
+      if (kSplit) ((uint2*)((uint8_t*)out + plane))[i] = make_uint2(lw[0], lw[1]);
+    } else {
+      ((uint4*)out)[i] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      if (kSplit) ((uint4*)((uint16_t*)out + plane))[i] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+  }
+}
+
+// Per-channel power-of-two scales of the scaled forms into chan_scale.
+static hcg_status channel_scales(const float* in, int64_t n, int64_t nchan, hcg_dtype dtype,
+                                 float* chan_scale, hipStream_t stream) {
+  HCG_HIP(hipMemsetAsync(chan_scale, 0, sizeof(float) * nchan, stream));
+  if (n > 0) {
+    const int64_t rows_per_block = std::max<int64_t>(64, (n + 255) / 256);
+    const dim3 grid((unsigned)((nchan + 255) / 256),
+                    (unsigned)((n + rows_per_block - 1) / rows_per_block));
+    k_chan_absmax<<<grid, 256, 0, stream>>>(in, n, nchan, rows_per_block, (uint32_t*)chan_scale);
+    HCG_LAUNCH_CHECK("k_chan_absmax");
+  }
+  const float top = (dtype == HCG_F16_SCALED) ? 16384.f : 448.f;
+  k_chan_scale<<<(unsigned)((nchan + 255) / 256), 256, 0, stream>>>(chan_scale, nchan, top);
+  HCG_LAUNCH_CHECK("k_chan_scale");
+  return HCG_OK;
+}
+
 }  // namespace hcg
 
 using namespace hcg;
@@ -79,18 +159,8 @@ extern "C" hcg_status hcg_quantize(const float* in, int64_t n, int64_t nchan, hc
   if (st != HCG_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
   if (scaled) {
-    HCG_HIP(hipMemsetAsync(chan_scale, 0, sizeof(float) * nchan, stream));
-    if (n > 0) {
-      const int64_t rows_per_block = std::max<int64_t>(64, (n + 255) / 256);
-      const dim3 grid((unsigned)((nchan + 255) / 256),
-                      (unsigned)((n + rows_per_block - 1) / rows_per_block));
-      k_chan_absmax<<<grid, 256, 0, stream>>>(in, n, nchan, rows_per_block,
-                                              (uint32_t*)chan_scale);
-      HCG_LAUNCH_CHECK("k_chan_absmax");
-    }
-    const float top = (dtype == HCG_F16_SCALED) ? 16384.f : 448.f;
-    k_chan_scale<<<(unsigned)((nchan + 255) / 256), 256, 0, stream>>>(chan_scale, nchan, top);
-    HCG_LAUNCH_CHECK("k_chan_scale");
+    st = channel_scales(in, n, nchan, dtype, chan_scale, stream);
+    if (st != HCG_OK) return st;
   }
   const int64_t total = n * nchan;
   if (total == 0) return HCG_OK;
@@ -113,5 +183,47 @@ extern "C" hcg_status hcg_quantize(const float* in, int64_t n, int64_t nchan, hc
       break;
   }
   HCG_LAUNCH_CHECK("k_encode");
+  return HCG_OK;
+}
+
+extern "C" hcg_status hcg_quantize_packed(hcg_plan_t plan, const float* in, int64_t nchan,
+                                          hcg_dtype dtype, void* out, float* chan_scale,
+                                          void* hip_stream) {
+  if (!plan) return fail(HCG_E_ARG, "hcg_quantize_packed: plan is NULL");
+  if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_quantize_packed: not a live plan");
+  if (nchan < 1) return fail(HCG_E_ARG, "hcg_quantize_packed: nchan must be >= 1");
+  if (!in || !out) return fail(HCG_E_ARG, "hcg_quantize_packed: NULL pointer");
+  const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED ||
+                       dtype == HCG_FP8E4M3_SPLIT);
+  if (dtype != HCG_BF16 && dtype != HCG_BF16_SPLIT && !scaled)
+    return fail(HCG_E_ARG, "hcg_quantize_packed: dtype %d is not a low-precision form", (int)dtype);
+  if (scaled && !chan_scale) return fail(HCG_E_ARG, "hcg_quantize_packed: chan_scale is required");
+  if (!scaled && chan_scale) return fail(HCG_E_ARG, "hcg_quantize_packed: chan_scale must be NULL");
+  const bool k8 = (dtype == HCG_FP8E4M3_SCALED || dtype == HCG_FP8E4M3_SPLIT);
+  if ((uintptr_t)out % (k8 ? 8 : 16) != 0)
+    return fail(HCG_E_ARG, "hcg_quantize_packed: out must be %d-byte aligned", k8 ? 8 : 16);
+  const hcg_plan_s* p = plan;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const int64_t n = p->n;
+  if (scaled) {
+    hcg_status st = channel_scales(in, n, nchan, dtype, chan_scale, stream);
+    if (st != HCG_OK) return st;
+  }
+  const int64_t cp = (nchan + 15) & ~int64_t(15);
+  const int64_t plane = (n + 7) / 8 * 8 * cp;  // elements per plane
+  const int64_t total = (n + 7) / 8 * cp;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+#define HCG_PACK(D)                                                                        \
+  k_encode_packed<D><<<blocks, 256, 0, stream>>>(in, n, nchan, p->perm, chan_scale, out,  \
+                                                  plane)
+  switch (dtype) {
+    case HCG_BF16: HCG_PACK(HCG_BF16); break;
+    case HCG_BF16_SPLIT: HCG_PACK(HCG_BF16_SPLIT); break;
+    case HCG_F16_SCALED: HCG_PACK(HCG_F16_SCALED); break;
+    case HCG_FP8E4M3_SCALED: HCG_PACK(HCG_FP8E4M3_SCALED); break;
+    default: HCG_PACK(HCG_FP8E4M3_SPLIT); break;
+  }
+#undef HCG_PACK
+  HCG_LAUNCH_CHECK("k_encode_packed");
   return HCG_OK;
 }

@@ -1,5 +1,6 @@
 """GPU parity at the full sizes of the benchmark configurations, in the launch
-configuration bench.py times (hcg_plan + hcg_grid on the whole map), checked
+configuration bench.py times (hcg_plan + hcg_grid on the whole map, and the
+plan-ordered encodings through hcg_quantize_packed + hcg_grid_packed), checked
 on sampled cells that the FP64 oracle computes one by one: seeded 16 x 16-cell
 patches, the corners and the ends of the centre row.
 
@@ -30,7 +31,7 @@ NAME = {hcg.HCG_F32: "f32", hcg.HCG_F16_SCALED: "f16_scaled", hcg.HCG_BF16_SPLIT
         hcg.HCG_FP8E4M3_SPLIT: "fp8e4m3_split"}
 
 
-def _check(w, forms, seed):
+def _check(w, forms, seed, packed=()):
     g = w.grid
     print(f"{w.name}: {w.n} samples x {w.nchan} channels", flush=True)
     groups = sample_cells(g, seed)
@@ -54,6 +55,16 @@ def _check(w, forms, seed):
         assert_weights_close(Wg, Wr)
         print(f"  {NAME[form]:>15s}: {cells.size} cells, max {e.max():.2e} "
               f"median {np.median(e):.2e}", flush=True)
+    for form in packed:  # plan-ordered encodings, as bench.py times them
+        enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
+        hcg.hcg_grid_packed(plan, enc, cube, W, dtype=form, chan_scale=scale)
+        del enc
+        torch.cuda.synchronize()
+        V, Wg = gather_cells(cube, W, cells)
+        e = assert_cube_close(V.T, Vr.T, TOL[form], f"{w.name} packed {NAME[form]}")
+        assert_weights_close(Wg, Wr)
+        print(f"  packed {NAME[form]:>15s}: {cells.size} cells, max {e.max():.2e} "
+              f"median {np.median(e):.2e}", flush=True)
     plan.destroy()
     del cube, W
     torch.cuda.empty_cache()
@@ -62,20 +73,24 @@ def _check(w, forms, seed):
 def test_drift_scan_1024_full_size():
     w = synth.drift_scan_1024(device=DEV)
     _check(w, [hcg.HCG_F32, hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT,
-               hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=11)
+               hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=11,
+           packed=[hcg.HCG_F16_SCALED, hcg.HCG_BF16, hcg.HCG_BF16_SPLIT,
+                   hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT])
     del w
     torch.cuda.empty_cache()
 
 
 def test_drift_scan_8192_full_size():
     w = synth.drift_scan_8192(device=DEV)
-    _check(w, [hcg.HCG_F32, hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT], seed=12)
+    _check(w, [hcg.HCG_F32, hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT], seed=12,
+           packed=[hcg.HCG_F16_SCALED, hcg.HCG_BF16_SPLIT])
     del w
     torch.cuda.empty_cache()
 
 
 def test_large_cube_full_size():
     w = synth.drift_scan_large(device=DEV)
-    _check(w, [hcg.HCG_F32, hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=14)
+    _check(w, [hcg.HCG_F32, hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=14,
+           packed=[hcg.HCG_FP8E4M3_SPLIT, hcg.HCG_F16_SCALED])
     del w
     torch.cuda.empty_cache()
