@@ -124,7 +124,9 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
 hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
   hcg_status st = launch_batch_reset(b->d_ctl, stream);
   if (st != HCG_OK) return st;
-  return launch_batch(b->qw, b->d_fields, b->d_segs, b->d_ctl, b->nblocks, stream);
+  bool wide = false;
+  for (const GatherArgs& f : b->h_fields) wide = wide || !(f.c2R < 1e-2);
+  return launch_batch(b->qw, wide, b->d_fields, b->d_segs, b->d_ctl, b->nblocks, stream);
 }
 
 std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {

@@ -276,7 +276,7 @@ struct PackedB<kFP8Split> {
 // (hcg_quantize_packed), so a lane's B operand (8 consecutive sorted samples
 // of one channel) is one load and the loads of a block are issued before its
 // weights are computed.
-template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide>
+template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide, bool kAhead = true>
 __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int slab,
                                             GatherSmem& sm) {
   constexpr int kK = FormTraits<kForm>::kK;
@@ -320,22 +320,38 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   uint4* sA16 = s_Araw;                        // [4][kNS][64] (+ lo plane after)
   uint2* sA8 = (uint2*)s_Araw;                 // [4][kNS][64]
 
-  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
+  // Candidate staging runs one block ahead (kAhead): wave 0 loads the next
+  // block's unit vectors and rows (or groups) into registers while the
+  // current block is processed, and stores them to LDS at the top of the next
+  // iteration.  Without kAhead (fewer registers) it loads them there.
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  uint32_t nrow = 0u;
+  auto fetch = [&](uint32_t qb) {
     if (tid < kKB) {
-      const uint32_t q = q0 + tid;
+      const uint32_t q = qb + tid;
       if (q < total) {
         const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
-        s_xyz[tid] = a.xyz[pos];
-        if (!kPacked) s_row[tid] = a.perm[pos];
-        else if ((tid & 7) == 0) s_row[tid >> 3] = pos >> 3;  // group of 8 sorted samples
+        const double4 v = a.xyz[pos];
+        nx = v.x;
+        ny = v.y;
+        nz = v.z;
+        nrow = kPacked ? pos >> 3 : a.perm[pos];  // group of 8 sorted samples, or row
       } else {
-        const double nan = __builtin_nan("");
-        s_xyz[tid] = make_double4(nan, nan, nan, nan);
-        if (!kPacked) s_row[tid] = 0u;
-        else if ((tid & 7) == 0) s_row[tid >> 3] = 0u;  // any group: its weights are 0
+        nx = ny = nz = __builtin_nan("");
+        nrow = 0u;  // any group or row: its weights are 0
       }
     }
+  };
+  if (kAhead) fetch(0);
+  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
+    if (!kAhead) fetch(q0);
+    if (tid < kKB) {
+      s_xyz[tid] = make_double4(nx, ny, nz, 0.0);
+      if (!kPacked) s_row[tid] = nrow;
+      else if ((tid & 7) == 0) s_row[tid >> 3] = nrow;
+    }
     __syncthreads();
+    if (kAhead && q0 + kKB < total) fetch(q0 + kKB);
 
     // plan-ordered spectra: issue the block's B loads now (the first k-step
     // only where registers are short), so that they are in flight while the
@@ -810,7 +826,7 @@ __global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
   for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
 }
 
-template <int kQW>
+template <int kQW, bool kWide>
 __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
                                                          const BatchSeg* __restrict__ segs,
                                                          uint32_t* __restrict__ ctl) {
@@ -847,8 +863,8 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
     const uint32_t tile = local - slab * sg.ntiles;
     const GatherArgs a = fields[sg.field];
     if (a.C <= 8) gather_cells_tile_wg(a, (int)tile, sm);
-    else if (a.vec) gather_tile<kF32, kQW, true, false, true>(a, (int)tile, (int)slab, sm);
-    else gather_tile<kF32, 1, false, false, true>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
+    else if (a.vec) gather_tile<kF32, kQW, true, false, kWide, false>(a, (int)tile, (int)slab, sm);
+    else gather_tile<kF32, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
     __syncthreads();
   }
 }
@@ -1051,12 +1067,16 @@ hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream) {
   return HCG_OK;
 }
 
-hcg_status launch_batch(int qw, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
-                        int nblocks, hipStream_t stream) {
-  if (qw == 2)
-    k_gather_batch<2><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+hcg_status launch_batch(int qw, bool wide, const GatherArgs* fields, const BatchSeg* segs,
+                        uint32_t* ctl, int nblocks, hipStream_t stream) {
+  if (qw == 2 && wide)
+    k_gather_batch<2, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  else if (qw == 2)
+    k_gather_batch<2, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  else if (wide)
+    k_gather_batch<1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
   else
-    k_gather_batch<1><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+    k_gather_batch<1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
   HCG_LAUNCH_CHECK("k_gather_batch");
   return HCG_OK;
 }
