@@ -413,14 +413,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         while (pm) {
           const int ks = __builtin_ctz(pm);
           pm &= pm - 1u;
-          // codes go to LDS one element at a time (2-byte or 1-byte
-          // stores), so that no packed words stay live in registers
-          const int slot = (wave * kNS + ks) * 64 + lane;
-          const int slot_lo = 4 * kNS * 64 + slot;
-          uint32_t any = 0u;
+          // codes packed as they are made: 16-bit forms two per word, FP8 four
+          uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
           if ((gm >> (4 * ks + grp)) & 1u) {
             const int k0 = kK * ks + 8 * grp;
-#pragma unroll 2
+#pragma unroll
             for (int t = 0; t < 8; ++t) {
               const double c2 = chord2(cell, s_xyz[k0 + t]);
               uint32_t h = 0u, l = 0u;
@@ -438,22 +435,31 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                 wsum += (double)wf;
                 wtsum += eff;
               }
-              if constexpr (is_fp8(kForm)) {
-                ((uint8_t*)&sA8[slot])[t] = (uint8_t)h;
-                if (kForm == kFP8Split) ((uint8_t*)&sA8[slot_lo])[t] = (uint8_t)l;
+              if (is_fp8(kForm)) {
+                hw[t >> 2] |= h << (8 * (t & 3));
+                if (kForm == kFP8Split) lw[t >> 2] |= l << (8 * (t & 3));
               } else {
-                ((uint16_t*)&sA16[slot])[t] = (uint16_t)h;
-                if (kForm == kBF16Split) ((uint16_t*)&sA16[slot_lo])[t] = (uint16_t)l;
+                hw[t >> 1] |= h << (16 * (t & 1));
+                if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
               }
-              any |= h | l;
+            }
+          }
+          uint32_t any;
+          const int slot = (wave * kNS + ks) * 64 + lane;
+          const int slot_lo = 4 * kNS * 64 + slot;
+          if (is_fp8(kForm)) {
+            sA8[slot] = make_uint2(hw[0], hw[1]);
+            any = hw[0] | hw[1];
+            if (kForm == kFP8Split) {
+              sA8[slot_lo] = make_uint2(lw[0], lw[1]);
+              any |= lw[0] | lw[1];
             }
           } else {
-            if constexpr (is_fp8(kForm)) {
-              sA8[slot] = make_uint2(0u, 0u);
-              if (kForm == kFP8Split) sA8[slot_lo] = make_uint2(0u, 0u);
-            } else {
-              sA16[slot] = make_uint4(0u, 0u, 0u, 0u);
-              if (kForm == kBF16Split) sA16[slot_lo] = make_uint4(0u, 0u, 0u, 0u);
+            sA16[slot] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            any = hw[0] | hw[1] | hw[2] | hw[3];
+            if (kForm == kBF16Split) {
+              sA16[slot_lo] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+              any |= lw[0] | lw[1] | lw[2] | lw[3];
             }
           }
           if (__ballot(any != 0u)) nzbits |= 1u << ks;
@@ -696,30 +702,51 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   }
   __syncthreads();
 
+  // A lane's four cells r = 0..3 of a cell block are consecutive in x: one
+  // 16-byte store per channel where rows and the cube allow it (a 4-byte
+  // store costs a whole 32-byte write in HBM), else one store per cell.
   const float qnan = __builtin_nanf("");
+  const bool st4 = (g.nx % 4 == 0) && (((uintptr_t)a.cube & 15u) == 0);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int y = ty * kTileY + (cb >> 1) * 4 + (lane >> 4);
+    const int x0 = tx * kTileX + (cb & 1) * 4;
+    if (y >= g.ny || x0 >= g.nx) continue;
+    float inv[4];
+    bool has[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int x = tx * kTileX + (cb & 1) * 4 + r;
-      if (x >= g.nx || y >= g.ny) continue;
       const double wt = s_Wt[cb * 16 + 4 * (lane >> 4) + r];
-      const float inv = (wt > 0.0) ? (float)(1.0 / wt) : 0.f;
-      const int64_t cellidx = (int64_t)y * g.nx + x;
-#pragma unroll
-      for (int h = 0; h < kQW; ++h)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          // accumulator 4 h + q: channel 4 (lane % 16) + 64 h + q, or for the
-          // plan-ordered spectra lane % 16 + 16 (4 h + q)
-          const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15) : my_ch + 64 * h + q;
-          if (ch >= C) continue;
-          float v = acc[cb][4 * h + q][r] * inv;
-          if (kForm == kF16S || is_fp8(kForm)) v *= a.scale[ch];
-          a.cube[ch * G + cellidx] = (wt > 0.0) ? v : qnan;
-        }
+      has[r] = wt > 0.0;
+      inv[r] = has[r] ? (float)(1.0 / wt) : 0.f;
     }
+    const int64_t row0 = (int64_t)y * g.nx + x0;
+    const bool full = st4 && x0 + 3 < g.nx;
+#pragma unroll
+    for (int h = 0; h < kQW; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // accumulator 4 h + q: channel 4 (lane % 16) + 64 h + q, or for the
+        // plan-ordered spectra lane % 16 + 16 (4 h + q)
+        const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15) : my_ch + 64 * h + q;
+        if (ch >= C) continue;
+        const float sc = (kForm == kF16S || is_fp8(kForm)) ? a.scale[ch] : 1.f;
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float t = acc[cb][4 * h + q][r] * inv[r];
+          if (kForm == kF16S || is_fp8(kForm)) t *= sc;
+          v[r] = has[r] ? t : qnan;
+        }
+        float* dst = a.cube + ch * G + row0;
+        if (full) {
+          *(floatx4*)dst = floatx4{v[0], v[1], v[2], v[3]};
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (x0 + r < g.nx) dst[r] = v[r];
+        }
+      }
   }
 }
 
