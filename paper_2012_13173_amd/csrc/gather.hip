@@ -382,6 +382,30 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
       for (int ks = 0; ks < kEarly; ++ks) load_b(ks);
     }
+    // FP32: the first kDepth k-steps' rows are loaded before the weights too
+    constexpr int kDepth = kWide ? 4 : 6;
+    floatx4 b[kForm == kF32 ? kDepth : 1][kQW];
+    auto load = [&](int ks, floatx4* dst) {
+      const float* spec = (const float*)a.spec;
+      const int64_t row = s_row[4 * ks + (lane >> 4)];
+#pragma unroll
+      for (int h = 0; h < kQW; ++h) {
+        const int64_t ch = my_ch + 64 * h;
+        const float* src = spec + row * C + ch;
+        if (kVec) {
+          dst[h] = (ch + 3 < C) ? *(const floatx4*)src : floatx4{0.f, 0.f, 0.f, 0.f};
+        } else {
+          dst[h].x = (ch + 0 < C) ? src[0] : 0.f;
+          dst[h].y = (ch + 1 < C) ? src[1] : 0.f;
+          dst[h].z = (ch + 2 < C) ? src[2] : 0.f;
+          dst[h].w = (ch + 3 < C) ? src[3] : 0.f;
+        }
+      }
+    };
+    if constexpr (kForm == kF32) {
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) load(d, b[d]);
+    }
 
     // ---- weights of cell block `wave`, in the A-operand layout.  A coarse
     // test against the block's centre (lane l: candidate l) marks the
@@ -471,28 +495,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 
     // ---- contraction over the block
     const uint32_t nzc[4] = {s_nz[0], s_nz[1], s_nz[2], s_nz[3]};
-    if (kForm == kF32) {
-      const float* spec = (const float*)a.spec;
-      constexpr int kDepth = 4;
-      floatx4 b[kDepth][kQW];
-      auto load = [&](int ks, floatx4* dst) {
-        const int64_t row = s_row[4 * ks + (lane >> 4)];
-#pragma unroll
-        for (int h = 0; h < kQW; ++h) {
-          const int64_t ch = my_ch + 64 * h;
-          const float* src = spec + row * C + ch;
-          if (kVec) {
-            dst[h] = (ch + 3 < C) ? *(const floatx4*)src : floatx4{0.f, 0.f, 0.f, 0.f};
-          } else {
-            dst[h].x = (ch + 0 < C) ? src[0] : 0.f;
-            dst[h].y = (ch + 1 < C) ? src[1] : 0.f;
-            dst[h].z = (ch + 2 < C) ? src[2] : 0.f;
-            dst[h].w = (ch + 3 < C) ? src[3] : 0.f;
-          }
-        }
-      };
-#pragma unroll
-      for (int d = 0; d < kDepth; ++d) load(d, b[d]);
+    if constexpr (kForm == kF32) {
 #pragma unroll
       for (int ks = 0; ks < kNS; ++ks) {
         floatx4 cb_b[kQW];
