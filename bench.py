@@ -36,8 +36,9 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = os.path.join(ROOT, "paper_2012_13173_amd", "csrc", "gather.hip")
 
 
-def measured_traffic(workload):
-    """HBM bytes per FP32 gather launch from the committed counter summary
+def measured_traffic(workload, kernel="f32"):
+    """HBM bytes per gather launch of ``kernel`` (a key of the summary's
+    "kernels": "f32" or a form name) from the committed counter summary
     (profiles/traffic_<workload>.json: FETCH_SIZE x its copy-kernel factor +
     WRITE_SIZE), or None if it was taken on another version of the kernel
     source."""
@@ -51,7 +52,8 @@ def measured_traffic(workload):
         sha = hashlib.sha256(f.read()).hexdigest()
     if rec.get("gather_source_sha256") != sha:
         return None
-    return float(rec["hbm_bytes_per_launch"])
+    k = rec.get("kernels", {}).get(kernel)
+    return float(k["hbm_bytes_per_launch"]) if k else None
 
 
 def log(msg):
@@ -213,7 +215,8 @@ def main():
     ap.add_argument("--workload", default="drift_scan", choices=["drift_scan", "batch"],
                     help="drift_scan: 9.12M samples x 1024 channels (default); batch: 64 fields")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
+                    help="run a kernel that reads 1 GiB and writes 1 GiB first (reference "
+                         "for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (sharding across GPUs is "
@@ -233,7 +236,7 @@ def main():
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)  # one elementwise kernel: 1 GiB in, 1 GiB out
         torch.cuda.synchronize()
         del src, dst
     cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=dev)
@@ -327,6 +330,11 @@ def main():
                           "grid_updates_per_s": updates / (ms * 1e-3),
                           "speedup_vs_f32_grid": grid_avg / ms,
                           "speedup_vs_f32_grid_incl_encode": grid_avg / (ms + enc_ms)}
+            hbm = measured_traffic(w.name, key)
+            if hbm:
+                forms[key]["hbm_bytes_per_launch"] = hbm
+                forms[key]["hbm_GBps"] = hbm / (ms * 1e-3) / 1e9
+                forms[key]["hbm_frac_of_peak"] = hbm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
             cubes[key] = out
             del enc
             log(f"plan-ordered form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 "

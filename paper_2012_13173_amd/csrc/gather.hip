@@ -891,9 +891,9 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
     const uint32_t local = it - sg.base;
     const uint32_t slab = local / sg.ntiles;
     const uint32_t tile = local - slab * sg.ntiles;
-    const GatherArgs a = fields[sg.field];
+    const GatherArgs& a = fields[sg.field];  // read on demand (scalar loads)
     if (a.C <= 8) gather_cells_tile_wg(a, (int)tile, sm);
-    else if (a.vec) gather_tile<kF32, kQW, true, false, kWide, false>(a, (int)tile, (int)slab, sm);
+    else if (a.vec) gather_tile<kF32, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
     else gather_tile<kF32, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
     __syncthreads();
   }
