@@ -60,11 +60,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, cubes, budget_s=15.0, patch=32, max_patches=40, seed=7):
-    """Times the FP64 oracle on patches of patch x patch cells (all channels)
-    until ~budget_s of wall time, and extrapolates to the whole grid.  Also
-    returns, for every GPU cube in ``cubes`` (name -> [C, ny, nx] tensor), the
-    per-channel relative L2 errors against the oracle on those cells."""
+def oracle_sample(w, budget_s=15.0, patch=32, max_patches=40, seed=7):
+    """Runs the FP64 oracle on seeded patches of patch x patch cells (all
+    channels) until ~budget_s of wall time; returns the cells, the oracle's
+    values on them and the time it took (the CPU baseline leg)."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     oracle.set_threads(cores)
@@ -72,15 +71,13 @@ def cpu_baseline(w, cubes, budget_s=15.0, patch=32, max_patches=40, seed=7):
     lon = w.lon.cpu().numpy()
     lat = w.lat.cpu().numpy()
     rng = np.random.default_rng(seed)
-    t_total, cells_done = 0.0, 0
-    num = {k: np.zeros(w.nchan) for k in cubes}
-    den = np.zeros(w.nchan)
+    t_total, cells, refs = 0.0, [], []
     R = w.support_deg
     for _ in range(max_patches):
         x0 = int(rng.integers(0, g.nx - patch + 1))
         y0 = int(rng.integers(0, g.ny - patch + 1))
         ix, iy = np.meshgrid(np.arange(x0, x0 + patch), np.arange(y0, y0 + patch))
-        cells = (iy * g.nx + ix).ravel()
+        c = (iy * g.nx + ix).ravel()
         clon = g.lon0 + (np.array([x0, x0 + patch - 1]) - (g.nx - 1) / 2) * g.dlon
         clat = g.lat0 + (np.array([y0, y0 + patch - 1]) - (g.ny - 1) / 2) * g.dlat
         m = 1.5 * R
@@ -89,28 +86,40 @@ def cpu_baseline(w, cubes, budget_s=15.0, patch=32, max_patches=40, seed=7):
                          & (lon >= clon.min() - m / coslat) & (lon <= clon.max() + m / coslat))[0]
         rows = w.spectra.index_select(0, torch.from_numpy(sel).to(w.spectra.device)).cpu().numpy()
         t0 = time.perf_counter()
-        V, W, _ = oracle.grid_cells(lon[sel], lat[sel], rows, g, w.fwhm_deg, R, cells)
-        dt = time.perf_counter() - t0
-        t_total += dt
-        cells_done += cells.size
-        ok = ~np.isnan(V)
-        r = np.where(ok, V, 0.0)
-        den += (r * r).sum(0)
-        for k, cube in cubes.items():
-            idx = torch.from_numpy(cells).to(cube.device)
-            gv = cube.reshape(cube.shape[0], -1)[:, idx].cpu().numpy().astype(np.float64).T
-            assert np.array_equal(ok, ~np.isnan(gv)), k
-            d = np.where(ok, gv - V, 0.0)
-            num[k] += (d * d).sum(0)
+        V, W, _ = oracle.grid_cells(lon[sel], lat[sel], rows, g, w.fwhm_deg, R, c)
+        t_total += time.perf_counter() - t0
+        cells.append(c)
+        refs.append(V)
         if t_total >= budget_s:
             break
-    t_full = t_total * g.ncells / cells_done
-    return {"value": w.n * w.nchan / t_full, "unit": "sample*channel updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{cells_done} of {g.ncells} cells ({cells_done // (patch * patch)} random "
-                      f"{patch}x{patch}-cell patches), all {w.nchan} channels, FP64 bucketed "
-                      f"oracle, {t_total:.1f} s measured, whole-grid time extrapolated by cell "
-                      f"count ({t_full:.0f} s)"}, {k: np.sqrt(num[k] / den) for k in cubes}
+    return {"cells": np.concatenate(cells), "V": np.concatenate(refs), "t": t_total,
+            "cores": cores, "patch": patch, "patches": len(cells)}
+
+
+def cpu_baseline(w, samp):
+    """The oracle's rate on the sample, extrapolated to the whole grid."""
+    g = w.grid
+    done = samp["cells"].size
+    t_full = samp["t"] * g.ncells / done
+    return {"value": w.n * w.nchan / t_full, "unit": "sample*channel updates/s",
+            "cores": samp["cores"], "kind": "oracle",
+            "sample": f"{done} of {g.ncells} cells ({samp['patches']} random "
+                      f"{samp['patch']}x{samp['patch']}-cell patches), all {w.nchan} channels, "
+                      f"FP64 bucketed oracle, {samp['t']:.1f} s measured, whole-grid time "
+                      f"extrapolated by cell count ({t_full:.0f} s)"}
+
+
+def sampled_errors(cube, samp):
+    """Per-channel relative L2 error of a GPU cube [C, ny, nx] against the
+    oracle on the sampled cells (NaN patterns must agree)."""
+    V = samp["V"]
+    idx = torch.from_numpy(samp["cells"]).to(cube.device)
+    gv = cube.reshape(cube.shape[0], -1).index_select(1, idx).cpu().numpy().astype(np.float64).T
+    ok = ~np.isnan(V)
+    assert np.array_equal(ok, ~np.isnan(gv)), "NaN patterns differ from the oracle"
+    d = np.where(ok, gv - V, 0.0)
+    r = np.where(ok, V, 0.0)
+    return np.sqrt((d * d).sum(0) / (r * r).sum(0))
 
 
 def run_batch(args):
@@ -212,8 +221,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the low-precision forms")
-    ap.add_argument("--workload", default="drift_scan", choices=["drift_scan", "batch"],
-                    help="drift_scan: 9.12M samples x 1024 channels (default); batch: 64 fields")
+    ap.add_argument("--workload", default="drift_scan",
+                    choices=["drift_scan", "drift_scan_8192", "large", "batch"],
+                    help="drift_scan: 9.12M samples x 1024 channels -> 600 x 600 (default); "
+                         "drift_scan_8192: 1.976M x 8192 -> 400 x 400; large: 20.064M x 1024 -> "
+                         "3000 x 3000; batch: 64 fields")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a kernel that reads 1 GiB and writes 1 GiB first (reference "
                          "for the HBM byte counters)")
@@ -228,7 +240,9 @@ def main():
         run_batch(args)
         return
     t0 = time.perf_counter()
-    w = synth.drift_scan_1024(device=dev)
+    make = {"drift_scan": synth.drift_scan_1024, "drift_scan_8192": synth.drift_scan_8192,
+            "large": synth.drift_scan_large}[args.workload]
+    w = make(device=dev)
     torch.cuda.synchronize()
     log(f"synthesised {w.n} samples x {w.nchan} channels in {time.perf_counter() - t0:.1f} s")
     g = w.grid
@@ -279,51 +293,76 @@ def main():
     updates = w.n * w.nchan
     value = updates / (ms_step * 1e-3)
 
-    # the matrix-core precision forms on the same plan (encoding not timed)
+    # the oracle on sampled cells: the CPU baseline, and the reference for the
+    # errors of every form (computed right after each form, whose cube is then
+    # freed)
+    samp = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        samp = oracle_sample(w)
+        errs["f32"] = sampled_errors(cube, samp)
+        log(f"oracle sample: {samp['cells'].size} cells in {time.perf_counter() - t0:.1f} s")
+
+    # the matrix-core precision forms on the same plan (encoding not timed,
+    # reported beside for the plan-ordered encodings)
+    order_forms = {
+        "drift_scan": [("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
+                       ("bf16_split", hcg.HCG_BF16_SPLIT),
+                       ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED),
+                       ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT)],
+        "drift_scan_8192": [("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
+                            ("bf16_split", hcg.HCG_BF16_SPLIT)],
+        "large": [("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED),
+                  ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT)],
+    }[args.workload]
+    packed_forms = {
+        "drift_scan": [("f16_scaled", hcg.HCG_F16_SCALED), ("bf16_split", hcg.HCG_BF16_SPLIT),
+                       ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT), ("bf16", hcg.HCG_BF16),
+                       ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED)],
+        "drift_scan_8192": [("f16_scaled", hcg.HCG_F16_SCALED), ("bf16_split", hcg.HCG_BF16_SPLIT),
+                            ("bf16", hcg.HCG_BF16)],
+        "large": [("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT),
+                  ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED), ("f16_scaled", hcg.HCG_F16_SCALED)],
+    }[args.workload]
     forms = {}
-    cubes = {"f32": cube}
     if not args.no_forms:
+        if samp is not None and args.workload != "drift_scan":
+            del cube  # the FP32 cube's errors are taken; make room for the forms' cubes
+            torch.cuda.empty_cache()
         plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
-        for name, form in (("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
-                           ("bf16_split", hcg.HCG_BF16_SPLIT),
-                           ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED),
-                           ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT)):
-            enc, scale = hcg.hcg_quantize(w.spectra, form)
-            out = torch.empty_like(cube)
-            hcg.hcg_grid(plan, enc, out, dtype=form, chan_scale=scale)
+        out_cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=dev)
+
+        def time_form(run):
+            run()
             evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                    for _ in range(3)]
             for a, b in evs:
                 a.record(stream)
-                hcg.hcg_grid(plan, enc, out, dtype=form, chan_scale=scale)
+                run()
                 b.record(stream)
             torch.cuda.synchronize()
-            ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+            return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+        for name, form in order_forms:
+            enc, scale = hcg.hcg_quantize(w.spectra, form)
+            ms = time_form(lambda: hcg.hcg_grid(plan, enc, out_cube, dtype=form, chan_scale=scale))
             forms[name] = {"grid_ms": ms, "grid_updates_per_s": updates / (ms * 1e-3),
                            "speedup_vs_f32_grid": grid_avg / ms}
-            cubes[name] = out
             del enc
+            if samp is not None:
+                errs[name] = sampled_errors(out_cube, samp)
             log(f"form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 gather)")
         # the same forms encoded once in the plan's sorted order
-        for name, form in (("f16_scaled", hcg.HCG_F16_SCALED), ("bf16_split", hcg.HCG_BF16_SPLIT),
-                           ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT), ("bf16", hcg.HCG_BF16),
-                           ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED)):
+        for name, form in packed_forms:
             enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
             del enc, scale  # the timed call below reuses the cached allocation
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
             e1.record(stream)
-            out = torch.empty_like(cube)
-            hcg.hcg_grid_packed(plan, enc, out, dtype=form, chan_scale=scale)
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in range(3)]
-            for a, b in evs:
-                a.record(stream)
-                hcg.hcg_grid_packed(plan, enc, out, dtype=form, chan_scale=scale)
-                b.record(stream)
-            torch.cuda.synchronize()
-            ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+            ms = time_form(lambda: hcg.hcg_grid_packed(plan, enc, out_cube, dtype=form,
+                                                       chan_scale=scale))
             enc_ms = e0.elapsed_time(e1)
             key = "packed_" + name
             forms[key] = {"grid_ms": ms, "encode_ms": enc_ms,
@@ -335,11 +374,13 @@ def main():
                 forms[key]["hbm_bytes_per_launch"] = hbm
                 forms[key]["hbm_GBps"] = hbm / (ms * 1e-3) / 1e9
                 forms[key]["hbm_frac_of_peak"] = hbm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-            cubes[key] = out
             del enc
+            if samp is not None:
+                errs[key] = sampled_errors(out_cube, samp)
             log(f"plan-ordered form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 "
                 f"gather), encode {enc_ms:.2f} ms")
         plan.destroy()
+        del out_cube
     flops = 2.0 * stats["pairs"] * w.nchan
     achieved = flops / (grid_avg * 1e-3) / 1e12
     traffic = measured_traffic(w.name)
@@ -374,18 +415,16 @@ def main():
                      "traffic_GBps": (traffic / (grid_avg * 1e-3) / 1e9) if traffic else None,
                      "algorithmic_flops_per_launch": flops},
     }
-    if not args.no_cpu_baseline:
-        t0 = time.perf_counter()
-        cb, errs = cpu_baseline(w, cubes)
+    if samp is not None:
+        cb = cpu_baseline(w, samp)
         out["cpu_baseline"] = cb
         for k, e in errs.items():
             rec = forms.setdefault(k, {"grid_ms": grid_avg, "grid_updates_per_s":
                                        updates / (grid_avg * 1e-3), "speedup_vs_f32_grid": 1.0})
             rec["rel_l2_max_over_channels"] = float(e.max())
             rec["rel_l2_median_over_channels"] = float(np.median(e))
-        log(f"cpu baseline {cb['value']:.3g} /s on {cb['cores']} cores "
-            f"({time.perf_counter() - t0:.1f} s); sampled errors "
-            + ", ".join(f"{k} {e.max():.2e}" for k, e in errs.items()))
+        log(f"cpu baseline {cb['value']:.3g} /s on {cb['cores']} cores ({samp['t']:.1f} s); "
+            "sampled errors " + ", ".join(f"{k} {e.max():.2e}" for k, e in errs.items()))
     if forms:
         out["forms"] = forms
     print(json.dumps(out), flush=True)
