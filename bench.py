@@ -406,7 +406,8 @@ def main():
         "pair_updates_per_s": stats["pairs"] * w.nchan / (grid_avg * 1e-3),
         "pairs": stats["pairs"],
         "candidates": stats["candidates"],
-        "roofline": {"kernel": "hcg::k_gather_mfma<0, 2, true> (FP32, 512-channel slabs)",
+        "roofline": {"kernel": "hcg::k_gather_mfma<0, 2, true, false, false> (FP32, 512-channel "
+                               "slabs, input order, narrow support)",
                      "bound": "mfma", "achieved": achieved,
                      "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": traffic,
