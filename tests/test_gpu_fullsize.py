@@ -9,7 +9,8 @@ patches, the corners and the ends of the centre row.
 * drift scan, 1,976,000 samples x 8,192 channels, 400 x 400 cells: FP32,
   BF16, FP16 x scale, BF16 hi+lo;
 * large cube, 20,064,000 samples x 1,024 channels, 3000 x 3000 cells: FP32,
-  FP8 E4M3 x scale and FP8 E4M3 hi+lo x scale.
+  FP8 E4M3 x scale and FP8 E4M3 hi+lo x scale;
+* the 64-field batch (one persistent launch), every field.
 
 Per-channel relative L2 over the sampled cells, tolerances as in
 test_gpu_precision.py (FP32 1e-5); W map elementwise 1e-6."""
@@ -93,4 +94,34 @@ def test_large_cube_full_size():
     _check(w, [hcg.HCG_F32, hcg.HCG_FP8E4M3_SCALED, hcg.HCG_FP8E4M3_SPLIT], seed=14,
            packed=[hcg.HCG_FP8E4M3_SPLIT, hcg.HCG_F16_SCALED])
     del w
+    torch.cuda.empty_cache()
+
+
+def test_batch_64_fields_full_size():
+    """The 64-field batch as bench.py runs it (one persistent launch, tuned
+    and graph-captured), every field checked on a sampled patch and its
+    corners."""
+    ws = synth.batch_fields(device=DEV)
+    print(f"batch: {len(ws)} fields, {sum(w.n * w.nchan for w in ws):.4g} sample*channels",
+          flush=True)
+    b = hcg.hcg_plan_batch([(w.lon, w.lat, w.grid, w.fwhm_deg, w.support_deg) for w in ws])
+    cubes = [torch.empty((w.nchan, w.grid.ny, w.grid.nx), dtype=torch.float32, device=DEV)
+             for w in ws]
+    wts = [torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=DEV) for w in ws]
+    hcg.hcg_grid_batch(b, [w.spectra for w in ws], cubes, wts)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for f, w in enumerate(ws):
+        groups = sample_cells(w.grid, seed=100 + f, patches=1, patch=6)
+        cells = np.concatenate(groups)
+        ref = [sampled_oracle(w, c) for c in groups]
+        Vr = np.concatenate([v for v, _ in ref])
+        Wr = np.concatenate([x for _, x in ref])
+        V, Wg = gather_cells(cubes[f], wts[f], cells)
+        e = assert_cube_close(V.T, Vr.T, TOL[hcg.HCG_F32], f"batch {w.name}")
+        assert_weights_close(Wg, Wr)
+        worst = max(worst, float(e.max()))
+    print(f"  all fields: max per-channel rel L2 {worst:.2e}", flush=True)
+    b.destroy()
+    del cubes, wts, ws
     torch.cuda.empty_cache()
