@@ -125,7 +125,7 @@ hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
   hcg_status st = launch_batch_reset(b->d_ctl, stream);
   if (st != HCG_OK) return st;
   bool wide = false;
-  for (const GatherArgs& f : b->h_fields) wide = wide || !(f.c2R < 1e-2);
+  for (const GatherArgs& f : b->h_fields) wide = wide || !(f.c2R < kNarrowChord2);
   return launch_batch(b->qw, wide, b->d_fields, b->d_segs, b->d_ctl, b->nblocks, stream);
 }
 

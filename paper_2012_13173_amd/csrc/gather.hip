@@ -59,12 +59,15 @@ __device__ __forceinline__ double chord2(const CellVec& c, const double4& v) {
 // d^2 = 4 asin^2(chord / 2) = 2 sum_n c2^n / (n^2 binom(2n, n))
 //     = c2 (1 + c2/12 + c2^2/90 + c2^3/560 + c2^4/3150 + c2^5/16632 + ...);
 // six terms leave a relative error below 2e-17 for c2 < 1e-2 (d < 5.7 deg),
-// the arcsine beyond.
-// kWide = false: the caller guarantees c2 < 1e-2 (a support radius below
-// 5.7 deg), which keeps the arcsine and its registers out of the kernel.
+// the arcsine beyond; three terms leave one below 2e-15 for c2 < 1e-4
+// (d < 0.57 deg).
+// kWide = false: the caller guarantees c2 < 1e-4 (a support radius below
+// 0.57 deg, every configuration here), which keeps the longer series, the
+// arcsine and their registers out of the kernel.
 template <bool kWide = true>
 __device__ __forceinline__ double dist2_from_chord2(double c2) {
-  if (!kWide || c2 < 1e-2)
+  if (!kWide) return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0)));
+  if (c2 < 1e-2)
     return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
            c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
   const double d = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
@@ -72,10 +75,12 @@ __device__ __forceinline__ double dist2_from_chord2(double c2) {
 }
 
 // FP32 weight of a pair inside the support: the exponent -d^2 log2(e) /
-// (2 sigma^2) is formed in FP64 and evaluated with exp2f.
+// (2 sigma^2) is formed in FP64 and evaluated with the hardware base-2
+// exponential (v_exp_f32; the exponent lies in [-6.5, 0] for a 3 sigma
+// support and [-18, 0] for 5 sigma, so no result is subnormal).
 template <bool kWide>
 __device__ __forceinline__ float pair_weight(double c2, double wscale) {
-  return exp2f((float)(dist2_from_chord2<kWide>(c2) * wscale));
+  return __builtin_amdgcn_exp2f((float)(dist2_from_chord2<kWide>(c2) * wscale));
 }
 
 // bit q (q < 8) of the result: any of bits 4q .. 4q + 3 of x
@@ -1050,9 +1055,9 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   const int64_t blocks = slabs * a.tiles_per_xcd * 8;
   if (blocks > INT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
   const dim3 grid((unsigned)blocks), block(256);
-  // supports below 5.7 deg (squared chord < 1e-2) take the kernels without
-  // the arcsine branch of the distance
-  const bool wide = !(a.c2R < 1e-2);
+  // supports below 0.57 deg (squared chord < 1e-4) take the kernels with the
+  // short distance series
+  const bool wide = !(a.c2R < kNarrowChord2);
 #define HCG_MFMA(QW, VEC)                                                                \
   do {                                                                                   \
     if (wide) k_gather_mfma<kForm, QW, VEC, kPacked, true><<<grid, block, 0, stream>>>(a); \

@@ -214,6 +214,9 @@ static_assert(offsetof(GatherArgs, sentinel) == 36 && offsetof(GatherArgs, C) ==
 // item base + s * ntiles + t being slab s of tile t.  Segments are listed in
 // increasing base.  The persistent kernel reads device arrays of GatherArgs
 // (one per field) and BatchSeg, and a control block of kBatchCtl words.
+// Largest squared support chord of the narrow-support gather kernels.
+constexpr double kNarrowChord2 = 1e-4;
+
 struct BatchSeg {
   uint32_t base, ntiles, slabs, field;
 };
@@ -222,8 +225,9 @@ constexpr int kBatchCtl = 16;
 GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
                          float* wmap);
 hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream);
-// wide: some field's support has a squared chord >= 1e-2 (radius >= 5.7
-// deg), so the kernel must carry the arcsine branch of the distance.
+// wide: some field's support has a squared chord >= 1e-4 (radius >= 0.57
+// deg), so the kernel must carry the long series and the arcsine branch of
+// the distance.
 hcg_status launch_batch(int qw, bool wide, const GatherArgs* fields, const BatchSeg* segs,
                         uint32_t* ctl, int nblocks, hipStream_t stream);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
