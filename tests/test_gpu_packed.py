@@ -67,7 +67,8 @@ def test_packed_encoding_is_the_sorted_grouped_encoding(n, nchan):
     plan.destroy()
 
 
-@pytest.mark.parametrize("n,nchan", [(15_001, 300), (15_003, 67), (14_999, 1024), (15_000, 20)])
+@pytest.mark.parametrize("n,nchan", [(15_001, 300), (15_003, 67), (14_999, 1024), (15_000, 20),
+                                    (15_005, 3), (15_002, 1)])
 def test_packed_forms_against_oracle(n, nchan):
     w = synth.small_cube(n=n, nchan=nchan, nx=29, ny=19)
     Vr, Wr, _ = run_oracle(w)

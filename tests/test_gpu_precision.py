@@ -42,7 +42,7 @@ def _grid_form(w, plan, form):
     return cube.cpu().numpy(), W.cpu().numpy()
 
 
-@pytest.mark.parametrize("nchan", [300, 67, 1024])
+@pytest.mark.parametrize("nchan", [300, 67, 1024, 5, 1])
 def test_forms_against_oracle(nchan):
     w = synth.small_cube(n=15_000, nchan=nchan, nx=29, ny=19)
     Vr, Wr, _ = run_oracle(w)
