@@ -67,6 +67,17 @@ def test_argument_errors_before_device_work():
     assert lib.hcg_sort_keys(vp(1), 4, 0, vp(2), vp(3), None) == hcg.HCG_E_ARG
     assert lib.hcg_sort_keys(vp(1), 4, 33, vp(2), vp(3), None) == hcg.HCG_E_ARG
     assert lib.hcg_sort_keys(vp(1), 4, 8, vp(1), vp(3), None) == hcg.HCG_E_ARG
+    # encoders and the plan-ordered gather
+    assert lib.hcg_quantize(vp(1), -1, 4, hcg.HCG_BF16, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_quantize(vp(1), 4, 4, hcg.HCG_F32, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_quantize(vp(1), 4, 4, hcg.HCG_FP8E4M3_SPLIT, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_quantize_packed(None, vp(1), 4, hcg.HCG_BF16, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_quantize_packed(vp(12345), vp(1), 4, hcg.HCG_BF16, vp(1), None, None) == hcg.HCG_E_STATE
+    assert lib.hcg_grid_packed(None, vp(1), 4, hcg.HCG_BF16, None, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_grid_packed(vp(12345), vp(1), 4, hcg.HCG_BF16, None, vp(1), None, None) == hcg.HCG_E_STATE
+    nbytes = ctypes.c_int64()
+    assert lib.hcg_packed_bytes(None, 4, hcg.HCG_BF16, ctypes.byref(nbytes)) == hcg.HCG_E_ARG
+    assert lib.hcg_packed_bytes(vp(12345), 4, hcg.HCG_BF16, ctypes.byref(nbytes)) == hcg.HCG_E_STATE
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
