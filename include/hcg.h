@@ -173,7 +173,8 @@ hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dty
  *               scale[c] = 2^ceil(log2(max_n |x[n][c]| / top)) with top =
  *               2^14 (FP16) or 448 (the largest E4M3 value); 1 for an
  *               all-zero channel.  NULL for the unscaled forms.
- * Every element is rounded to nearest even (E4M3 saturates at 448).
+ * Every element is rounded to nearest even (the scales keep every x / scale
+ * within the E4M3 range, +-448).
  * Asynchronous on hip_stream.  Errors: HCG_E_ARG (shape, NULL pointer,
  * dtype not a low-precision form, missing chan_scale), HCG_E_DEVICE.
  */

@@ -229,21 +229,12 @@ struct FormTraits<kFP8S> { static constexpr int kK = 32; };
 template <>
 struct FormTraits<kFP8Split> { static constexpr int kK = 32; };
 
-// E4M3 codes of the weights through the conversion instructions of gfx950
-// (OCP E4M3, round to nearest even): equal to f32_to_e4m3 / e4m3_to_f32 over
-// the whole range the weights take, subnormals included, and one
-// instruction each instead of a dozen.
-__device__ __forceinline__ uint32_t e4m3_cvt(float x) {
-  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xFFu;
-}
-__device__ __forceinline__ float e4m3_cvt_to_f32(uint32_t c) {
-  return __builtin_amdgcn_cvt_f32_fp8((int)c, 0);
-}
-
+// E4M3 codes of the weights (256 w <= 256, and its remainder) go through the
+// conversion instructions (f32_to_e4m3_cvt), one instruction each.
 template <int kForm>
 __device__ __forceinline__ uint32_t enc_w(float w) {
   if (kForm == kF16S) return f32_to_f16(w);
-  if (is_fp8(kForm)) return e4m3_cvt(w * kW8Scale);
+  if (is_fp8(kForm)) return f32_to_e4m3_cvt(w * kW8Scale);
   return f32_to_bf16(w);
 }
 template <int kForm>
@@ -469,7 +460,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                   l = f32_to_bf16(wf - dec_w<kForm>(h));
                   eff += (double)bf16_to_f32(l);
                 } else if (kForm == kFP8Split) {
-                  l = e4m3_cvt(wf * kW8Scale - dec_w<kForm>(h));
+                  l = f32_to_e4m3_cvt(wf * kW8Scale - dec_w<kForm>(h));
                   eff += (double)e4m3_cvt_to_f32(l);
                 }
                 wsum += (double)wf;

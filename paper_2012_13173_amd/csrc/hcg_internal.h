@@ -139,6 +139,17 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
   return (c & 0x80u) ? -v : v;
 }
 
+// The same two conversions through the gfx950 conversion instructions (OCP
+// E4M3, round to nearest even): equal to f32_to_e4m3 / e4m3_to_f32 for every
+// |x| <= 448, subnormals included (checked on the device over that range),
+// one instruction each.  Callers keep their arguments within +-448.
+__device__ __forceinline__ uint32_t f32_to_e4m3_cvt(float x) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xFFu;
+}
+__device__ __forceinline__ float e4m3_cvt_to_f32(uint32_t c) {
+  return __builtin_amdgcn_cvt_f32_fp8((int)c, 0);
+}
+
 }  // namespace hcg
 
 // The plan object behind hcg_plan_t.  Every device array lives in one arena.

@@ -98,11 +98,11 @@ __global__ void __launch_bounds__(256) k_encode(const float* __restrict__ in, in
       ((uint16_t*)out)[i] = (uint16_t)f32_to_f16(x / scale[c]);
     } else if (kDtype == HCG_FP8E4M3_SPLIT) {
       const float y = x / scale[c];
-      const uint32_t hi = f32_to_e4m3(y);
+      const uint32_t hi = f32_to_e4m3_cvt(y);
       ((uint8_t*)out)[i] = (uint8_t)hi;
-      ((uint8_t*)out)[total + i] = (uint8_t)f32_to_e4m3(y - e4m3_to_f32(hi));
+      ((uint8_t*)out)[total + i] = (uint8_t)f32_to_e4m3_cvt(y - e4m3_cvt_to_f32(hi));
     } else {
-      ((uint8_t*)out)[i] = (uint8_t)f32_to_e4m3(x / scale[c]);
+      ((uint8_t*)out)[i] = (uint8_t)f32_to_e4m3_cvt(x / scale[c]);
     }
   }
 }
@@ -118,8 +118,8 @@ __device__ __forceinline__ uint32_t encode_elem(float x, uint32_t* lo) {
     return hi;
   }
   if (kDtype == HCG_F16_SCALED) return f32_to_f16(x);
-  const uint32_t hi = f32_to_e4m3(x);
-  if (kDtype == HCG_FP8E4M3_SPLIT) *lo = f32_to_e4m3(x - e4m3_to_f32(hi));
+  const uint32_t hi = f32_to_e4m3_cvt(x);
+  if (kDtype == HCG_FP8E4M3_SPLIT) *lo = f32_to_e4m3_cvt(x - e4m3_cvt_to_f32(hi));
   return hi;
 }
 
