@@ -129,3 +129,16 @@ def test_grid_argument_errors():
     assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, hcg.HCG_F32, vp(spec.data_ptr()), vp(cube.data_ptr()), None, None) == hcg.HCG_E_ARG
     plan.destroy()
     assert lib.hcg_grid(plan.handle, vp(spec.data_ptr()), 4, 0, None, vp(cube.data_ptr()), None, None) in (hcg.HCG_E_ARG, hcg.HCG_E_STATE)
+
+
+@pytest.mark.parametrize("n", [1, 5, 9, 64])
+@pytest.mark.parametrize("nchan", [1, 40])
+def test_tiny_sample_counts(n, nchan):
+    # a handful of samples: most cells are empty, the candidate lists are
+    # shorter than one staged block (and than one group of 8 sorted samples)
+    w = synth.small_cube(n=n, nchan=nchan, nx=12, ny=10, cell_arcmin=1.0, pad_arcmin=-1.0,
+                         seed=300 + n)
+    V, W = run_gpu(w)
+    Vr, Wr, _ = run_oracle(w)
+    assert_cube_close(V, Vr, TOL_F32, f"n={n} C={nchan}")
+    assert_weights_close(W, Wr)

@@ -172,3 +172,16 @@ def test_packed_argument_errors():
     assert nbytes.value == 2 * ((2001 + 7) // 8) * 8 * 32
     torch.cuda.synchronize()
     plan.destroy()
+
+
+@pytest.mark.parametrize("n", [1, 5, 9, 64])
+def test_packed_tiny_sample_counts(n):
+    w = synth.small_cube(n=n, nchan=24, nx=12, ny=10, cell_arcmin=1.0, pad_arcmin=-1.0,
+                         seed=400 + n)
+    Vr, Wr, _ = run_oracle(w)
+    plan = _plan(w)
+    for name, (form, tol) in FORMS.items():
+        V, W = _grid_packed(w, plan, form)
+        assert_cube_close(V, Vr, tol, f"packed {name} n={n}")
+        assert_weights_close(W, Wr)
+    plan.destroy()
