@@ -389,6 +389,29 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
       for (int ks = 0; ks < kEarly; ++ks) load_b(ks);
     }
+    // input-order 16-bit and FP8 spectra: the first k-step's raw row pieces
+    // are loaded before the weights as well (repacked where they are used)
+    constexpr bool kEarlyRaw = !kPacked && kVec && (kForm == kBF16 || kForm == kF16S ||
+                                                    kForm == kFP8S);
+    uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
+    uint32_t e8[(kEarlyRaw && is_fp8(kForm)) ? kQW : 1][8];
+    if constexpr (kEarlyRaw) {
+#pragma unroll
+      for (int h = 0; h < kQW; ++h) {
+        const int64_t ch = my_ch + 64 * h;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int64_t row = s_row[8 * (lane >> 4) + t];
+          if constexpr (is_fp8(kForm)) {
+            const uint8_t* src = (const uint8_t*)a.spec + row * C + ch;
+            e8[h][t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
+          } else {
+            const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
+            e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+          }
+        }
+      }
+    }
     // FP32: the first kDepth k-steps' rows are loaded before the weights too
     constexpr int kDepth = kWide ? 4 : 6;
     floatx4 b[kForm == kF32 ? kDepth : 1][kQW];
@@ -601,7 +624,9 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
               for (int t = 0; t < 8; ++t) {
                 const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
                 const uint8_t* src = spec + row * C + ch;
-                if (kVec) {
+                if (kEarlyRaw && ks == 0) {
+                  d[t] = e8[kEarlyRaw ? h : 0][t];
+                } else if (kVec) {
                   d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
                 } else {
                   d[t] = 0u;
@@ -636,7 +661,9 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
               for (int t = 0; t < 8; ++t) {
                 const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
                 const uint16_t* src = spec + row * C + ch;
-                if (kVec) {
+                if (kEarlyRaw && ks == 0 && plane == 0) {
+                  d[t] = e16[kEarlyRaw ? h : 0][t];
+                } else if (kVec) {
                   d[t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
                 } else {
                   const uint32_t e0 = (ch + 0 < C) ? src[0] : 0u, e1 = (ch + 1 < C) ? src[1] : 0u;
