@@ -296,7 +296,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   uint32_t* s_nz = sm.nz;
   double* s_Wt = sm.Wt;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const GridGeom& g = a.g;
   const int64_t C = a.C;
@@ -322,6 +323,10 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   uint32_t cur = 0;
   const int64_t c_w = (int64_t)slab * (256 * kQW) + wave * (64 * kQW);
   const int64_t my_ch = c_w + 4 * (lane & 15);  // + 64 h + q
+  // FP32: 64-channel groups of this wave that hold a channel < C (uniform);
+  // the others issue no products (a wave past the last channel still
+  // computes its cell block's weights for the others)
+  const int hlive = (int)min<int64_t>(kQW, max<int64_t>(0, (C - c_w + 63) / 64));
 
   float* sA32 = (float*)s_Araw;                // [4][16][64]
   uint4* sA16 = s_Araw;                        // [4][kNS][64] (+ lo plane after)
@@ -538,6 +543,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
             const float av = sA32[(cb * kNS + ks) * 64 + lane];
 #pragma unroll
             for (int h = 0; h < kQW; ++h) {
+              if (h >= hlive) continue;
               acc[cb][4 * h + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].x, acc[cb][4 * h + 0], 0, 0, 0);
               acc[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].y, acc[cb][4 * h + 1], 0, 0, 0);
               acc[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].z, acc[cb][4 * h + 2], 0, 0, 0);
