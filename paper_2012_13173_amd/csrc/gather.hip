@@ -4,15 +4,22 @@
 //
 // Work decomposition: one workgroup per 8 x 8 tile of output cells (and per
 // 256- or 512-channel slab for many channels).  The tile's candidate samples
-// come from the plan's sorted-sample ranges and are staged in blocks of 64:
-//   1. weights: FP64 haversine distance of every (cell, candidate) pair of
-//      the block, exact support test, FP64 Gaussian weight, rounded to the
-//      operand type of the form; FP64 sums of the weights per cell;
+// come from the plan's sorted-sample ranges and are staged in blocks of 64,
+// one block ahead:
+//   1. weights: FP64 great-circle distance of every (cell, candidate) pair
+//      of the block that a coarse per-cell-block test cannot rule out (from
+//      the chord of the unit vectors), exact support test, Gaussian weight
+//      (exponent in FP64; exp2 in FP32 for the matrix-core forms, in FP64 for
+//      the few-channel path), rounded to the operand type of the form; FP64
+//      sums of the weights per cell;
 //   2. accumulation: for many channels the block is a dense contraction
 //      U[cells x channels] += Wt[cells x 64] . S[64 x channels] done on the
 //      matrix cores with FP32 accumulation -- FP32 operands
 //      (v_mfma_f32_16x16x4_f32) or BF16 / FP16 / FP8 operands (16x16x32),
 //      skipping every 16-cell x k-step sub-block whose weights are all zero;
+//      the spectra are read in the caller's sample order through the plan's
+//      permutation, or (low-precision forms) from an encoding in the plan's
+//      sorted order whose groups of 8 samples are ready-made B operands;
 //      for a few FP32 channels each lane owns one cell and accumulates in
 //      FP64;
 //   3. epilogue: V = U / W~ (W~ the sum of the weights actually multiplied,
