@@ -122,6 +122,78 @@ def sampled_errors(cube, samp):
     return np.sqrt((d * d).sum(0) / (r * r).sum(0))
 
 
+def run_host_stream(w, slabs, samp, pageable_slab=0):
+    """hcg_grid_host with the spectra and the cube in host memory: wall time
+    per cube (plan built beforehand, not timed) and the host-to-device rate it
+    implies, beside the rate of one plain 4 GiB page-locked host-to-device
+    copy (the bound of the stream).  Page-locked: the first channels that fit
+    20 GB of spectra (torch rounds page-locked blocks up to a power of two, and
+    the page-locked total is limited), once per slab width; pageable: the
+    whole cube, once."""
+    g = w.grid
+    dev = w.spectra.device
+    nch = int(min(w.nchan, max(16, 20e9 // (4 * w.n) // 16 * 16)))
+    t0 = time.perf_counter()
+    spec_h = torch.empty((w.n, nch), dtype=torch.float32, pin_memory=True)
+    spec_h.copy_(w.spectra[:, :nch])
+    cube_h = torch.empty((nch, g.ny, g.nx), dtype=torch.float32, pin_memory=True)
+    W_h = torch.empty((g.ny, g.nx), dtype=torch.float32, pin_memory=True)
+    log(f"host stream: page-locked copy of {nch} channels made in "
+        f"{time.perf_counter() - t0:.1f} s")
+    chunk = min(spec_h.numel(), 1 << 30)
+    dst = torch.empty(chunk, dtype=torch.float32, device=dev)
+    src = spec_h.view(-1)[:chunk]
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 4.0 * chunk / (time.perf_counter() - t0) / 1e9
+    del dst
+    samp_h = None
+    if samp is not None:
+        samp_h = dict(samp, V=samp["V"][:, :nch])
+    plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
+
+    def timed(spec, cube, W, cs, reps):
+        hcg.hcg_grid_host(plan, spec, cube, W, slab=cs)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            hcg.hcg_grid_host(plan, spec, cube, W, slab=cs)
+            ts.append(time.perf_counter() - t0)
+        ms = 1e3 * float(np.mean(ts))
+        C = spec.shape[1]
+        h2d = 4.0 * w.n * C
+        return {"nchan": C, "slab": cs, "ms": ms, "updates_per_s": w.n * C / (ms * 1e-3),
+                "h2d_bytes": h2d, "d2h_bytes": 4.0 * C * g.ncells,
+                "h2d_GBps": h2d / (ms * 1e-3) / 1e9,
+                "frac_of_plain_copy": h2d / (ms * 1e-3) / 1e9 / copy_gbs}
+
+    out = {"plain_h2d_copy_GBps": copy_gbs, "page_locked": [], "pageable": None}
+    for cs in slabs:
+        rec = timed(spec_h, cube_h, W_h, cs, 2)
+        if samp_h is not None:
+            rec["rel_l2_max_over_channels"] = float(sampled_errors(cube_h, samp_h).max())
+        out["page_locked"].append(rec)
+        log(f"host stream, page-locked, slabs of {cs}: {rec['ms']:.1f} ms per {nch}-channel "
+            f"cube, host-to-device {rec['h2d_GBps']:.1f} GB/s (plain copy {copy_gbs:.1f} GB/s)")
+    del spec_h, cube_h
+    if pageable_slab:
+        spec_p = w.spectra.cpu()
+        cube_p = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32)
+        rec = timed(spec_p, cube_p, W_h, pageable_slab, 1)
+        if samp is not None:
+            rec["rel_l2_max_over_channels"] = float(sampled_errors(cube_p, samp).max())
+        out["pageable"] = rec
+        log(f"host stream, pageable, slabs of {pageable_slab}: {rec['ms']:.1f} ms per "
+            f"{w.nchan}-channel cube, host-to-device {rec['h2d_GBps']:.1f} GB/s")
+        del spec_p, cube_p
+    plan.destroy()
+    return out
+
+
 def run_batch(args):
     """64 independent fields of uneven size: one batched launch (persistent
     kernel, hipGraph replay, autotuned) against 64 separate plan + grid calls
@@ -226,6 +298,9 @@ def main():
                     help="drift_scan: 9.12M samples x 1024 channels -> 600 x 600 (default); "
                          "drift_scan_8192: 1.976M x 8192 -> 400 x 400; large: 20.064M x 1024 -> "
                          "3000 x 3000; batch: 64 fields")
+    ap.add_argument("--host-stream", default="",
+                    help="comma-separated slab widths: also time hcg_grid_host (spectra and "
+                         "cube in page-locked host memory) for each")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a kernel that reads 1 GiB and writes 1 GiB first (reference "
                          "for the HBM byte counters)")
@@ -303,6 +378,10 @@ def main():
         samp = oracle_sample(w)
         errs["f32"] = sampled_errors(cube, samp)
         log(f"oracle sample: {samp['cells'].size} cells in {time.perf_counter() - t0:.1f} s")
+
+    host_stream = None
+    if args.host_stream:
+        host_stream = run_host_stream(w, [int(x) for x in args.host_stream.split(",")], samp)
 
     # the matrix-core precision forms on the same plan (encoding not timed,
     # reported beside for the plan-ordered encodings)
@@ -428,6 +507,8 @@ def main():
             "sampled errors " + ", ".join(f"{k} {e.max():.2e}" for k, e in errs.items()))
     if forms:
         out["forms"] = forms
+    if host_stream:
+        out["host_stream"] = host_stream
     print(json.dumps(out), flush=True)
 
 

@@ -223,6 +223,38 @@ hcg_status hcg_grid_packed(hcg_plan_t plan, const void* packed, int64_t nchan, h
                            const float* chan_scale, float* cube, float* weights,
                            void* hip_stream);
 
+/*
+ * hcg_grid_host -- hcg_grid (FP32 form) for spectra and a cube held in host
+ * memory, streamed through the device in channel slabs: the overlap of
+ * host-device copies with the gridding on separate streams that Section 5
+ * names as future work, so that a cube larger than device memory can be
+ * made with one plan.
+ *
+ *   spectra_host  host float [n][nchan] in the sample order given to
+ *                 hcg_plan, channel-fastest.
+ *   nchan         >= 1.
+ *   slab_chan     channels per slab; 0 picks 512 (fewer if one slab of
+ *                 spectra or of the cube would exceed 4 GiB).  The last slab
+ *                 may be shorter.
+ *   cube_host     host float [nchan][ny][nx]: V as hcg_grid writes it.
+ *   weights_host  host float [ny][nx] or NULL: W as hcg_grid writes it.
+ *
+ * Slab s + 1 is copied in on a stream of the library's while slab s is
+ * gridded on hip_stream and slab s - 1 is copied out on a third stream, each
+ * through two device buffers of slab_chan channels (2 slab_chan (n + nx ny)
+ * floats of device memory, plus nx ny for W, allocated per call and freed on
+ * return).  The copies overlap the gridding only for page-locked host memory
+ * (hipHostMalloc); pageable memory gives the same result, slower.
+ * Synchronous: returns after the last slab has reached cube_host (the work
+ * queued earlier on hip_stream runs first).  Errors: HCG_E_ARG (NULL pointer,
+ * nchan < 1, slab_chan < 0), HCG_E_STATE (not a live plan), HCG_E_NOMEM (the
+ * slab buffers do not fit), HCG_E_DEVICE (a copy or launch failed; the
+ * streams are drained before the call returns).
+ */
+hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
+                         int64_t slab_chan, float* cube_host, float* weights_host,
+                         void* hip_stream);
+
 /* hcg_destroy -- wait for the device, then free the plan.  NULL is a no-op
  * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE. */
 hcg_status hcg_destroy(hcg_plan_t plan);

@@ -84,7 +84,7 @@ EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_pl
             "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
             "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
             "hcg_destroy_batch", "hcg_get_batch_info", "hcg_quantize_packed", "hcg_grid_packed",
-            "hcg_packed_bytes"]
+            "hcg_packed_bytes", "hcg_grid_host"]
 
 _lib = None
 
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
     lib.hcg_quantize_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp]
     lib.hcg_grid_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
     lib.hcg_packed_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(i64)]
+    lib.hcg_grid_host.argtypes = [vp, vp, i64, i64, vp, vp, vp]
     lib.hcg_plan_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(FieldDescC),
                                    ctypes.POINTER(OptsC), vp]
     lib.hcg_grid_batch.argtypes = [vp, ctypes.POINTER(FieldDataC), vp]
@@ -232,6 +233,37 @@ def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None
                          _dptr(cube, torch.float32, "cube"),
                          _dptr(weights, torch.float32, "weights"), _stream(stream))
     _check(st, "hcg_grid")
+
+
+def _hptr(t, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cpu":
+        raise TypeError(f"{name} must be a CPU tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def hcg_grid_host(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None,
+                  slab: int = 0, stream=None) -> None:
+    """Grids host spectra [n, C] into the host cube [C, ny, nx] (and weights
+    [ny, nx]) in channel slabs streamed through the device (FP32 form).
+    Synchronous.  Page-locked tensors (``pin_memory()``) let the copies
+    overlap the gridding."""
+    if spectra.dim() != 2:
+        raise ValueError("spectra must be [n, nchan]")
+    n, C = (int(x) for x in spectra.shape)
+    if n != int(plan.info()["n"]):
+        raise ValueError(f"spectra has {n} rows, the plan {int(plan.info()['n'])} samples")
+    g = plan.grid
+    if tuple(cube.shape) != (C, g.ny, g.nx):
+        raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
+    if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
+        raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
+    st = load().hcg_grid_host(plan.handle, _hptr(spectra, "spectra"), C, int(slab),
+                              _hptr(cube, "cube"), _hptr(weights, "weights"), _stream(stream))
+    _check(st, "hcg_grid_host")
 
 
 def hcg_quantize(spectra: torch.Tensor, dtype: int, stream=None):

@@ -1,0 +1,153 @@
+"""GPU parity of hcg_grid_host: spectra and cube in host memory, gridded in
+channel slabs streamed through the device (the copy/compute overlap on
+streams that Section 5 names as future work).
+
+Each streamed slab must equal, bit for bit, hcg_grid run on the device over
+the same channels (the same kernels on the same inputs), and the whole cube
+must agree with the FP64 oracle to the FP32 bound of 1e-5.  Cases: ragged last
+slab, one-channel slabs, a slab wider than the cube, pageable and page-locked
+host memory, W omitted, and a full-size sample count with sampled cells."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_13173_amd as hcg
+import synth
+from tests.gridcheck import (assert_cube_close, assert_weights_close, gather_cells, run_oracle,
+                             sample_cells, sampled_oracle)
+
+pytestmark = pytest.mark.gpu
+TOL_F32 = 1e-5
+
+
+def _plan(w):
+    dev = torch.device("cuda:0")
+    return hcg.hcg_plan(w.lon.to(dev), w.lat.to(dev), w.grid, w.fwhm_deg, w.support_deg,
+                        nside=w.nside)
+
+
+def _host(shape, pinned):
+    t = torch.empty(shape, dtype=torch.float32, pin_memory=pinned)
+    t.fill_(-7.0)  # every element must be overwritten
+    return t
+
+
+def _device_slabs(plan, w, slab):
+    """hcg_grid on the device, one call per slab of channels."""
+    dev = torch.device("cuda:0")
+    C, g = w.nchan, w.grid
+    cs = slab if slab else C
+    V = np.empty((C, g.ny, g.nx), dtype=np.float32)
+    W = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev)
+    for c0 in range(0, C, cs):
+        cn = min(cs, C - c0)
+        spec = w.spectra[:, c0:c0 + cn].contiguous().to(dev)
+        cube = torch.empty((cn, g.ny, g.nx), dtype=torch.float32, device=dev)
+        hcg.hcg_grid(plan, spec, cube, W if c0 == 0 else None)
+        V[c0:c0 + cn] = cube.cpu().numpy()
+    torch.cuda.synchronize()
+    return V, W.cpu().numpy()
+
+
+def _streamed(plan, w, slab, pinned=True, with_weights=True):
+    g = w.grid
+    spec = w.spectra.contiguous()
+    if pinned:
+        spec = spec.pin_memory()
+    cube = _host((w.nchan, g.ny, g.nx), pinned)
+    W = _host((g.ny, g.nx), pinned) if with_weights else None
+    hcg.hcg_grid_host(plan, spec, cube, W, slab=slab)
+    return cube.numpy(), (W.numpy() if with_weights else None)
+
+
+@pytest.mark.parametrize("nchan,slab,pinned", [
+    (300, 64, True),    # 4 full slabs and a ragged one of 44 channels
+    (300, 64, False),   # the same from pageable memory
+    (37, 1, True),      # one channel per slab (the one-lane-per-cell kernel)
+    (70, 9, True),      # slabs that switch between the two accumulation kernels
+    (20, 0, True),      # default slab, wider than the cube
+    (600, 300, True),   # slabs above 256 channels
+])
+def test_streamed_equals_device_slabs(nchan, slab, pinned):
+    w = synth.small_cube(n=12_000, nchan=nchan, nx=29, ny=19)
+    plan = _plan(w)
+    V, W = _streamed(plan, w, slab, pinned)
+    Vd, Wd = _device_slabs(plan, w, slab if slab else 512)
+    plan.destroy()
+    assert np.array_equal(V, Vd, equal_nan=True), "streamed cube differs from hcg_grid"
+    assert np.array_equal(W, Wd)
+    Vr, Wr, _ = run_oracle(w)
+    assert_cube_close(V, Vr, TOL_F32, f"C={nchan} slab={slab}")
+    assert_weights_close(W, Wr)
+
+
+def test_streamed_without_weights_and_repeated():
+    w = synth.small_cube(n=9000, nchan=50, nx=23, ny=31, lat_c=-60.0)
+    plan = _plan(w)
+    V1, _ = _streamed(plan, w, 16, with_weights=False)
+    V2, W2 = _streamed(plan, w, 7)
+    plan.destroy()
+    Vr, Wr, _ = run_oracle(w)
+    assert_cube_close(V1, Vr, TOL_F32, "no W")
+    assert_cube_close(V2, Vr, TOL_F32, "slab 7")
+    assert_weights_close(W2, Wr)
+
+
+def test_streamed_after_work_on_the_stream():
+    # work queued earlier on the caller's stream (the plan build) comes first
+    w = synth.small_cube(n=10_000, nchan=33, nx=20, ny=20)
+    s = torch.cuda.Stream()
+    dev = torch.device("cuda:0")
+    with torch.cuda.stream(s):
+        plan = hcg.hcg_plan(w.lon.to(dev), w.lat.to(dev), w.grid, w.fwhm_deg, w.support_deg,
+                            nside=w.nside, stream=s)
+        cube = _host((w.nchan, w.grid.ny, w.grid.nx), True)
+        hcg.hcg_grid_host(plan, w.spectra.pin_memory(), cube, None, slab=8, stream=s)
+    plan.destroy()
+    Vr, _, _ = run_oracle(w)
+    assert_cube_close(cube.numpy(), Vr, TOL_F32, "plan on a side stream")
+
+
+def test_argument_errors():
+    w = synth.small_cube(n=2000, nchan=4, nx=8, ny=8)
+    plan = _plan(w)
+    g = w.grid
+    cube = torch.empty((4, g.ny, g.nx), dtype=torch.float32)
+    with pytest.raises(TypeError):
+        hcg.hcg_grid_host(plan, w.spectra.cuda(), cube)
+    with pytest.raises(ValueError):
+        hcg.hcg_grid_host(plan, w.spectra[:100].contiguous(), cube)
+    with pytest.raises(ValueError):
+        hcg.hcg_grid_host(plan, w.spectra, cube[:3].contiguous())
+    with pytest.raises(hcg.HcgError):
+        hcg.hcg_grid_host(plan, w.spectra, cube, slab=-1)
+    plan.destroy()
+
+
+def test_full_size_sample_count_sampled():
+    """The 9.12M-sample drift scan (64 channels, slabs of 16) streamed from
+    page-locked memory: slabs equal to hcg_grid on the device, sampled cells
+    against the oracle."""
+    dev = torch.device("cuda:0")
+    w = synth.drift_scan_cube(40, 12_000, 64, 600, 0.5, 3.0, synth.SEED0 + 1, device=dev,
+                              name="drift_scan_600x600_c64")
+    print(f"{w.name}: {w.n} samples x {w.nchan} channels", flush=True)
+    plan = _plan(w)
+    g = w.grid
+    spec = w.spectra.cpu().pin_memory()
+    cube = _host((w.nchan, g.ny, g.nx), True)
+    W = _host((g.ny, g.nx), True)
+    hcg.hcg_grid_host(plan, spec, cube, W, slab=16)
+    del spec
+    Vd, Wd = _device_slabs(plan, w, 16)
+    plan.destroy()
+    assert np.array_equal(cube.numpy(), Vd, equal_nan=True)
+    assert np.array_equal(W.numpy(), Wd)
+    groups = sample_cells(g, seed=3, patches=3, patch=8)
+    cells = np.concatenate(groups)
+    ref = [sampled_oracle(w, c) for c in groups]
+    Vr = np.concatenate([v for v, _ in ref])
+    Wr = np.concatenate([x for _, x in ref])
+    Vg, Wg = gather_cells(cube, W, cells)
+    assert_cube_close(Vg.T, Vr.T, TOL_F32, "drift scan, sampled")
+    assert_weights_close(Wg, Wr)
