@@ -122,7 +122,7 @@ def sampled_errors(cube, samp):
     return np.sqrt((d * d).sum(0) / (r * r).sum(0))
 
 
-def run_host_stream(w, slabs, samp, pageable_slab=0):
+def run_host_stream(w, slabs, samp, pageable_slab=256):
     """hcg_grid_host with the spectra and the cube in host memory: wall time
     per cube (plan built beforehand, not timed) and the host-to-device rate it
     implies, beside the rate of one plain 4 GiB page-locked host-to-device
@@ -181,8 +181,11 @@ def run_host_stream(w, slabs, samp, pageable_slab=0):
             f"cube, host-to-device {rec['h2d_GBps']:.1f} GB/s (plain copy {copy_gbs:.1f} GB/s)")
     del spec_h, cube_h
     if pageable_slab:
+        t0 = time.perf_counter()
         spec_p = w.spectra.cpu()
         cube_p = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32)
+        log(f"host stream: pageable copy of {w.nchan} channels made in "
+            f"{time.perf_counter() - t0:.1f} s")
         rec = timed(spec_p, cube_p, W_h, pageable_slab, 1)
         if samp is not None:
             rec["rel_l2_max_over_channels"] = float(sampled_errors(cube_p, samp).max())

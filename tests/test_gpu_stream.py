@@ -49,29 +49,34 @@ def _device_slabs(plan, w, slab):
     return V, W.cpu().numpy()
 
 
-def _streamed(plan, w, slab, pinned=True, with_weights=True):
+def _streamed(plan, w, slab, pinned=True, with_weights=True, pinned_out=None):
     g = w.grid
+    pinned_out = pinned if pinned_out is None else pinned_out
     spec = w.spectra.contiguous()
     if pinned:
         spec = spec.pin_memory()
-    cube = _host((w.nchan, g.ny, g.nx), pinned)
-    W = _host((g.ny, g.nx), pinned) if with_weights else None
+    cube = _host((w.nchan, g.ny, g.nx), pinned_out)
+    W = _host((g.ny, g.nx), pinned_out) if with_weights else None
     hcg.hcg_grid_host(plan, spec, cube, W, slab=slab)
     return cube.numpy(), (W.numpy() if with_weights else None)
 
 
-@pytest.mark.parametrize("nchan,slab,pinned", [
-    (300, 64, True),    # 4 full slabs and a ragged one of 44 channels
-    (300, 64, False),   # the same from pageable memory
-    (37, 1, True),      # one channel per slab (the one-lane-per-cell kernel)
-    (70, 9, True),      # slabs that switch between the two accumulation kernels
-    (20, 0, True),      # default slab, wider than the cube
-    (600, 300, True),   # slabs above 256 channels
+@pytest.mark.parametrize("nchan,slab,pinned,pinned_out", [
+    (300, 64, True, True),     # 4 full slabs and a ragged one of 44 channels
+    (300, 64, False, False),   # the same through the library's page-locked chunks
+    (300, 64, True, False),    # page-locked spectra, pageable cube
+    (300, 64, False, True),    # pageable spectra, page-locked cube
+    (37, 1, True, True),       # one channel per slab (the one-lane-per-cell kernel)
+    (70, 9, True, True),       # slabs that switch between the two accumulation kernels
+    (70, 9, False, False),
+    (20, 0, True, True),       # default slab, wider than the cube
+    (20, 0, False, False),     # one slab of whole rows: contiguous packing
+    (600, 300, True, True),    # slabs above 256 channels
 ])
-def test_streamed_equals_device_slabs(nchan, slab, pinned):
+def test_streamed_equals_device_slabs(nchan, slab, pinned, pinned_out):
     w = synth.small_cube(n=12_000, nchan=nchan, nx=29, ny=19)
     plan = _plan(w)
-    V, W = _streamed(plan, w, slab, pinned)
+    V, W = _streamed(plan, w, slab, pinned, pinned_out=pinned_out)
     Vd, Wd = _device_slabs(plan, w, slab if slab else 512)
     plan.destroy()
     assert np.array_equal(V, Vd, equal_nan=True), "streamed cube differs from hcg_grid"
@@ -125,9 +130,10 @@ def test_argument_errors():
 
 
 def test_full_size_sample_count_sampled():
-    """The 9.12M-sample drift scan (64 channels, slabs of 16) streamed from
-    page-locked memory: slabs equal to hcg_grid on the device, sampled cells
-    against the oracle."""
+    """The 9.12M-sample drift scan (64 channels) streamed from page-locked
+    memory in slabs of 16, and from pageable memory in slabs of 48 (27 packed
+    chunks in per slab, two chunks out): slabs equal to hcg_grid on the
+    device, sampled cells against the oracle."""
     dev = torch.device("cuda:0")
     w = synth.drift_scan_cube(40, 12_000, 64, 600, 0.5, 3.0, synth.SEED0 + 1, device=dev,
                               name="drift_scan_600x600_c64")
@@ -140,9 +146,18 @@ def test_full_size_sample_count_sampled():
     hcg.hcg_grid_host(plan, spec, cube, W, slab=16)
     del spec
     Vd, Wd = _device_slabs(plan, w, 16)
-    plan.destroy()
     assert np.array_equal(cube.numpy(), Vd, equal_nan=True)
     assert np.array_equal(W.numpy(), Wd)
+    spec = w.spectra.cpu()
+    cube_p = _host((w.nchan, g.ny, g.nx), False)
+    W_p = _host((g.ny, g.nx), False)
+    hcg.hcg_grid_host(plan, spec, cube_p, W_p, slab=48)
+    del spec
+    Vd, _ = _device_slabs(plan, w, 48)
+    plan.destroy()
+    assert np.array_equal(cube_p.numpy(), Vd, equal_nan=True)
+    assert np.array_equal(W_p.numpy(), Wd)
+    del cube_p, W_p
     groups = sample_cells(g, seed=3, patches=3, patch=8)
     cells = np.concatenate(groups)
     ref = [sampled_oracle(w, c) for c in groups]
