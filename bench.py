@@ -197,6 +197,82 @@ def run_host_stream(w, slabs, samp, pageable_slab=256):
     return out
 
 
+def sweep_points(name):
+    """(label, paper_field kwargs) of the paper's scaling experiments
+    (Section 4.2): e2 coarsening at 10^8 samples on 5 deg x 5 deg over cell
+    sizes; e3 input volume 10^3 .. 3.6 x 10^8 on 5 deg x 5 deg, 90 x 90;
+    e4 field size 0.1 .. 60 deg at 10^5 samples per square degree, 200" cells."""
+    if name == "e2":
+        return [(f'cell {c:g}"', dict(n=100_000_000, side_deg=5.0, cell_arcsec=c))
+                for c in (200.0, 100.0, 50.0, 25.0)]
+    if name == "e3":
+        return [(f"N {n:.0e}", dict(n=n, side_deg=5.0))
+                for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000, 100_000_000,
+                          360_000_000)]
+    return [(f"field {d:g} deg", dict(n=int(round(1e5 * d * d)), side_deg=d))
+            for d in (0.1, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 40.0, 60.0)]
+
+
+def run_sweep(args):
+    """Plan, the tile gather (hcg_grid, one channel) and the paper's
+    thread-per-row-cells gather (hcg_grid_rowthreads, gamma 1..3, 64 and
+    256 threads per block) on each point of a sweep; the maps of the two
+    gathers are compared.  One JSON line."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=3):
+        fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+    rows = []
+    for label, kw in sweep_points(args.sweep):
+        w = synth.paper_field(device=dev, **kw)
+        g = w.grid
+        spec = w.spectra[:, 0].contiguous()
+        V = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev)
+        Vt = torch.empty((1, g.ny, g.nx), dtype=torch.float32, device=dev)
+        plan_ms = timed(lambda: hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg,
+                                             nside=w.nside).destroy(), reps=2)
+        plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
+        stats = plan.stats()
+        rec = {"point": label, "n": w.n, "grid": [g.nx, g.ny], "side_deg": kw["side_deg"],
+               "pairs": stats["pairs"], "candidates": stats["candidates"], "plan_ms": plan_ms,
+               "tile_gather_ms": timed(lambda: hcg.hcg_grid(plan, spec[:, None], Vt))}
+        log(f"  {label}: plan {plan_ms:.2f} ms, tile gather {rec['tile_gather_ms']:.3f} ms")
+        ok = ~torch.isnan(Vt[0])
+        scale = float(Vt[0][ok].abs().max()) if bool(ok.any()) else 1.0
+        paper = {}
+        for gamma in (1, 2, 3):
+            for block in (64, 256):
+                ms = timed(lambda: hcg.hcg_grid_rowthreads(plan, spec, V, gamma=gamma,
+                                                           block=block))
+                same = bool(torch.equal(torch.isnan(V), ~ok))
+                diff = float((V[ok] - Vt[0][ok]).abs().max()) / scale if bool(ok.any()) else 0.0
+                paper[f"gamma{gamma}_block{block}"] = {"ms": ms, "nan_same": same,
+                                                       "max_rel_diff": diff}
+                log(f"  {label}: paper scheme gamma {gamma} block {block}: {ms:.3f} ms")
+        rec["paper_scheme"] = paper
+        best = min(paper.values(), key=lambda r: r["ms"])["ms"]
+        rec["paper_best_ms"] = best
+        rec["tile_speedup_vs_paper_best"] = best / rec["tile_gather_ms"]
+        plan.destroy()
+        rows.append(rec)
+        log(f"{args.sweep} {label}: N {w.n}, {g.nx}x{g.ny}, plan {plan_ms:.2f} ms, tile gather "
+            f"{rec['tile_gather_ms']:.3f} ms, paper scheme best {best:.3f} ms")
+        del w, spec, V, Vt
+        torch.cuda.empty_cache()
+    print(json.dumps({"sweep": args.sweep, "unit": "ms", "kernel_fwhm_arcsec": 300.0,
+                      "support_sigma": 3.0, "rows": rows}), flush=True)
+
+
 def run_batch(args):
     """64 independent fields of uneven size: one batched launch (persistent
     kernel, hipGraph replay, autotuned) against 64 separate plan + grid calls
@@ -301,6 +377,9 @@ def main():
                     help="drift_scan: 9.12M samples x 1024 channels -> 600 x 600 (default); "
                          "drift_scan_8192: 1.976M x 8192 -> 400 x 400; large: 20.064M x 1024 -> "
                          "3000 x 3000; batch: 64 fields")
+    ap.add_argument("--sweep", choices=["e2", "e3", "e4"],
+                    help="instead of the benchmark: the paper's coarsening (e2), input-volume "
+                         "(e3) or field-size (e4) sweep, tile gather against the paper's scheme")
     ap.add_argument("--host-stream", default="",
                     help="comma-separated slab widths: also time hcg_grid_host (spectra and "
                          "cube in page-locked host memory) for each")
@@ -314,6 +393,9 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        run_sweep(args)
+        return
     if args.workload == "batch":
         run_batch(args)
         return

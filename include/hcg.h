@@ -255,6 +255,29 @@ hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nch
                          int64_t slab_chan, float* cube_host, float* weights_host,
                          void* hip_stream);
 
+/*
+ * hcg_grid_rowthreads -- the paper's GPU gather scheme on one channel, the
+ * baseline that hcg_grid is measured against: one thread per gamma
+ * consecutive cells of a latitude row (Section 3.5 I, thread organisation
+ * and coarsening), each thread searching its own candidates through the
+ * plan's ring table and sorted keys (Section 3.4, steps i-v) and summing in
+ * FP64 registers.
+ *
+ *   spectra  device float [n], one value per sample, in the sample order
+ *            given to hcg_plan.
+ *   gamma    cells per thread, 1 .. 4 (the coarsening factor).
+ *   block    threads per block, a multiple of 64 in 64 .. 1024.
+ *   map      device float [ny][nx]: V of Eq. (1), NaN where W = 0.
+ *   weights  device float [ny][nx] or NULL: W.
+ *
+ * The result equals that of hcg_grid with nchan = 1 up to the order of the
+ * FP64 sums.  Asynchronous on hip_stream.  Errors: HCG_E_ARG (NULL spectra
+ * or map, gamma or block out of range), HCG_E_STATE (not a live plan),
+ * HCG_E_DEVICE (launch failure).
+ */
+hcg_status hcg_grid_rowthreads(hcg_plan_t plan, const float* spectra, int gamma, int block,
+                               float* map, float* weights, void* hip_stream);
+
 /* hcg_destroy -- wait for the device, then free the plan.  NULL is a no-op
  * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE. */
 hcg_status hcg_destroy(hcg_plan_t plan);

@@ -84,7 +84,7 @@ EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_pl
             "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
             "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
             "hcg_destroy_batch", "hcg_get_batch_info", "hcg_quantize_packed", "hcg_grid_packed",
-            "hcg_packed_bytes", "hcg_grid_host"]
+            "hcg_packed_bytes", "hcg_grid_host", "hcg_grid_rowthreads"]
 
 _lib = None
 
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
     lib.hcg_grid_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
     lib.hcg_packed_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(i64)]
     lib.hcg_grid_host.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    lib.hcg_grid_rowthreads.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.hcg_plan_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(FieldDescC),
                                    ctypes.POINTER(OptsC), vp]
     lib.hcg_grid_batch.argtypes = [vp, ctypes.POINTER(FieldDataC), vp]
@@ -264,6 +265,24 @@ def hcg_grid_host(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights
     st = load().hcg_grid_host(plan.handle, _hptr(spectra, "spectra"), C, int(slab),
                               _hptr(cube, "cube"), _hptr(weights, "weights"), _stream(stream))
     _check(st, "hcg_grid_host")
+
+
+def hcg_grid_rowthreads(plan: Plan, spectra: torch.Tensor, out: torch.Tensor, weights=None,
+                        gamma: int = 1, block: int = 64, stream=None) -> None:
+    """The paper's thread-per-row-cells gather on one channel: ``spectra`` [n]
+    into ``out`` [ny, nx] (and ``weights`` [ny, nx]), ``gamma`` cells per
+    thread, ``block`` threads per block."""
+    g = plan.grid
+    if spectra.dim() != 1 or int(spectra.shape[0]) != int(plan.info()["n"]):
+        raise ValueError("spectra must be [n] with the plan's sample count")
+    if tuple(out.shape) != (g.ny, g.nx):
+        raise ValueError(f"out must be [{g.ny}, {g.nx}]")
+    if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
+        raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
+    st = load().hcg_grid_rowthreads(plan.handle, _dptr(spectra, torch.float32, "spectra"),
+                                    int(gamma), int(block), _dptr(out, torch.float32, "out"),
+                                    _dptr(weights, torch.float32, "weights"), _stream(stream))
+    _check(st, "hcg_grid_rowthreads")
 
 
 def hcg_quantize(spectra: torch.Tensor, dtype: int, stream=None):

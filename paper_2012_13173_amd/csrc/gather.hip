@@ -29,57 +29,13 @@
 #include <vector>
 
 #include "hcg_internal.h"
+#include "sphere.h"
 
 namespace hcg {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKB = 64;             // candidates staged per block
-
-// Unit vector of cell (ix, iy); NaN outside the grid (never within R).
-struct CellVec {
-  double x, y, z;
-};
-
-__device__ __forceinline__ CellVec cell_vec(const GridGeom& g, int ix, int iy) {
-  CellVec c;
-  if (ix >= g.nx || iy >= g.ny) {
-    c.x = c.y = c.z = __builtin_nan("");
-    return c;
-  }
-  double sb, cb, sl, cl;
-  sincos(cell_lat_deg(g, iy) * kDeg2Rad, &sb, &cb);
-  sincos(cell_lon_deg(g, ix) * kDeg2Rad, &sl, &cl);
-  c.x = cb * cl;
-  c.y = cb * sl;
-  c.z = sb;
-  return c;
-}
-
-// Squared chord |u - v|^2 = 4 sin^2(d/2) between a cell and a sample.
-__device__ __forceinline__ double chord2(const CellVec& c, const double4& v) {
-  const double dx = v.x - c.x, dy = v.y - c.y, dz = v.z - c.z;
-  return dx * dx + dy * dy + dz * dz;
-}
-
-// Squared great-circle distance from the squared chord c2:
-// d^2 = 4 asin^2(chord / 2) = 2 sum_n c2^n / (n^2 binom(2n, n))
-//     = c2 (1 + c2/12 + c2^2/90 + c2^3/560 + c2^4/3150 + c2^5/16632 + ...);
-// six terms leave a relative error below 2e-17 for c2 < 1e-2 (d < 5.7 deg),
-// the arcsine beyond; three terms leave one below 2e-15 for c2 < 1e-4
-// (d < 0.57 deg).
-// kWide = false: the caller guarantees c2 < 1e-4 (a support radius below
-// 0.57 deg, every configuration here), which keeps the longer series, the
-// arcsine and their registers out of the kernel.
-template <bool kWide = true>
-__device__ __forceinline__ double dist2_from_chord2(double c2) {
-  if (!kWide) return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0)));
-  if (c2 < 1e-2)
-    return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
-           c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
-  const double d = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
-  return d * d;
-}
 
 // FP32 weight of a pair inside the support: the exponent -d^2 log2(e) /
 // (2 sigma^2) is formed in FP64 and evaluated with the hardware base-2
@@ -949,6 +905,12 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
 // ---------------------------------------------------------------------------
 // Few channels (C <= 8) and pair counting: one lane per cell of the 8 x 8
 // tile, candidates staged 64 at a time, FP64 accumulation.
+// A map of few tiles gives too few waves to hide the latency of the
+// candidate loads, so the candidates of a tile can be split over nsplit
+// workgroups (blockIdx.y takes every nsplit-th staged block of 64); each
+// then writes its FP64 partial sums to part[split][kCM + 1][tile * 64 +
+// lane] (the channel sums, then W) and k_cells_finish adds them in split
+// order.  nsplit = 1 writes the map directly.
 // ---------------------------------------------------------------------------
 template <int kCM, bool kCount>
 __global__ void __launch_bounds__(64) k_gather_cells(
@@ -956,7 +918,7 @@ __global__ void __launch_bounds__(64) k_gather_cells(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ nranges, int maxr,
     const float* __restrict__ spectra, int C, GridGeom g, int ntx, double c2R,
     double wscale, float* __restrict__ cube, float* __restrict__ wmap,
-    unsigned long long* __restrict__ pair_count) {
+    unsigned long long* __restrict__ pair_count, int nsplit, double* __restrict__ part) {
   __shared__ uint2 s_rng[kMaxRangesLimit];
   __shared__ uint32_t s_pre[kMaxRangesLimit + 1];
   __shared__ double4 s_xyz[kKB];
@@ -975,7 +937,8 @@ __global__ void __launch_bounds__(64) k_gather_cells(
   double wsum = 0.0;
   unsigned long long npair = 0;
   uint32_t cur = 0;
-  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
+  const uint32_t step = (uint32_t)nsplit * kKB;
+  for (uint32_t q0 = blockIdx.y * (uint32_t)kKB; q0 < total; q0 += step) {
     const uint32_t q = q0 + lane;
     if (q < total) {
       const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
@@ -1011,6 +974,14 @@ __global__ void __launch_bounds__(64) k_gather_cells(
     if (lane == 0) atomicAdd(pair_count, npair);
     return;
   }
+  if (nsplit > 1) {
+    const int64_t slots = (int64_t)gridDim.x * kTileCells;
+    double* out = part + (int64_t)blockIdx.y * (kCM + 1) * slots + (int64_t)tile * kTileCells + lane;
+#pragma unroll
+    for (int c = 0; c < kCM; ++c) out[c * slots] = accv[c];
+    out[kCM * slots] = wsum;
+    return;
+  }
   if (ix >= g.nx || iy >= g.ny) return;
   const int64_t G = (int64_t)g.nx * g.ny;
   const int64_t cellidx = (int64_t)iy * g.nx + ix;
@@ -1020,30 +991,83 @@ __global__ void __launch_bounds__(64) k_gather_cells(
     if (c < C) cube[c * G + cellidx] = (wsum > 0.0) ? (float)(accv[c] / wsum) : __builtin_nanf("");
 }
 
-// Squared chord of the support radius, 4 sin^2(R / 2), and the exponent
-// scale -log2(e) / (2 sigma^2) of the weights.
-static double support_chord2(const hcg_plan_s* p) {
-  const double s = std::sin(0.5 * p->support_rad);
-  return 4.0 * s * s;
+// Sum of the nsplit partial sums of every cell, in split order; V and W.
+template <int kCM>
+__global__ void __launch_bounds__(256) k_cells_finish(const double* __restrict__ part, int nsplit,
+                                                       int ntiles, int C, GridGeom g, int ntx,
+                                                       float* __restrict__ cube,
+                                                       float* __restrict__ wmap) {
+  const int64_t slots = (int64_t)ntiles * kTileCells;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= slots) return;
+  const int tile = (int)(slot / kTileCells), lane = (int)(slot % kTileCells);
+  const int ix = (tile % ntx) * kTileX + (lane & 7), iy = (tile / ntx) * kTileY + (lane >> 3);
+  if (ix >= g.nx || iy >= g.ny) return;
+  double accv[kCM];
+#pragma unroll
+  for (int c = 0; c < kCM; ++c) accv[c] = 0.0;
+  double wsum = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double* in = part + (int64_t)sp * (kCM + 1) * slots + slot;
+#pragma unroll
+    for (int c = 0; c < kCM; ++c) accv[c] += in[c * slots];
+    wsum += in[kCM * slots];
+  }
+  const int64_t G = (int64_t)g.nx * g.ny;
+  const int64_t cellidx = (int64_t)iy * g.nx + ix;
+  if (wmap) wmap[cellidx] = (float)wsum;
+#pragma unroll
+  for (int c = 0; c < kCM; ++c)
+    if (c < C) cube[c * G + cellidx] = (wsum > 0.0) ? (float)(accv[c] / wsum) : __builtin_nanf("");
 }
-static double weight_scale(const hcg_plan_s* p) {
-  return -1.4426950408889634 / (2.0 * p->sigma_rad * p->sigma_rad);
-}
+
+// A map of fewer than kCellsSplitBelow tiles is spread over about
+// kCellsTargetGroups workgroups (eight per CU); from about 2000 tiles on, a
+// split of two measured slower than none (the partial sums cost more than
+// the extra waves gain).
+constexpr int kCellsSplitBelow = 1024;
+constexpr int kCellsTargetGroups = 2048;
+constexpr int kCellsMaxSplit = 64;
 
 static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, float* cube,
                                float* wmap, hipStream_t stream) {
   const double c2R = support_chord2(p), wscale = weight_scale(p);
   const unsigned ntiles = (unsigned)(p->ntx * p->nty);
-#define HCG_CELLS(CM)                                                                       \
-  k_gather_cells<CM, false><<<ntiles, 64, 0, stream>>>(p->xyz, p->perm, p->ranges,          \
-                                                       p->nranges, p->maxr, spec, C, p->grid, \
-                                                       p->ntx, c2R, wscale, cube, wmap, nullptr)
-  if (C == 1) HCG_CELLS(1);
-  else if (C == 2) HCG_CELLS(2);
-  else if (C <= 4) HCG_CELLS(4);
+  const int cm = (C == 1) ? 1 : (C == 2) ? 2 : (C <= 4) ? 4 : 8;
+  int nsplit = (ntiles >= (unsigned)kCellsSplitBelow)
+                   ? 1
+                   : (int)std::min<int64_t>(kCellsMaxSplit,
+                                            (kCellsTargetGroups + ntiles - 1) / ntiles);
+  double* part = nullptr;
+  if (nsplit > 1) {
+    const size_t bytes = sizeof(double) * (size_t)nsplit * (cm + 1) * ntiles * kTileCells;
+    if (hipMallocAsync((void**)&part, bytes, stream) != hipSuccess) {
+      (void)hipGetLastError();  // no room for the partial sums: one workgroup per tile
+      part = nullptr;
+      nsplit = 1;
+    }
+  }
+  const dim3 grid(ntiles, (unsigned)nsplit);
+  const unsigned fin_blocks = (unsigned)((ntiles * (int64_t)kTileCells + 255) / 256);
+#define HCG_CELLS(CM)                                                                          \
+  do {                                                                                         \
+    k_gather_cells<CM, false><<<grid, 64, 0, stream>>>(p->xyz, p->perm, p->ranges, p->nranges, \
+                                                       p->maxr, spec, C, p->grid, p->ntx, c2R, \
+                                                       wscale, cube, wmap, nullptr, nsplit,    \
+                                                       part);                                  \
+    if (nsplit > 1)                                                                            \
+      k_cells_finish<CM><<<fin_blocks, 256, 0, stream>>>(part, nsplit, (int)ntiles, C,         \
+                                                         p->grid, p->ntx, cube, wmap);         \
+  } while (0)
+  if (cm == 1) HCG_CELLS(1);
+  else if (cm == 2) HCG_CELLS(2);
+  else if (cm == 4) HCG_CELLS(4);
   else HCG_CELLS(8);
 #undef HCG_CELLS
-  HCG_LAUNCH_CHECK("k_gather_cells");
+  const hipError_t le = hipGetLastError();
+  if (part) (void)hipFreeAsync(part, stream);
+  if (le != hipSuccess)
+    return fail(HCG_E_DEVICE, "launch of k_gather_cells failed: %s", hipGetErrorString(le));
   return HCG_OK;
 }
 
@@ -1270,7 +1294,7 @@ extern "C" hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats,
   k_gather_cells<0, true><<<ntiles, 64, 0, stream>>>(p->xyz, p->perm, p->ranges, p->nranges,
                                                      p->maxr, nullptr, 0, p->grid, p->ntx,
                                                      support_chord2(p), 0.0,
-                                                     nullptr, nullptr, dcount);
+                                                     nullptr, nullptr, dcount, 1, nullptr);
   HCG_LAUNCH_CHECK("k_gather_cells<count>");
   unsigned long long pairs = 0;
   HCG_HIP(hipMemcpyAsync(&pairs, dcount, sizeof(pairs), hipMemcpyDeviceToHost, stream));

@@ -14,6 +14,7 @@
 #include <set>
 
 #include "hcg_internal.h"
+#include "sphere.h"
 
 namespace hcg {
 
@@ -349,77 +350,9 @@ __global__ void k_ring_csr(const uint32_t* __restrict__ keys, int64_t n, int ns,
 }
 
 // ---------------------------------------------------------------------------
-// a5: candidate ranges per tile of output cells.  For every ring whose sample
-// band (between the latitudes of its two neighbouring rings) comes within R
-// of the tile's latitude span, the longitude half-width that a pair within R
-// can have is bounded from the haversine,
-//   sin^2(dlon/2) <= (sin^2(R/2) - sin^2(dlat_min/2)) / (cos lat_g,min cos lat_n,min),
-// widened by half a pixel of that ring (every sample lies within half a
-// pixel spacing of its pixel centre in longitude), turned into a pixel range
-// and then into a range of sorted positions by binary search inside the ring.
+// a5: candidate ranges per tile of output cells: ring_ranges (sphere.h) for
+// every ring that can hold a sample within R of the tile.
 // ---------------------------------------------------------------------------
-// Ranges of ring i for the tile: up to two [a, b) pieces, in key order.
-struct RingRanges {
-  uint32_t a0, b0, a1, b1;
-};
-
-__device__ RingRanges ring_ranges(int i, const uint32_t* __restrict__ keys,
-                                  const uint32_t* __restrict__ csr, int ns, int ring_first,
-                                  uint32_t pix_base, double lon_a, double lon_b, double lat_a,
-                                  double lat_b, double Rs, double hR, double cos_g) {
-  RingRanges out{0u, 0u, 0u, 0u};
-  const double zt = hpx_ring_z(ns, i - 1), zb = hpx_ring_z(ns, i + 1);
-  const double d_hi = asin(fmin(1.0, zt)), d_lo = asin(fmax(-1.0, zb));
-  const double dmin = fmax(0.0, fmax(d_lo - lat_b, lat_a - d_hi));
-  if (dmin > Rs) return out;
-  const double sd = sin(0.5 * dmin);
-  const double hrem = hR - sd * sd;
-  if (hrem < 0.0) return out;
-  const uint32_t ra = csr[i - ring_first], rb = csr[i - ring_first + 1];
-  if (rb <= ra) return out;
-  const double cos_n = cos(fmax(fabs(d_lo), fabs(d_hi)));
-  const double denom = cos_g * cos_n;
-  bool whole = !(denom > 1e-300) || hrem >= denom;
-  double dal = 0.0;
-  if (!whole) {
-    dal = 2.0 * asin(sqrt(hrem / denom));
-    whole = (lon_b - lon_a) + 2.0 * dal >= 2.0 * kPi;
-  }
-  const int64_t npix = hpx_ring_npix(ns, i);
-  const int64_t start = hpx_ring_start(ns, i);
-  int64_t j_lo = 0, j_hi = 0;
-  if (!whole) {
-    const double shift = (i < ns || i > 3 * ns) ? 0.5 : 0.5 * (double)((i - ns + 1) & 1);
-    const double width = 2.0 * kPi / (double)npix;
-    const double x_lo = (lon_a - dal - 0.5 * width) / width - shift;
-    const double x_hi = (lon_b + dal + 0.5 * width) / width - shift;
-    j_lo = (int64_t)ceil(x_lo - 1e-7);
-    j_hi = (int64_t)floor(x_hi + 1e-7);
-    whole = (j_hi - j_lo + 1) >= npix;
-  }
-  if (whole) {
-    out.a0 = ra;
-    out.b0 = rb;
-    return out;
-  }
-  if (j_hi < j_lo) return out;
-  int64_t jl = j_lo % npix;
-  if (jl < 0) jl += npix;
-  int64_t jh = j_hi % npix;
-  if (jh < 0) jh += npix;
-  const int64_t base = (int64_t)pix_base;
-  if (jl <= jh) {
-    out.a0 = lower_bound_u32(keys, ra, rb, start + jl - base);
-    out.b0 = lower_bound_u32(keys, out.a0, rb, start + jh + 1 - base);
-  } else {  // wraps through longitude 0 of this ring: two pieces, in key order
-    out.a0 = ra;
-    out.b0 = lower_bound_u32(keys, ra, rb, start + jh + 1 - base);
-    out.a1 = lower_bound_u32(keys, out.b0, rb, start + jl - base);
-    out.b1 = rb;
-  }
-  return out;
-}
-
 // One wave per tile; lane r handles ring i_lo + r (+64, ...).  Ranges are
 // written in ring order, two slots at most per ring.
 __global__ void __launch_bounds__(256) k_tile_ranges(

@@ -1,0 +1,140 @@
+// Device geometry shared by the gather kernels and the plan: unit vectors of
+// cells, chord and great-circle distances, and the per-ring candidate search
+// of Section 3.4 (steps i-iv).
+#pragma once
+
+#include <cmath>
+
+#include "hcg_internal.h"
+
+namespace hcg {
+
+// Unit vector of cell (ix, iy); NaN outside the grid (never within R).
+struct CellVec {
+  double x, y, z;
+};
+
+__device__ __forceinline__ CellVec cell_vec(const GridGeom& g, int ix, int iy) {
+  CellVec c;
+  if (ix >= g.nx || iy >= g.ny) {
+    c.x = c.y = c.z = __builtin_nan("");
+    return c;
+  }
+  double sb, cb, sl, cl;
+  sincos(cell_lat_deg(g, iy) * kDeg2Rad, &sb, &cb);
+  sincos(cell_lon_deg(g, ix) * kDeg2Rad, &sl, &cl);
+  c.x = cb * cl;
+  c.y = cb * sl;
+  c.z = sb;
+  return c;
+}
+
+// Squared chord |u - v|^2 = 4 sin^2(d/2) between a cell and a sample.
+__device__ __forceinline__ double chord2(const CellVec& c, const double4& v) {
+  const double dx = v.x - c.x, dy = v.y - c.y, dz = v.z - c.z;
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// Squared great-circle distance from the squared chord c2:
+// d^2 = 4 asin^2(chord / 2) = 2 sum_n c2^n / (n^2 binom(2n, n))
+//     = c2 (1 + c2/12 + c2^2/90 + c2^3/560 + c2^4/3150 + c2^5/16632 + ...);
+// six terms leave a relative error below 2e-17 for c2 < 1e-2 (d < 5.7 deg),
+// the arcsine beyond; three terms leave one below 2e-15 for c2 < 1e-4
+// (d < 0.57 deg).
+// kWide = false: the caller guarantees c2 < 1e-4 (a support radius below
+// 0.57 deg, every configuration here), which keeps the longer series, the
+// arcsine and their registers out of the kernel.
+template <bool kWide = true>
+__device__ __forceinline__ double dist2_from_chord2(double c2) {
+  if (!kWide) return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0)));
+  if (c2 < 1e-2)
+    return c2 * (1.0 + c2 * (1.0 / 12.0 + c2 * (1.0 / 90.0 + c2 * (1.0 / 560.0 +
+           c2 * (1.0 / 3150.0 + c2 * (1.0 / 16632.0))))));
+  const double d = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
+  return d * d;
+}
+
+// Candidate search in one ring for cells spanning [lon_a, lon_b] x
+// [lat_a, lat_b] (radians): for ring i whose sample band (between the
+// latitudes of its two neighbouring rings) comes within R of that span, the
+// longitude half-width that a pair within R can have is bounded from the
+// haversine,
+//   sin^2(dlon/2) <= (sin^2(R/2) - sin^2(dlat_min/2)) / (cos lat_g,min cos lat_n,min),
+// widened by half a pixel of that ring (every sample lies within half a
+// pixel spacing of its pixel centre in longitude), turned into a pixel range
+// and then into a range of sorted positions by binary search inside the
+// ring's part of the sorted keys (csr).  Rs is the support radius, hR =
+// sin^2(Rs / 2), cos_g = cos of the span's largest |latitude|.
+// Ranges of ring i for the tile: up to two [a, b) pieces, in key order.
+struct RingRanges {
+  uint32_t a0, b0, a1, b1;
+};
+
+__device__ inline RingRanges ring_ranges(int i, const uint32_t* __restrict__ keys,
+                                  const uint32_t* __restrict__ csr, int ns, int ring_first,
+                                  uint32_t pix_base, double lon_a, double lon_b, double lat_a,
+                                  double lat_b, double Rs, double hR, double cos_g) {
+  RingRanges out{0u, 0u, 0u, 0u};
+  const double zt = hpx_ring_z(ns, i - 1), zb = hpx_ring_z(ns, i + 1);
+  const double d_hi = asin(fmin(1.0, zt)), d_lo = asin(fmax(-1.0, zb));
+  const double dmin = fmax(0.0, fmax(d_lo - lat_b, lat_a - d_hi));
+  if (dmin > Rs) return out;
+  const double sd = sin(0.5 * dmin);
+  const double hrem = hR - sd * sd;
+  if (hrem < 0.0) return out;
+  const uint32_t ra = csr[i - ring_first], rb = csr[i - ring_first + 1];
+  if (rb <= ra) return out;
+  const double cos_n = cos(fmax(fabs(d_lo), fabs(d_hi)));
+  const double denom = cos_g * cos_n;
+  bool whole = !(denom > 1e-300) || hrem >= denom;
+  double dal = 0.0;
+  if (!whole) {
+    dal = 2.0 * asin(sqrt(hrem / denom));
+    whole = (lon_b - lon_a) + 2.0 * dal >= 2.0 * kPi;
+  }
+  const int64_t npix = hpx_ring_npix(ns, i);
+  const int64_t start = hpx_ring_start(ns, i);
+  int64_t j_lo = 0, j_hi = 0;
+  if (!whole) {
+    const double shift = (i < ns || i > 3 * ns) ? 0.5 : 0.5 * (double)((i - ns + 1) & 1);
+    const double width = 2.0 * kPi / (double)npix;
+    const double x_lo = (lon_a - dal - 0.5 * width) / width - shift;
+    const double x_hi = (lon_b + dal + 0.5 * width) / width - shift;
+    j_lo = (int64_t)ceil(x_lo - 1e-7);
+    j_hi = (int64_t)floor(x_hi + 1e-7);
+    whole = (j_hi - j_lo + 1) >= npix;
+  }
+  if (whole) {
+    out.a0 = ra;
+    out.b0 = rb;
+    return out;
+  }
+  if (j_hi < j_lo) return out;
+  int64_t jl = j_lo % npix;
+  if (jl < 0) jl += npix;
+  int64_t jh = j_hi % npix;
+  if (jh < 0) jh += npix;
+  const int64_t base = (int64_t)pix_base;
+  if (jl <= jh) {
+    out.a0 = lower_bound_u32(keys, ra, rb, start + jl - base);
+    out.b0 = lower_bound_u32(keys, out.a0, rb, start + jh + 1 - base);
+  } else {  // wraps through longitude 0 of this ring: two pieces, in key order
+    out.a0 = ra;
+    out.b0 = lower_bound_u32(keys, ra, rb, start + jh + 1 - base);
+    out.a1 = lower_bound_u32(keys, out.b0, rb, start + jl - base);
+    out.b1 = rb;
+  }
+  return out;
+}
+
+// Squared chord of the support radius, 4 sin^2(R / 2), and the exponent
+// scale -log2(e) / (2 sigma^2) of the weights.
+inline double support_chord2(const hcg_plan_s* p) {
+  const double s = std::sin(0.5 * p->support_rad);
+  return 4.0 * s * s;
+}
+inline double weight_scale(const hcg_plan_s* p) {
+  return -1.4426950408889634 / (2.0 * p->sigma_rad * p->sigma_rad);
+}
+
+}  // namespace hcg

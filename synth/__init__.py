@@ -280,6 +280,23 @@ def small_cube(n=20_000, nchan=67, nx=45, ny=37, cell_arcmin=0.75, fwhm_arcmin=3
                     nside if nside else nside_for(fwhm), src)
 
 
+def paper_field(n, side_deg=5.0, cell_arcsec=200.0, fwhm_arcsec=300.0, seed=SEED0 + 200,
+                device="cpu", lon_c=180.0, lat_c=30.0, name=None) -> Workload:
+    """The simulation of the paper's experiments (Section 4): one N(0,1) value
+    at each of n coordinate-uniform random positions in a side x side field,
+    gridded onto side / cell cells per axis (5 deg at 200" = 90 x 90), kernel
+    FWHM 300", support 3 sigma, nside by the sigma/2 rule."""
+    lon, lat = uniform_positions(n, lon_c, lat_c, side_deg, side_deg, seed, device)
+    g = _gen(seed + 1, device)
+    spec = torch.randn((n, 1), generator=g, dtype=torch.float32, device=device)
+    ncell = max(1, int(round(side_deg * 3600.0 / cell_arcsec)))
+    cell = cell_arcsec / 3600.0
+    grid = GridDesc(ncell, ncell, lon_c, lat_c, cell, cell)
+    fwhm = fwhm_arcsec / 3600.0
+    return Workload(name or f"paper_field_{side_deg:g}deg_n{n}", lon, lat, spec, grid, fwhm,
+                    3.0 * fwhm * FWHM_TO_SIGMA, nside_for(fwhm), [])
+
+
 def batch_field_params(nfields=64, seed=SEED0 + 3):
     """Per-field draws of the batched configuration: sample count log-uniform
     in [1e4, 2e6], channels in {1, 64, 512, 2048}, square grid side uniform in

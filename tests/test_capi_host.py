@@ -75,6 +75,9 @@ def test_argument_errors_before_device_work():
     assert lib.hcg_quantize_packed(vp(12345), vp(1), 4, hcg.HCG_BF16, vp(1), None, None) == hcg.HCG_E_STATE
     assert lib.hcg_grid_packed(None, vp(1), 4, hcg.HCG_BF16, None, vp(1), None, None) == hcg.HCG_E_ARG
     assert lib.hcg_grid_packed(vp(12345), vp(1), 4, hcg.HCG_BF16, None, vp(1), None, None) == hcg.HCG_E_STATE
+    # the paper-scheme gather
+    assert lib.hcg_grid_rowthreads(None, vp(1), 1, 64, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_grid_rowthreads(vp(12345), vp(1), 1, 64, vp(1), None, None) == hcg.HCG_E_STATE
     # host streaming
     assert lib.hcg_grid_host(None, vp(1), 4, 0, vp(1), None, None) == hcg.HCG_E_ARG
     assert lib.hcg_grid_host(vp(12345), vp(1), 4, 0, vp(1), None, None) == hcg.HCG_E_STATE
