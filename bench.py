@@ -206,7 +206,7 @@ def sweep_points(name):
         return [(f'cell {c:g}"', dict(n=100_000_000, side_deg=5.0, cell_arcsec=c))
                 for c in (200.0, 100.0, 50.0, 25.0)]
     if name == "e3":
-        return [(f"N {n:.0e}", dict(n=n, side_deg=5.0))
+        return [(f"N {n:.2g}", dict(n=n, side_deg=5.0))
                 for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000, 100_000_000,
                           360_000_000)]
     return [(f"field {d:g} deg", dict(n=int(round(1e5 * d * d)), side_deg=d))
