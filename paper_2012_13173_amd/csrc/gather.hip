@@ -810,7 +810,7 @@ __device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& 
       for (int k = 0; k < kmax; ++k) {
         const double c2 = chord2(cell, wxyz[k]);
         if (c2 <= a.c2R) {
-          const double w = exp2(dist2_from_chord2(c2) * a.wscale);
+          const double w = pair_weight64(c2, a.wscale);
           wsum += w;
 #pragma unroll
           for (int c = 0; c < 8; ++c) acc[c] += w * (double)wspec[k * 8 + c];
@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
 
 // ---------------------------------------------------------------------------
 // Few channels (C <= 8) and pair counting: one lane per cell of the 8 x 8
-// tile, candidates staged 64 at a time, FP64 accumulation.
+// tile, candidates staged 64 at a time, FP32 weights summed in FP64.
 // A map of few tiles gives too few waves to hide the latency of the
 // candidate loads, so the candidates of a tile can be split over nsplit
 // workgroups (blockIdx.y takes every nsplit-th staged block of 64); each
@@ -960,7 +960,7 @@ __global__ void __launch_bounds__(64) k_gather_cells(
         if (kCount) {
           ++npair;
         } else {
-          const double w = exp2(dist2_from_chord2(c2) * wscale);
+          const double w = pair_weight64(c2, wscale);
           wsum += w;
 #pragma unroll
           for (int c = 0; c < kCM; ++c) accv[c] += w * (double)s_spec[k][c];

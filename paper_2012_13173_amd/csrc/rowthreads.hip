@@ -11,8 +11,8 @@
 // sorted keys; it then walks the samples and accumulates, for its gamma
 // cells, the weights and weighted values in registers (step v).  The
 // distance and weight are those of the tile kernels' one-lane-per-cell
-// path (FP64 chord series, FP64 base-2 exponential, FP64 sums), so the two
-// differ only in how work and candidates are organised.
+// path (FP64 chord series, pair_weight64, FP64 sums), so the two differ only
+// in how work and candidates are organised.
 #include "hcg_internal.h"
 #include "sphere.h"
 
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(1024) k_gather_rowthreads(
         for (int j = 0; j < kGamma; ++j) {
           const double c2 = chord2(cell[j], v);
           if (c2 <= c2R) {
-            const double w = exp2(dist2_from_chord2(c2) * wscale);
+            const double w = pair_weight64(c2, wscale);
             wsum[j] += w;
             acc[j] += w * s;
           }

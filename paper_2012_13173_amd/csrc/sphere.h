@@ -54,6 +54,16 @@ __device__ __forceinline__ double dist2_from_chord2(double c2) {
   return d * d;
 }
 
+// FP64 weight of a pair inside the support for the one-lane-per-cell paths
+// (FP64 sums): the exponent -d^2 log2(e) / (2 sigma^2) is formed in FP64 and
+// evaluated with the hardware base-2 exponential (v_exp_f32, relative error
+// about 1e-7) while the result is a normal float, with the FP64 exp2 below
+// that (supports wider than about 13 sigma).
+__device__ __forceinline__ double pair_weight64(double c2, double wscale) {
+  const double e = dist2_from_chord2(c2) * wscale;
+  return (e > -126.0) ? (double)__builtin_amdgcn_exp2f((float)e) : exp2(e);
+}
+
 // Candidate search in one ring for cells spanning [lon_a, lon_b] x
 // [lat_a, lat_b] (radians): for ring i whose sample band (between the
 // latitudes of its two neighbouring rings) comes within R of that span, the
