@@ -26,6 +26,8 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <thread>
 #include <vector>
 
@@ -40,7 +42,14 @@ namespace {
 class HostPool {
  public:
   explicit HostPool(int nthreads) : n_(std::max(1, nthreads)) {
-    for (int i = 1; i < n_; ++i) th_.emplace_back([this, i] { worker(i); });
+    for (int i = 1; i < n_; ++i) {
+      try {
+        th_.emplace_back([this, i] { worker(i); });
+      } catch (...) {  // fewer threads than asked: the parts are cut for those started
+        n_ = i;
+        break;
+      }
+    }
   }
   ~HostPool() {
     {
@@ -221,9 +230,9 @@ constexpr size_t kChunkBytes = size_t(64) << 20;
 
 }  // namespace
 
-extern "C" hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
-                                    int64_t slab_chan, float* cube_host, float* weights_host,
-                                    void* hip_stream) {
+static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
+                            int64_t slab_chan, float* cube_host, float* weights_host,
+                            void* hip_stream) {
   if (!plan) return fail(HCG_E_ARG, "hcg_grid_host: plan is NULL");
   if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid_host: not a live plan");
   if (!spectra_host || !cube_host) return fail(HCG_E_ARG, "hcg_grid_host: NULL pointer");
@@ -377,4 +386,19 @@ extern "C" hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, 
                 hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
   if (!out_direct) return ring_drain(r.rout, pool);
   return HCG_OK;
+}
+
+// No C++ exception crosses the C ABI: thread creation and the pool's job
+// objects can throw; the streams are drained by the resources' destructors
+// before the status is returned.
+extern "C" hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
+                                    int64_t slab_chan, float* cube_host, float* weights_host,
+                                    void* hip_stream) {
+  try {
+    return grid_host(plan, spectra_host, nchan, slab_chan, cube_host, weights_host, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(HCG_E_NOMEM, "hcg_grid_host: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(HCG_E_DEVICE, "hcg_grid_host: %s", e.what());
+  }
 }
