@@ -76,6 +76,14 @@ def test_geometry_cases(kw):
     _check(w, 3, 64, kw["name"])
 
 
+@pytest.mark.parametrize("nx,ny,n", [(1, 1, 500), (2, 3, 800), (5, 1, 1)])
+def test_tiny_maps(nx, ny, n):
+    # rows narrower than gamma, a single cell, a single sample
+    w = synth.small_cube(n=n, nchan=1, nx=nx, ny=ny, pad_arcmin=1.0)
+    for gamma in (1, 3, 4):
+        _check(w, gamma, 64, f"{nx}x{ny} n={n} gamma {gamma}")
+
+
 def test_argument_errors():
     w = synth.small_cube(n=2000, nchan=1, nx=8, ny=8)
     plan = hcg.hcg_plan(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg,

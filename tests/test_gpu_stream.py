@@ -129,6 +129,20 @@ def test_argument_errors():
     plan.destroy()
 
 
+def test_device_pointer_refused():
+    # the C ABI itself rejects device memory given as host memory
+    import ctypes
+    w = synth.small_cube(n=2000, nchan=4, nx=8, ny=8)
+    plan = _plan(w)
+    spec_d = w.spectra.cuda()
+    cube = torch.empty((4, 8, 8), dtype=torch.float32)
+    lib = hcg.load()
+    st = lib.hcg_grid_host(plan.handle, ctypes.c_void_p(spec_d.data_ptr()), 4, 0,
+                           ctypes.c_void_p(cube.data_ptr()), None, None)
+    assert st == hcg.HCG_E_ARG and b"device pointer" in lib.hcg_last_error()
+    plan.destroy()
+
+
 def test_full_size_sample_count_sampled():
     """The 9.12M-sample drift scan (64 channels) streamed from page-locked
     memory in slabs of 16, and from pageable memory in slabs of 48 (27 packed
