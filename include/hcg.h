@@ -266,7 +266,7 @@ hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nch
  *   spectra  device float [n], one value per sample, in the sample order
  *            given to hcg_plan.
  *   gamma    cells per thread, 1 .. 4 (the coarsening factor).
- *   block    threads per block, a multiple of 64 in 64 .. 1024.
+ *   block    threads per block, a multiple of 64 in 64 .. 512.
  *   map      device float [ny][nx]: V of Eq. (1), NaN where W = 0.
  *   weights  device float [ny][nx] or NULL: W.
  *

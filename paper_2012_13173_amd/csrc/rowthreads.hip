@@ -20,7 +20,7 @@ namespace hcg {
 namespace {
 
 template <int kGamma>
-__global__ void __launch_bounds__(1024) k_gather_rowthreads(
+__global__ void __launch_bounds__(512) k_gather_rowthreads(
     const double4* __restrict__ xyz, const uint32_t* __restrict__ keys,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ csr, int ns, int ring_first,
     int ring_last, uint32_t pix_base, GridGeom g, double support_rad, double c2R, double wscale,
@@ -101,8 +101,8 @@ extern "C" hcg_status hcg_grid_rowthreads(hcg_plan_t plan, const float* spectra,
   if (!spectra || !map) return fail(HCG_E_ARG, "hcg_grid_rowthreads: NULL pointer");
   if (gamma < 1 || gamma > 4)
     return fail(HCG_E_ARG, "hcg_grid_rowthreads: gamma must be 1 .. 4 (got %d)", gamma);
-  if (block < 64 || block > 1024 || block % 64 != 0)
-    return fail(HCG_E_ARG, "hcg_grid_rowthreads: block must be a multiple of 64 in 64 .. 1024");
+  if (block < 64 || block > 512 || block % 64 != 0)
+    return fail(HCG_E_ARG, "hcg_grid_rowthreads: block must be a multiple of 64 in 64 .. 512");
   const hcg_plan_s* p = plan;
   const GridGeom g = p->grid;
   const int64_t threads = (int64_t)((g.nx + gamma - 1) / gamma) * g.ny;

@@ -5,7 +5,7 @@ and 3.5), against the FP64 oracle and against hcg_grid on one channel.
 Both kernels sum in FP64 and differ only in the order of the sums, so the
 maps must agree to 1e-6 relative per cell (W too) and with the oracle to the
 FP32 bound of 1e-5; NaN patterns identical.  Cases: every gamma with ragged
-row ends, block sizes 64 .. 1024, longitude wrap, polar cap, south, a wide
+row ends, block sizes 64 .. 512, longitude wrap, polar cap, south, a wide
 support, empty cells, and the 5 deg x 5 deg, 90 x 90 field of the paper's
 experiments at 10^7 samples with sampled cells."""
 import numpy as np
@@ -56,7 +56,7 @@ def _check(w, gamma, block, what):
 
 
 @pytest.mark.parametrize("gamma", [1, 2, 3, 4])
-@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("block", [64, 256, 512])
 def test_gamma_and_block(gamma, block):
     w = synth.small_cube(n=15_000, nchan=1, nx=29, ny=19)  # 29 cells: ragged for gamma 2, 3, 4
     _check(w, gamma, block, f"gamma {gamma} block {block}")
@@ -90,7 +90,7 @@ def test_argument_errors():
                         nside=w.nside)
     spec = w.spectra[:, 0].contiguous().to(DEV)
     V = torch.empty((8, 8), dtype=torch.float32, device=DEV)
-    for gamma, block in [(0, 64), (5, 64), (1, 32), (1, 100), (1, 2048)]:
+    for gamma, block in [(0, 64), (5, 64), (1, 32), (1, 100), (1, 1024)]:
         with pytest.raises(hcg.HcgError):
             hcg.hcg_grid_rowthreads(plan, spec, V, gamma=gamma, block=block)
     with pytest.raises(ValueError):
