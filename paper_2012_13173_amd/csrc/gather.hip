@@ -1071,6 +1071,10 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
   return HCG_OK;
 }
 
+// Below this many 512-channel workgroups (two per CU on 256 CUs, twice
+// over) a gather takes 256-channel slabs.
+constexpr int64_t kFewGroups = 1024;
+
 template <int kForm, bool kPacked = false>
 static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void* spec_lo,
                               const float* scale, int64_t C, float* cube, float* wmap,
@@ -1103,8 +1107,10 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
     return fail(HCG_E_ARG, "hcg_grid_packed: spectra must be %zu-byte aligned", 8 * esz);
   a.vec = vec ? 1 : 0;
   // 512-channel slabs (weights computed once per 512 channels) where the
-  // registers allow it, else 256
-  const int qw = (C > 256 && vec && kForm != kBF16Split) ? 2 : 1;
+  // registers allow it, else 256; a map of few tiles takes 256-channel slabs
+  // too, for twice the workgroups (512-channel slabs would leave CUs idle)
+  const int64_t groups512 = (int64_t)a.ntiles * ((C + 511) / 512);
+  const int qw = (C > 256 && vec && kForm != kBF16Split && groups512 >= kFewGroups) ? 2 : 1;
   const int64_t slab_ch = 256 * qw;
   const int64_t slabs = (C + slab_ch - 1) / slab_ch;
   const int64_t blocks = slabs * a.tiles_per_xcd * 8;
