@@ -17,6 +17,12 @@ What it computes (HCGrid, Wang et al. 2020):
 * ``ring_csr`` -- the second-level lookup table of Section 3.3 step III: for
   each ring, the position in the sorted sample array where that ring begins,
   followed by an end sentinel.
+* ``neighbours`` -- the samples within R of each listed cell (all pairs).
+* ``grid_points`` -- Eq. (1) at arbitrary cell centres (the pixel centres of
+  a projected WCS map, Section 2.1), with the kernel shapes of Section 3.6
+  (iii) -- Gaussian, elliptical Gaussian, Gaussian-tapered sinc -- and
+  per-channel flags (a non-finite value leaves its sample out of that channel,
+  which then has its own weight sum).
 """
 from __future__ import annotations
 
@@ -41,6 +47,12 @@ def build(verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("fwhm_deg", ctypes.c_double),
+                ("fwhm_minor_deg", ctypes.c_double), ("pa_deg", ctypes.c_double),
+                ("sinc_deg", ctypes.c_double), ("taper_deg", ctypes.c_double)]
 
 
 class _Grid(ctypes.Structure):
@@ -71,8 +83,6 @@ def _load():
     lib.orc_hpx_ang2pix_many.argtypes = [i64, i64, vp, vp, vp]
     lib.orc_sigma_rad.restype = f64
     lib.orc_sigma_rad.argtypes = [f64]
-    lib.orc_distance_deg.restype = f64
-    lib.orc_distance_deg.argtypes = [f64, f64, f64, f64]
     lib.orc_grid_allpairs.restype = ctypes.c_int
     lib.orc_grid_allpairs.argtypes = [i64, vp, vp, vp, i64, ctypes.POINTER(_Grid), f64, f64,
                                       vp, vp, vp]
@@ -81,8 +91,9 @@ def _load():
                                    vp, vp, vp, vp]
     lib.orc_neighbours.restype = ctypes.c_int
     lib.orc_neighbours.argtypes = [i64, vp, vp, ctypes.POINTER(_Grid), f64, i64, vp, vp, vp, vp]
-    lib.orc_needed_samples.restype = ctypes.c_int
-    lib.orc_needed_samples.argtypes = [i64, vp, vp, ctypes.POINTER(_Grid), f64, i64, vp, vp]
+    lib.orc_grid_points.restype = ctypes.c_int
+    lib.orc_grid_points.argtypes = [i64, vp, vp, vp, i64, i64, vp, vp, ctypes.POINTER(_Kernel),
+                                    f64, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.orc_set_threads.restype = None
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_max_threads.restype = ctypes.c_int
@@ -182,10 +193,6 @@ def sigma_rad(fwhm_deg: float) -> float:
     return float(_load().orc_sigma_rad(fwhm_deg))
 
 
-def distance_deg(lon1, lat1, lon2, lat2) -> float:
-    return float(_load().orc_distance_deg(lon1, lat1, lon2, lat2))
-
-
 def _inputs(lon, lat, spec):
     lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
     lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
@@ -249,15 +256,63 @@ def neighbours(lon, lat, grid, support_deg: float, cells):
     return [out[offsets[q]:offsets[q + 1]] for q in range(cells.shape[0])]
 
 
-def needed_samples(lon, lat, grid, support_deg: float, cells) -> np.ndarray:
-    """Indices of the samples within R of at least one listed cell."""
-    lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
-    lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
-    cells = np.ascontiguousarray(cells, dtype=np.int64).ravel()
-    mask = np.empty(lon.shape[0], dtype=np.uint8)
-    g = _grid(grid)
-    rc = _load().orc_needed_samples(lon.shape[0], _ptr(lon), _ptr(lat), ctypes.byref(g),
-                                    support_deg, cells.shape[0], _ptr(cells), _ptr(mask))
+# --------------------------------------------------------------------------
+# Eq. (1) at arbitrary cell centres, kernel shapes and per-channel flags
+# --------------------------------------------------------------------------
+
+GAUSS, ELLIPTIC_GAUSS, TAPERED_SINC = 0, 1, 2
+
+
+class Kernel:
+    """A kernel w(g, n) of Section 3.6 (iii) (see ``hcg_oracle.c``):
+
+    * ``Kernel.gauss(fwhm)`` -- exp(-d^2 / 2 sigma^2);
+    * ``Kernel.elliptic(fwhm_major, fwhm_minor, pa_deg)`` -- a Gaussian with
+      sigmas along the major axis (position angle ``pa_deg`` from north
+      through east) and the minor axis, evaluated at the sample's bearing;
+    * ``Kernel.tapered_sinc(b, a)`` -- sinc(d / b) exp(-(d / a)^2).
+    All widths in degrees."""
+
+    def __init__(self, type_, fwhm=0.0, fwhm_minor=0.0, pa=0.0, sinc=0.0, taper=0.0):
+        self.type, self.fwhm, self.fwhm_minor = int(type_), float(fwhm), float(fwhm_minor)
+        self.pa, self.sinc, self.taper = float(pa), float(sinc), float(taper)
+
+    @classmethod
+    def gauss(cls, fwhm_deg):
+        return cls(GAUSS, fwhm=fwhm_deg)
+
+    @classmethod
+    def elliptic(cls, fwhm_major_deg, fwhm_minor_deg, pa_deg):
+        return cls(ELLIPTIC_GAUSS, fwhm=fwhm_major_deg, fwhm_minor=fwhm_minor_deg, pa=pa_deg)
+
+    @classmethod
+    def tapered_sinc(cls, sinc_deg, taper_deg):
+        return cls(TAPERED_SINC, sinc=sinc_deg, taper=taper_deg)
+
+    def _c(self) -> _Kernel:
+        return _Kernel(self.type, self.fwhm, self.fwhm_minor, self.pa, self.sinc, self.taper)
+
+
+def grid_points(lon, lat, spec, cell_lon, cell_lat, support_deg: float, kernel: Kernel,
+                masked: bool = False, allpairs: bool = False):
+    """Eq. (1) at the listed cell centres (degrees; non-finite centres are
+    cells without samples).  ``masked``: a non-finite spectrum value flags
+    that sample in that channel only, which then has its own weight sum.
+
+    Returns (V [ncells, C], W [ncells] or [ncells, C] when masked, npair [ncells])."""
+    lon, lat, spec = _inputs(lon, lat, spec)
+    n, C = spec.shape
+    cl = np.ascontiguousarray(cell_lon, dtype=np.float64).ravel()
+    cb = np.ascontiguousarray(cell_lat, dtype=np.float64).ravel()
+    if cl.shape != cb.shape:
+        raise ValueError("cell_lon and cell_lat must have the same length")
+    V = np.empty((cl.shape[0], C), dtype=np.float64)
+    W = np.empty((cl.shape[0], C) if masked else (cl.shape[0],), dtype=np.float64)
+    npair = np.empty(cl.shape[0], dtype=np.int64)
+    k = kernel._c()
+    rc = _load().orc_grid_points(n, _ptr(lon), _ptr(lat), _ptr(spec), C, cl.shape[0], _ptr(cl),
+                                 _ptr(cb), ctypes.byref(k), float(support_deg), int(bool(masked)),
+                                 int(bool(allpairs)), _ptr(V), _ptr(W), _ptr(npair))
     if rc != 0:
-        raise ValueError(f"orc_needed_samples failed ({rc})")
-    return np.nonzero(mask)[0]
+        raise ValueError(f"orc_grid_points failed ({rc})")
+    return V, W, npair

@@ -185,10 +185,6 @@ double orc_sigma_rad(double fwhm_deg) {
   return fwhm_deg * ORC_DEG2RAD / (2.0 * sqrt(2.0 * log(2.0)));
 }
 
-double orc_distance_deg(double lon1, double lat1, double lon2, double lat2) {
-  return gc_dist(lon1, lat1, lon2, lat2) / ORC_DEG2RAD;
-}
-
 /* Neumaier-compensated accumulation */
 static inline void nsum_add(double* s, double* c, double x) {
   double t = *s + x;
@@ -467,38 +463,153 @@ int orc_neighbours(int64_t n, const double* lon, const double* lat, const orc_gr
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Eq. (1) at arbitrary cell centres, with the kernel shapes of Section 3.6  */
+/* (iii) and per-channel flags.                                              */
+/* ------------------------------------------------------------------------ */
+
 /*
- * The union of the samples within R of any listed cell (bucketed search),
- * written as a 0/1 mask over the n samples.  Used to ship only the needed
- * spectra rows to the oracle for large inputs.
+ * Kernel w(g, n) of a cell g and a sample n at great-circle distance d
+ * (d <= R; pairs beyond R have w = 0):
+ *   type 0  Gaussian              exp(-d^2 / (2 sigma^2)), sigma from fwhm_deg;
+ *   type 1  elliptical Gaussian   exp(-d^2/2 [cos^2(b - pa) / sa^2 + sin^2(b - pa) / sb^2])
+ *           with b the position angle (bearing, from north through east) of
+ *           the sample seen from the cell, sa / sb the sigmas of the major
+ *           (fwhm_deg) and minor (fwhm_minor_deg) axes and pa the position
+ *           angle of the major axis (pa_deg);
+ *   type 2  Gaussian-tapered sinc sinc(d / b) exp(-(d / a)^2), sinc(x) =
+ *           sin(pi x) / (pi x), b = sinc_deg, a = taper_deg: the sinc that
+ *           Section 3.6 (iii) names as the optimal kernel of infinite length,
+ *           cut to finite length by a Gaussian taper.
  */
-int orc_needed_samples(int64_t n, const double* lon, const double* lat, const orc_grid* g,
-                       double support_deg, int64_t ncells, const int64_t* cells, uint8_t* mask) {
-  orc_buckets b;
-  if (buckets_build(&b, n, lon, lat, support_deg)) { buckets_free(&b); return 2; }
-  double R = support_deg * ORC_DEG2RAD;
-  memset(mask, 0, (size_t)n);
-#pragma omp parallel
-  {
-    int64_t* cand = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-#pragma omp for schedule(dynamic, 1)
-    for (int64_t q = 0; q < ncells; ++q) {
-      double clon, clat;
-      int64_t cell = cells[q];
-      cell_centre(g, cell % g->nx, cell / g->nx, &clon, &clat);
-      int64_t nc = buckets_candidates(&b, clon, clat, support_deg, cand);
-      for (int64_t m = 0; m < nc; ++m) {
-        int64_t k = cand[m];
-        if (gc_dist(clon, clat, lon[k], lat[k]) <= R) {
-#pragma omp atomic write
-          mask[k] = 1;
-        }
+typedef struct {
+  int32_t type;
+  double fwhm_deg, fwhm_minor_deg, pa_deg, sinc_deg, taper_deg;
+} orc_kernel;
+
+/* initial bearing of (lon2, lat2) seen from (lon1, lat1), radians, east of north */
+static double gc_bearing(double lon1, double lat1, double lon2, double lat2) {
+  double p1 = lat1 * ORC_DEG2RAD, p2 = lat2 * ORC_DEG2RAD;
+  double dl = (lon2 - lon1) * ORC_DEG2RAD;
+  return atan2(sin(dl) * cos(p2), cos(p1) * sin(p2) - sin(p1) * cos(p2) * cos(dl));
+}
+
+static double kernel_weight(const orc_kernel* k, double d, double clon, double clat, double slon,
+                            double slat) {
+  if (k->type == 0) {
+    double s = orc_sigma_rad(k->fwhm_deg);
+    return exp(-(d * d) / (2.0 * s * s));
+  }
+  if (k->type == 1) {
+    if (d == 0.0) return 1.0;
+    double sa = orc_sigma_rad(k->fwhm_deg), sb = orc_sigma_rad(k->fwhm_minor_deg);
+    double t = gc_bearing(clon, clat, slon, slat) - k->pa_deg * ORC_DEG2RAD;
+    double ct = cos(t), st = sin(t);
+    return exp(-0.5 * d * d * (ct * ct / (sa * sa) + st * st / (sb * sb)));
+  }
+  double x = d / (k->sinc_deg * ORC_DEG2RAD);
+  double sinc = (x == 0.0) ? 1.0 : sin(ORC_PI * x) / (ORC_PI * x);
+  double u = d / (k->taper_deg * ORC_DEG2RAD);
+  return sinc * exp(-u * u);
+}
+
+static int kernel_valid(const orc_kernel* k) {
+  if (k->type == 0) return k->fwhm_deg > 0.0;
+  if (k->type == 1) return k->fwhm_deg > 0.0 && k->fwhm_minor_deg > 0.0 && isfinite(k->pa_deg);
+  if (k->type == 2) return k->sinc_deg > 0.0 && k->taper_deg > 0.0;
+  return 0;
+}
+
+/* One cell at (clon, clat) over a candidate list that holds every sample with
+ * d <= R.  masked = 0: W[0] = sum of the weights, V[c] = U[c] / W[0].
+ * masked = 1: a non-finite value s_n[c] is a flag -- sample n is left out of
+ * channel c, numerator and weights alike -- so W[c] = sum over the unflagged
+ * samples of channel c and V[c] = U[c] / W[c].  V is NaN where its W is 0. */
+static void grid_one_point(double clon, double clat, int64_t ncand, const int64_t* cand,
+                           const double* lon, const double* lat, const float* spec, int64_t C,
+                           double R, const orc_kernel* k, int masked, double* Vout, double* Wout,
+                           int64_t* npair_out, double* num, double* numc, double* ws,
+                           double* wc) {
+  int64_t np = 0;
+  int64_t nw = masked ? C : 1;
+  for (int64_t c = 0; c < C; ++c) { num[c] = 0.0; numc[c] = 0.0; }
+  for (int64_t c = 0; c < nw; ++c) { ws[c] = 0.0; wc[c] = 0.0; }
+  for (int64_t q = 0; q < ncand; ++q) {
+    int64_t m = cand ? cand[q] : q;
+    double d = gc_dist(clon, clat, lon[m], lat[m]);
+    if (!(d <= R)) continue;
+    double w = kernel_weight(k, d, clon, clat, lon[m], lat[m]);
+    ++np;
+    const float* row = spec + m * C;
+    if (!masked) {
+      nsum_add(&ws[0], &wc[0], w);
+      for (int64_t c = 0; c < C; ++c) nsum_add(&num[c], &numc[c], w * (double)row[c]);
+    } else {
+      for (int64_t c = 0; c < C; ++c) {
+        if (!isfinite(row[c])) continue;
+        nsum_add(&ws[c], &wc[c], w);
+        nsum_add(&num[c], &numc[c], w * (double)row[c]);
       }
     }
-    free(cand);
   }
-  buckets_free(&b);
-  return 0;
+  *npair_out = np;
+  for (int64_t c = 0; c < nw; ++c) Wout[c] = ws[c] + wc[c];
+  for (int64_t c = 0; c < C; ++c) {
+    double W = Wout[masked ? c : 0];
+    Vout[c] = (W != 0.0) ? (num[c] + numc[c]) / W : NAN;
+  }
+}
+
+/*
+ * Eq. (1) at ncells arbitrary cell centres (cell_lon/cell_lat, degrees): a
+ * target grid given by the world coordinates of its pixel centres, as a
+ * projected (WCS) map gives them.  allpairs = 1 tests every (cell, sample)
+ * pair; 0 takes the candidates of the latitude-band search, which only skips
+ * pairs with d > R.  V is [ncells][C]; W is [ncells] (masked = 0) or
+ * [ncells][C] (masked = 1); npair[ncells] (optional) counts the samples
+ * within R.  A cell centre that is not finite has no samples (W = 0, V =
+ * NaN).  Returns 0 on success.
+ */
+int orc_grid_points(int64_t n, const double* lon, const double* lat, const float* spec,
+                    int64_t C, int64_t ncells, const double* cell_lon, const double* cell_lat,
+                    const orc_kernel* k, double support_deg, int masked, int allpairs, double* V,
+                    double* W, int64_t* npair) {
+  if (n < 0 || C < 1 || ncells < 0 || !(support_deg >= 0.0) || !kernel_valid(k)) return 1;
+  orc_buckets b;
+  memset(&b, 0, sizeof(b));
+  if (!allpairs && buckets_build(&b, n, lon, lat, support_deg)) { buckets_free(&b); return 2; }
+  double R = support_deg * ORC_DEG2RAD;
+  int64_t nw = masked ? C : 1;
+  int err = 0;
+#pragma omp parallel
+  {
+    double* num = (double*)malloc(sizeof(double) * C);
+    double* numc = (double*)malloc(sizeof(double) * C);
+    double* ws = (double*)malloc(sizeof(double) * nw);
+    double* wc = (double*)malloc(sizeof(double) * nw);
+    int64_t* cand = allpairs ? NULL : (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!num || !numc || !ws || !wc || (!allpairs && !cand)) {
+#pragma omp atomic write
+      err = 3;
+    }
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < ncells; ++q) {
+      if (err) continue;
+      double clon = cell_lon[q], clat = cell_lat[q];
+      int64_t np = 0, nc = 0;
+      if (isfinite(clon) && isfinite(clat)) {
+        nc = allpairs ? n : buckets_candidates(&b, clon, clat, support_deg, cand);
+      } else {
+        clon = clat = 0.0;
+      }
+      grid_one_point(clon, clat, nc, allpairs ? NULL : cand, lon, lat, spec, C, R, k, masked,
+                     V + q * C, W + q * nw, &np, num, numc, ws, wc);
+      if (npair) npair[q] = np;
+    }
+    free(num); free(numc); free(ws); free(wc); free(cand);
+  }
+  if (!allpairs) buckets_free(&b);
+  return err;
 }
 
 void orc_set_threads(int nthreads) {
