@@ -133,14 +133,117 @@ hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_de
                     const hcg_grid_desc* grid, double fwhm_deg, double support_deg,
                     const hcg_opts* opts, void* hip_stream);
 
+/* Kernel shapes w(g, n) for a pair at great-circle distance d <= R
+ * (Section 3.6 (iii): the Gaussian is the default; the sinc is the optimal
+ * kernel of infinite length, used here with a Gaussian taper):
+ *   HCG_KERNEL_GAUSS           exp(-d^2 / (2 sigma^2)), sigma from fwhm_deg.
+ *   HCG_KERNEL_ELLIPTIC_GAUSS  exp(-d^2/2 [cos^2(b - pa) / sa^2 + sin^2(b - pa) / sb^2]),
+ *                              b the bearing of the sample seen from the cell
+ *                              (east of north), sa and sb the sigmas of the
+ *                              major (fwhm_deg) and minor (fwhm_minor_deg)
+ *                              axes, pa = pa_deg the position angle of the
+ *                              major axis; 1 at d = 0.  At a pole the bearing
+ *                              is taken in the frame of longitude 0.
+ *   HCG_KERNEL_TAPERED_SINC    sinc(d / b) exp(-(d / a)^2), sinc(x) = sin(pi x) /
+ *                              (pi x), b = sinc_deg, a = taper_deg.  Weights
+ *                              can be negative; V is NaN where W = 0.
+ * Unused fields are ignored.  The automatic nside follows the sigma/2 rule
+ * with sigma of the Gaussian, of the minor axis, or half the smaller of a
+ * and b. */
+typedef enum {
+  HCG_KERNEL_GAUSS = 0,
+  HCG_KERNEL_ELLIPTIC_GAUSS = 1,
+  HCG_KERNEL_TAPERED_SINC = 2
+} hcg_kernel_type;
+
+typedef struct {
+  int32_t type;          /* hcg_kernel_type */
+  double fwhm_deg;       /* Gaussian FWHM; elliptical: major axis */
+  double fwhm_minor_deg; /* elliptical: minor axis */
+  double pa_deg;         /* elliptical: position angle of the major axis */
+  double sinc_deg;       /* tapered sinc: b, the first zero */
+  double taper_deg;      /* tapered sinc: a, the Gaussian taper width */
+} hcg_kernel;
+
+/* Target cells given by their centres: the pixel centres of a projected
+ * (WCS) map, which the paper grids onto (Section 2.1).  lon_deg / lat_deg
+ * are device float64 [ny][nx]; a centre that is not finite (or |lat| > 90)
+ * is a cell that no sample reaches (W = 0, V = NaN).  hcg_wcs_centres
+ * computes them for the CAR, SFL, SIN and TAN projections. */
+typedef struct {
+  int32_t nx, ny;
+  const double* lon_deg;
+  const double* lat_deg;
+} hcg_cell_centres;
+
+/* A projected map: FITS world coordinates with a diagonal CDELT (Calabretta
+ * & Greisen 2002, the reference the paper gives for its WCS-space gridding,
+ * Section 2.1).  Pixel (ix, iy) of the [ny][nx] map is FITS pixel
+ * (ix + 1, iy + 1).  lonpole: LONPOLE in degrees when lonpole_set, else its
+ * default (0 when CRVAL2 >= theta_0, else 180; theta_0 = 0 for CAR and SFL,
+ * 90 for SIN and TAN); latpole: LATPOLE in degrees (FITS default 90), which
+ * picks between the two celestial poles a cylindrical map can have. */
+typedef enum {
+  HCG_PROJ_CAR = 0, /* plate carree */
+  HCG_PROJ_SFL = 1, /* Sanson-Flamsteed */
+  HCG_PROJ_SIN = 2, /* orthographic (no xi / eta terms) */
+  HCG_PROJ_TAN = 3  /* gnomonic */
+} hcg_projection;
+
+typedef struct {
+  int32_t proj;         /* hcg_projection */
+  int32_t nx, ny;
+  int32_t lonpole_set;
+  double crpix1, crpix2; /* reference pixel (1-based) */
+  double cdelt1, cdelt2; /* degrees per pixel, non-zero */
+  double crval1, crval2; /* world coordinates of the reference pixel */
+  double lonpole, latpole;
+} hcg_wcs;
+
+/*
+ * hcg_wcs_centres -- world coordinates (lon, lat in degrees, lon in
+ * [0, 360)) of every pixel centre of a projected map, into device float64
+ * lon_deg / lat_deg [ny][nx]: pixel -> intermediate world coordinates ->
+ * native spherical coordinates (the projection's inverse) -> celestial
+ * coordinates (Paper II eq. (2), with the celestial pole from eqs. (8) to
+ * (10)).  Pixels outside the projection's domain (SIN beyond its disc) get
+ * NaN.  The result feeds hcg_plan_ex as hcg_cell_centres.  Asynchronous on
+ * hip_stream.  Errors: HCG_E_ARG (NULL pointer, bad sizes, zero CDELT,
+ * non-finite parameters, |CRVAL2| > 90, a LONPOLE that reaches no celestial
+ * pole), HCG_E_UNSUPPORTED (projection), HCG_E_DEVICE.
+ */
+hcg_status hcg_wcs_centres(const hcg_wcs* wcs, double* lon_deg, double* lat_deg,
+                           void* hip_stream);
+
+/*
+ * hcg_plan_ex -- hcg_plan for any kernel shape and for a target given
+ * either as a linear grid (grid, centres = NULL) or by cell centres (grid =
+ * NULL).  With centres, the candidate search of each 8 x 8 tile starts from
+ * the smallest cap (about the normalised mean of its cells) that holds them,
+ * widened by R; the result is the same Eq. (1).  The centre arrays are read
+ * during the call only.  Errors as hcg_plan, plus HCG_E_ARG for both or
+ * neither of grid and centres, bad centre dimensions or kernel parameters,
+ * and HCG_E_UNSUPPORTED for an unknown kernel type or tiles whose cells
+ * spread over more rings than the range table holds.
+ */
+hcg_status hcg_plan_ex(hcg_plan_t* out, const double* lon_deg, const double* lat_deg, int64_t n,
+                       const hcg_grid_desc* grid, const hcg_cell_centres* centres,
+                       const hcg_kernel* kernel, double support_deg, const hcg_opts* opts,
+                       void* hip_stream);
+
 /*
  * hcg_grid -- Eq. (1) for every cell and channel of the plan's grid.
  *
  *   spectra     device [n][nchan] in the sample order given to hcg_plan,
  *               channel-fastest, in the storage type of dtype (two planes
- *               for the split dtypes).  Values must be finite: a non-finite
- *               value reaches every cell of the 4 x 4 cell block that
- *               shares its matrix-core step, not only the cells within R.
+ *               for the split dtypes).  Values should be finite: with
+ *               nchan <= 8 (FP32) a non-finite value reaches exactly the
+ *               cells within R of its sample, but the matrix-core forms
+ *               multiply zero weights too (0 x NaN = NaN), so it can reach
+ *               any cell of an 8 x 8 tile that lists the sample as a
+ *               candidate (within about R + the tile's diagonal + one
+ *               HEALPix pixel).  Data with flagged (NaN) values go through
+ *               hcg_grid_masked, which leaves them out channel by channel.
  *   nchan       >= 1.
  *   chan_scale  device float [nchan] for the scaled dtypes (the scales the
  *               encoding used); NULL for the others.
@@ -158,6 +261,22 @@ hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_de
  */
 hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dtype dtype,
                     const float* chan_scale, float* cube, float* weights, void* hip_stream);
+
+/*
+ * hcg_grid_masked -- Eq. (1) with per-channel flags, for data whose flagged
+ * values (RFI, Section 4) are non-finite: a NaN or infinite s_n[c] leaves
+ * sample n out of channel c, from the numerator and from that channel's
+ * weight sum alike, so every channel has its own W.
+ *   spectra       device float32 [n][nchan] (input sample order).
+ *   cube          device float32 [nchan][ny][nx]: V[c] = U[c] / W[c], NaN
+ *                 where W[c] = 0.
+ *   chan_weights  device float32 [nchan][ny][nx] or NULL: W[c] (FP64 sums
+ *                 for nchan <= 8, FP32 matrix-core sums otherwise).
+ * FP32 only.  Asynchronous on hip_stream.  Errors: HCG_E_ARG (NULL spectra
+ * or cube, nchan < 1), HCG_E_STATE, HCG_E_DEVICE.
+ */
+hcg_status hcg_grid_masked(hcg_plan_t plan, const float* spectra, int64_t nchan, float* cube,
+                           float* chan_weights, void* hip_stream);
 
 /*
  * hcg_quantize -- encode float32 spectra for a low-precision form of
@@ -407,10 +526,13 @@ hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_des
  * shared counter.  The first call may run the batch several times to
  * autotune (same results every time); it then captures the launch in a
  * hipGraph that later calls replay.  Pointers and channel counts may change
- * between calls (the device tables are rewritten before the replay).
+ * between calls (the device tables are rewritten before the replay; the
+ * rewrite waits for the previous launch, on whichever stream it ran).
  * Asynchronous on hip_stream after the first call (which synchronises).
  * Errors: HCG_E_ARG (NULL pointers, nchan < 1), HCG_E_STATE (not a live
- * batch), HCG_E_NOMEM, HCG_E_DEVICE.  Calls on one batch must not overlap.
+ * batch), HCG_E_NOMEM, HCG_E_DEVICE.  Calls on one batch must not overlap
+ * on the host (one thread at a time); the outputs of successive calls are
+ * written in call order.
  */
 hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* data, void* hip_stream);
 

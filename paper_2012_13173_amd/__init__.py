@@ -25,6 +25,9 @@ HCG_OK, HCG_E_ARG, HCG_E_NOMEM, HCG_E_DEVICE, HCG_E_UNSUPPORTED, HCG_E_STATE = r
 (HCG_F32, HCG_BF16, HCG_BF16_SPLIT, HCG_F16_SCALED, HCG_FP8E4M3_SCALED,
  HCG_FP8E4M3_SPLIT) = range(6)
 HCG_ARR_KEYS, HCG_ARR_PERM, HCG_ARR_RING_CSR, HCG_ARR_TILE_NRANGES, HCG_ARR_TILE_RANGES = range(5)
+HCG_KERNEL_GAUSS, HCG_KERNEL_ELLIPTIC_GAUSS, HCG_KERNEL_TAPERED_SINC = range(3)
+HCG_PROJ_CAR, HCG_PROJ_SFL, HCG_PROJ_SIN, HCG_PROJ_TAN = range(4)
+PROJECTIONS = {"CAR": HCG_PROJ_CAR, "SFL": HCG_PROJ_SFL, "SIN": HCG_PROJ_SIN, "TAN": HCG_PROJ_TAN}
 STATUS_NAMES = {0: "HCG_OK", 1: "HCG_E_ARG", 2: "HCG_E_NOMEM", 3: "HCG_E_DEVICE",
                 4: "HCG_E_UNSUPPORTED", 5: "HCG_E_STATE"}
 
@@ -45,6 +48,26 @@ class OptsC(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("coarsen", ctypes.c_int32), ("chan_tile", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class KernelC(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("fwhm_deg", ctypes.c_double),
+                ("fwhm_minor_deg", ctypes.c_double), ("pa_deg", ctypes.c_double),
+                ("sinc_deg", ctypes.c_double), ("taper_deg", ctypes.c_double)]
+
+
+class CellCentresC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("lon_deg", ctypes.c_void_p),
+                ("lat_deg", ctypes.c_void_p)]
+
+
+class WcsC(ctypes.Structure):
+    _fields_ = [("proj", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("lonpole_set", ctypes.c_int32), ("crpix1", ctypes.c_double),
+                ("crpix2", ctypes.c_double), ("cdelt1", ctypes.c_double),
+                ("cdelt2", ctypes.c_double), ("crval1", ctypes.c_double),
+                ("crval2", ctypes.c_double), ("lonpole", ctypes.c_double),
+                ("latpole", ctypes.c_double)]
 
 
 class PlanInfoC(ctypes.Structure):
@@ -84,7 +107,8 @@ EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_pl
             "hcg_export", "hcg_export_size", "hcg_get_plan_stats", "hcg_ang2pix",
             "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
             "hcg_destroy_batch", "hcg_get_batch_info", "hcg_quantize_packed", "hcg_grid_packed",
-            "hcg_packed_bytes", "hcg_grid_host", "hcg_grid_rowthreads"]
+            "hcg_packed_bytes", "hcg_grid_host", "hcg_grid_rowthreads", "hcg_plan_ex",
+            "hcg_grid_masked", "hcg_wcs_centres"]
 
 _lib = None
 
@@ -101,6 +125,11 @@ def load(path: str = LIB_PATH):
     lib.hcg_plan.argtypes = [ctypes.POINTER(vp), vp, vp, i64, ctypes.POINTER(GridDescC), f64, f64,
                              ctypes.POINTER(OptsC), vp]
     lib.hcg_grid.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    lib.hcg_plan_ex.argtypes = [ctypes.POINTER(vp), vp, vp, i64, ctypes.POINTER(GridDescC),
+                                ctypes.POINTER(CellCentresC), ctypes.POINTER(KernelC), f64,
+                                ctypes.POINTER(OptsC), vp]
+    lib.hcg_grid_masked.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.hcg_wcs_centres.argtypes = [ctypes.POINTER(WcsC), vp, vp, vp]
     lib.hcg_destroy.argtypes = [vp]
     lib.hcg_last_error.restype = ctypes.c_char_p
     lib.hcg_last_error.argtypes = []
@@ -157,9 +186,10 @@ def grid_desc(g) -> GridDescC:
 class Plan:
     """Owns an hcg_plan_t; destroyed explicitly or on garbage collection."""
 
-    def __init__(self, handle: ctypes.c_void_p, grid):
+    def __init__(self, handle: ctypes.c_void_p, grid, n: int):
         self.handle = handle
         self.grid = grid
+        self.n = int(n)
 
     def info(self) -> dict:
         out = PlanInfoC()
@@ -206,7 +236,107 @@ def hcg_plan(lon: torch.Tensor, lat: torch.Tensor, grid, fwhm_deg: float, suppor
                       _dptr(lat, torch.float64, "lat"), n, ctypes.byref(g), float(fwhm_deg),
                       float(support_deg), ctypes.byref(opts), _stream(stream))
     _check(st, "hcg_plan")
-    return Plan(handle, grid)
+    return Plan(handle, grid, n)
+
+
+class Kernel:
+    """A kernel shape of ``hcg_plan_ex`` (widths in degrees):
+    ``Kernel.gauss(fwhm)``, ``Kernel.elliptic(fwhm_major, fwhm_minor, pa_deg)``,
+    ``Kernel.tapered_sinc(sinc_deg, taper_deg)``."""
+
+    def __init__(self, type_, fwhm=0.0, fwhm_minor=0.0, pa=0.0, sinc=0.0, taper=0.0):
+        self.c = KernelC(int(type_), float(fwhm), float(fwhm_minor), float(pa), float(sinc),
+                         float(taper))
+
+    @classmethod
+    def gauss(cls, fwhm_deg):
+        return cls(HCG_KERNEL_GAUSS, fwhm=fwhm_deg)
+
+    @classmethod
+    def elliptic(cls, fwhm_major_deg, fwhm_minor_deg, pa_deg):
+        return cls(HCG_KERNEL_ELLIPTIC_GAUSS, fwhm=fwhm_major_deg, fwhm_minor=fwhm_minor_deg,
+                   pa=pa_deg)
+
+    @classmethod
+    def tapered_sinc(cls, sinc_deg, taper_deg):
+        return cls(HCG_KERNEL_TAPERED_SINC, sinc=sinc_deg, taper=taper_deg)
+
+
+class CellGrid:
+    """Shape of a target given by cell centres (what ``Plan.grid`` needs)."""
+
+    def __init__(self, nx: int, ny: int):
+        self.nx, self.ny = int(nx), int(ny)
+
+
+def hcg_plan_ex(lon: torch.Tensor, lat: torch.Tensor, kernel: Kernel, support_deg: float,
+                grid=None, cell_lon=None, cell_lat=None, nside: int = 0, stream=None) -> Plan:
+    """Plan for any kernel shape, on a linear ``grid`` or on cell centres
+    ``cell_lon`` / ``cell_lat`` (device float64 [ny, nx], degrees)."""
+    lib = load()
+    n = int(lon.shape[0])
+    if int(lat.shape[0]) != n:
+        raise ValueError("lon and lat must have the same length")
+    if (grid is None) == (cell_lon is None):
+        raise ValueError("give exactly one of grid and cell_lon / cell_lat")
+    handle = ctypes.c_void_p()
+    opts = OptsC(int(nside), 0, 0, 0, 0, 0)
+    if grid is not None:
+        g = grid_desc(grid)
+        st = lib.hcg_plan_ex(ctypes.byref(handle), _dptr(lon, torch.float64, "lon"),
+                             _dptr(lat, torch.float64, "lat"), n, ctypes.byref(g), None,
+                             ctypes.byref(kernel.c), float(support_deg), ctypes.byref(opts),
+                             _stream(stream))
+        shape = grid
+    else:
+        if cell_lon.dim() != 2 or tuple(cell_lat.shape) != tuple(cell_lon.shape):
+            raise ValueError("cell_lon and cell_lat must be [ny, nx] of the same shape")
+        ny, nx = (int(x) for x in cell_lon.shape)
+        cc = CellCentresC(nx, ny, _dptr(cell_lon, torch.float64, "cell_lon"),
+                          _dptr(cell_lat, torch.float64, "cell_lat"))
+        st = lib.hcg_plan_ex(ctypes.byref(handle), _dptr(lon, torch.float64, "lon"),
+                             _dptr(lat, torch.float64, "lat"), n, None, ctypes.byref(cc),
+                             ctypes.byref(kernel.c), float(support_deg), ctypes.byref(opts),
+                             _stream(stream))
+        shape = CellGrid(nx, ny)
+    _check(st, "hcg_plan_ex")
+    return Plan(handle, shape, n)
+
+
+def hcg_wcs_centres(proj, nx: int, ny: int, crpix, cdelt, crval, lonpole=None, latpole=90.0,
+                    device="cuda", stream=None):
+    """World coordinates (degrees) of the pixel centres of a CAR / SFL / SIN /
+    TAN map: device float64 (lon [ny, nx], lat [ny, nx])."""
+    p = PROJECTIONS[proj.upper()] if isinstance(proj, str) else int(proj)
+    w = WcsC(p, int(nx), int(ny), 0 if lonpole is None else 1, float(crpix[0]), float(crpix[1]),
+             float(cdelt[0]), float(cdelt[1]), float(crval[0]), float(crval[1]),
+             0.0 if lonpole is None else float(lonpole), float(latpole))
+    lon = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=device)
+    lat = torch.empty_like(lon)
+    _check(load().hcg_wcs_centres(ctypes.byref(w), ctypes.c_void_p(lon.data_ptr()),
+                                  ctypes.c_void_p(lat.data_ptr()), _stream(stream)),
+           "hcg_wcs_centres")
+    return lon, lat
+
+
+def hcg_grid_masked(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, chan_weights=None,
+                    stream=None) -> None:
+    """Eq. (1) with per-channel flags: non-finite values of ``spectra`` [n, C]
+    (float32) are left out of their channel; ``cube`` [C, ny, nx] gets V and
+    ``chan_weights`` [C, ny, nx] (or None) each channel's W."""
+    if spectra.dim() != 2 or int(spectra.shape[0]) != plan.n:
+        raise ValueError(f"spectra must be [{plan.n}, nchan]")
+    C = int(spectra.shape[1])
+    g = plan.grid
+    if tuple(cube.shape) != (C, g.ny, g.nx):
+        raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
+    if chan_weights is not None and tuple(chan_weights.shape) != (C, g.ny, g.nx):
+        raise ValueError(f"chan_weights must be [{C}, {g.ny}, {g.nx}]")
+    st = load().hcg_grid_masked(plan.handle, _dptr(spectra, torch.float32, "spectra"), C,
+                                _dptr(cube, torch.float32, "cube"),
+                                _dptr(chan_weights, torch.float32, "chan_weights"),
+                                _stream(stream))
+    _check(st, "hcg_grid_masked")
 
 
 # storage dtype of each form's spectra and the shape prefix of its buffer
@@ -222,6 +352,8 @@ def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None
     sdt, prefix = _FORM_STORAGE[dtype]
     if spectra.dim() != 2 + len(prefix) or tuple(spectra.shape[:len(prefix)]) != prefix:
         raise ValueError(f"spectra must be [{', '.join(map(str, prefix + ('n', 'nchan')))}]")
+    if int(spectra.shape[-2]) != plan.n:
+        raise ValueError(f"spectra has {int(spectra.shape[-2])} rows, the plan {plan.n} samples")
     C = int(spectra.shape[-1])
     g = plan.grid
     if tuple(cube.shape) != (C, g.ny, g.nx):
@@ -255,8 +387,8 @@ def hcg_grid_host(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights
     if spectra.dim() != 2:
         raise ValueError("spectra must be [n, nchan]")
     n, C = (int(x) for x in spectra.shape)
-    if n != int(plan.info()["n"]):
-        raise ValueError(f"spectra has {n} rows, the plan {int(plan.info()['n'])} samples")
+    if n != plan.n:
+        raise ValueError(f"spectra has {n} rows, the plan {plan.n} samples")
     g = plan.grid
     if tuple(cube.shape) != (C, g.ny, g.nx):
         raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
@@ -273,7 +405,7 @@ def hcg_grid_rowthreads(plan: Plan, spectra: torch.Tensor, out: torch.Tensor, we
     into ``out`` [ny, nx] (and ``weights`` [ny, nx]), ``gamma`` cells per
     thread, ``block`` threads per block."""
     g = plan.grid
-    if spectra.dim() != 1 or int(spectra.shape[0]) != int(plan.info()["n"]):
+    if spectra.dim() != 1 or int(spectra.shape[0]) != plan.n:
         raise ValueError("spectra must be [n] with the plan's sample count")
     if tuple(out.shape) != (g.ny, g.nx):
         raise ValueError(f"out must be [{g.ny}, {g.nx}]")
@@ -305,7 +437,7 @@ def _packed_shape(plan: Plan, C: int, dtype: int):
     sdt, prefix = _FORM_STORAGE[dtype]
     if dtype == HCG_F32:
         raise ValueError("plan-ordered spectra are a low-precision form")
-    n = int(plan.info()["n"])
+    n = plan.n
     planes = prefix[0] if prefix else 1
     nbytes = ctypes.c_int64()
     _check(load().hcg_packed_bytes(plan.handle, C, int(dtype), ctypes.byref(nbytes)),
@@ -385,9 +517,10 @@ def hcg_sort_keys(keys: torch.Tensor, key_bits: int, stream=None):
 class Batch:
     """Owns an hcg_batch_t (one plan per field)."""
 
-    def __init__(self, handle: ctypes.c_void_p, grids):
+    def __init__(self, handle: ctypes.c_void_p, grids, ns):
         self.handle = handle
         self.grids = grids
+        self.ns = [int(n) for n in ns]
 
     def info(self) -> dict:
         out = BatchInfoC()
@@ -421,7 +554,7 @@ def hcg_plan_batch(fields, chan_tile: int = 0, nside: int = 0, stream=None) -> B
     handle = ctypes.c_void_p()
     _check(load().hcg_plan_batch(ctypes.byref(handle), len(fields), arr, ctypes.byref(opts),
                                  _stream(stream)), "hcg_plan_batch")
-    return Batch(handle, [f[2] for f in fields])
+    return Batch(handle, [f[2] for f in fields], [int(f[0].shape[0]) for f in fields])
 
 
 def hcg_grid_batch(batch: Batch, spectra, cubes, weights=None, stream=None) -> None:
@@ -435,9 +568,13 @@ def hcg_grid_batch(batch: Batch, spectra, cubes, weights=None, stream=None) -> N
     arr = (FieldDataC * nf)()
     for i in range(nf):
         g, sp, cb = batch.grids[i], spectra[i], cubes[i]
+        if sp.dim() != 2 or int(sp.shape[0]) != batch.ns[i]:
+            raise ValueError(f"field {i}: spectra must be [{batch.ns[i]}, nchan]")
         C = int(sp.shape[1])
         if tuple(cb.shape) != (C, g.ny, g.nx):
             raise ValueError(f"field {i}: cube must be [{C}, {g.ny}, {g.nx}]")
+        if weights[i] is not None and tuple(weights[i].shape) != (g.ny, g.nx):
+            raise ValueError(f"field {i}: weights must be [{g.ny}, {g.nx}]")
         arr[i] = FieldDataC(_dptr(sp, torch.float32, "spectra"), C,
                             _dptr(cb, torch.float32, "cube"),
                             _dptr(weights[i], torch.float32, "weights"))

@@ -11,7 +11,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["capi.hip", "plan.hip", "gather.hip", "quant.hip", "batch.hip", "stream.hip", "rowthreads.hip"]
+SOURCES = ["capi.hip", "plan.hip", "gather.hip", "quant.hip", "batch.hip", "stream.hip",
+           "rowthreads.hip", "wcs.hip"]
 LIB = os.path.join(PKG, "libhcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

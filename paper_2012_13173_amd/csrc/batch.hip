@@ -51,6 +51,10 @@ struct hcg_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_qw = 0;
+  // recorded after every launch: the next call's table updates wait for it,
+  // so a call on another stream cannot rewrite tables a launch still reads
+  hipEvent_t done = nullptr;
+  bool launched = false;
 };
 
 namespace {
@@ -65,6 +69,7 @@ bool batch_is_live(const hcg_batch_s* b) {
 }
 
 void free_batch(hcg_batch_s* b) {
+  if (b->done) (void)hipEventDestroy(b->done);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -223,7 +228,8 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||
       hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields) != hipSuccess ||
       hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl) != hipSuccess ||
-      hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     free_batch(b);
     return fail(HCG_E_NOMEM, "hcg_plan_batch: cannot allocate the batch tables");
@@ -245,6 +251,9 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
   hcg_batch_s* b = batch;
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t nf = b->plans.size();
+  // the tables below are rewritten on this stream: wait for the last launch,
+  // whichever stream it ran on
+  if (b->launched) HCG_HIP(hipStreamWaitEvent(stream, b->done, 0));
   // argument table
   bool layout_changed = b->built_C.size() != nf;
   std::vector<GatherArgs> fresh(nf);
@@ -327,6 +336,8 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     b->graph_qw = b->qw;
   }
   HCG_HIP(hipGraphLaunch(b->exec, stream));
+  HCG_HIP(hipEventRecord(b->done, stream));
+  b->launched = true;
   return HCG_OK;
 }
 

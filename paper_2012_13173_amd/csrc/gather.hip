@@ -76,8 +76,9 @@ __device__ void block_centres(const GatherArgs& a, int tx, int ty, int t, double
   const GridGeom& g = a.g;
   const int cb = t >> 4, i = t & 15;
   const int x = tx * kTileX + (cb & 1) * 4 + (i & 3), y = ty * kTileY + (cb >> 1) * 4 + (i >> 2);
-  const bool valid = x < g.nx && y < g.ny;
-  const CellVec v = cell_vec(g, x, y);
+  const bool in_grid = x < g.nx && y < g.ny;
+  const CellVec v = cell_at(a.cells, g, x, y);
+  const bool valid = in_grid && v.x == v.x;  // a cell without a centre is left out
   double sx = valid ? v.x : 0.0, sy = valid ? v.y : 0.0, sz = valid ? v.z : 0.0;
 #pragma unroll
   for (int o = 1; o < 16; o <<= 1) {
@@ -246,9 +247,16 @@ struct PackedB<kFP8Split> {
 // (hcg_quantize_packed), so a lane's B operand (8 consecutive sorted samples
 // of one channel) is one load and the loads of a block are issued before its
 // weights are computed.
-template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide, bool kAhead = true>
+// kGen: a kernel shape other than the circular Gaussian (FP64 weights through
+// pair_weight_gen).  kMask (FP32, input order): a non-finite spectrum value is
+// a flag -- it is replaced by 0 in the product and its sample is left out of
+// that channel's weight sum, accumulated by a second contraction with the
+// 0/1 flags as the B operand.
+template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide, bool kAhead = true,
+          bool kGen = false, bool kMask = false>
 __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int slab,
                                             GatherSmem& sm) {
+  static_assert(!kMask || (kForm == kF32 && !kPacked), "flags are an FP32 input-order form");
   constexpr int kK = FormTraits<kForm>::kK;
   constexpr int kNS = kKB / kK;  // k-steps per staged block
   uint2* s_rng = sm.rng;
@@ -269,7 +277,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   const int ci = lane & 15;
   const int my_x = tx * kTileX + (wave & 1) * 4 + (ci & 3);
   const int my_y = ty * kTileY + (wave >> 1) * 4 + (ci >> 2);
-  const CellVec cell = cell_vec(g, my_x, my_y);
+  const CellVec cell = cell_at(a.cells, g, my_x, my_y);
+  const CellFrame frame = kGen ? cell_frame(cell) : CellFrame{0.0, 0.0, 0.0, 0.0, 0.0};
+  // weight of this lane's cell and a staged candidate inside the support
+  auto weight = [&](double c2, const double4& v) -> float {
+    if constexpr (kGen) return (float)pair_weight_gen(a.kern, c2, v, cell, frame);
+    else return pair_weight<kWide>(c2, a.kern.wscale);
+  };
 
   const uint32_t total =
       stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre,
@@ -277,10 +291,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   if (tid < 64) block_centres(a, tx, ty, tid, sm.ctr);
 
   floatx4 acc[4][4 * kQW];
+  floatx4 accw[kMask ? 4 : 1][kMask ? 4 * kQW : 1];  // flagged form: channel weight sums
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int q = 0; q < 4 * kQW; ++q) acc[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4 * kQW; ++q) {
+      acc[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (kMask) accw[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
   double wsum = 0.0;   // FP64 sum of the unrounded weights (this lane's share)
   double wtsum = 0.0;  // FP64 sum of the weights as used in the products
   uint32_t cur = 0;
@@ -301,6 +319,18 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   // iteration.  Without kAhead (fewer registers) it loads them there.
   double nx = 0.0, ny = 0.0, nz = 0.0;
   uint32_t nrow = 0u;
+  // Padding past the last candidate has weight 0 (a NaN position) and the
+  // row or group of the last candidate, which shares the matrix-core step
+  // with every padding candidate that is ever multiplied: a non-finite
+  // spectrum value then reaches no cell through padding (0 x NaN) that it
+  // would not reach through its own candidate.
+  uint32_t pad_row = 0u;
+  if (total > 0u) {
+    uint32_t c0 = 0u;
+    const uint32_t last = cand_pos(total - 1u, s_rng, s_pre, &c0);
+    pad_row = kPacked ? last >> 3 : a.perm[last];
+  }
+  pad_row = __builtin_amdgcn_readfirstlane(pad_row);
   auto fetch = [&](uint32_t qb) {
     if (tid < kKB) {
       const uint32_t q = qb + tid;
@@ -313,7 +343,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         nrow = kPacked ? pos >> 3 : a.perm[pos];  // group of 8 sorted samples, or row
       } else {
         nx = ny = nz = __builtin_nan("");
-        nrow = 0u;  // any group or row: its weights are 0
+        nrow = pad_row;
       }
     }
   };
@@ -420,9 +450,10 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         while (pm) {
           const int ks = __builtin_ctz(pm);
           pm &= pm - 1u;
-          const double c2 = chord2(cell, s_xyz[4 * ks + (lane >> 4)]);
+          const double4 sv = s_xyz[4 * ks + (lane >> 4)];
+          const double c2 = chord2(cell, sv);
           float wf = 0.f;
-          if (c2 <= a.c2R) wf = pair_weight<kWide>(c2, a.wscale);
+          if (c2 <= a.c2R) wf = weight(c2, sv);
           wsum += (double)wf;
           sA32[(wave * kNS + ks) * 64 + lane] = wf;
           if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
@@ -441,10 +472,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
             const int k0 = kK * ks + 8 * grp;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-              const double c2 = chord2(cell, s_xyz[k0 + t]);
+              const double4 sv = s_xyz[k0 + t];
+              const double c2 = chord2(cell, sv);
               uint32_t h = 0u, l = 0u;
               if (c2 <= a.c2R) {
-                const float wf = pair_weight<kWide>(c2, a.wscale);
+                const float wf = weight(c2, sv);
                 h = enc_w<kForm>(wf);
                 double eff = (double)dec_w<kForm>(h);
                 if (kForm == kBF16Split) {
@@ -497,8 +529,21 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
       for (int ks = 0; ks < kNS; ++ks) {
         floatx4 cb_b[kQW];
+        floatx4 cb_m[kMask ? kQW : 1];
 #pragma unroll
-        for (int h = 0; h < kQW; ++h) cb_b[h] = b[ks % kDepth][h];
+        for (int h = 0; h < kQW; ++h) {
+          cb_b[h] = b[ks % kDepth][h];
+          if constexpr (kMask) {
+            // flags: a non-finite value becomes 0 in the product and 0 in
+            // the channel's weight operand
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const bool fin = (__float_as_uint(cb_b[h][e]) & 0x7F800000u) != 0x7F800000u;
+              cb_m[h][e] = fin ? 1.f : 0.f;
+              cb_b[h][e] = fin ? cb_b[h][e] : 0.f;
+            }
+          }
+        }
         if (ks + kDepth < kNS) load(ks + kDepth, b[ks % kDepth]);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
@@ -511,6 +556,12 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
               acc[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].y, acc[cb][4 * h + 1], 0, 0, 0);
               acc[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].z, acc[cb][4 * h + 2], 0, 0, 0);
               acc[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].w, acc[cb][4 * h + 3], 0, 0, 0);
+              if constexpr (kMask) {
+                accw[cb][4 * h + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].x, accw[cb][4 * h + 0], 0, 0, 0);
+                accw[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].y, accw[cb][4 * h + 1], 0, 0, 0);
+                accw[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].z, accw[cb][4 * h + 2], 0, 0, 0);
+                accw[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].w, accw[cb][4 * h + 3], 0, 0, 0);
+              }
             }
           }
         }
@@ -703,7 +754,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   wtsum += __shfl_xor(wtsum, 32);
   if (lane < 16) {
     s_Wt[wave * 16 + lane] = wtsum;
-    if (a.wmap && slab == 0 && my_x < g.nx && my_y < g.ny)
+    if (!kMask && a.wmap && slab == 0 && my_x < g.nx && my_y < g.ny)
       a.wmap[(int64_t)my_y * g.nx + my_x] = (float)wsum;
   }
   __syncthreads();
@@ -723,7 +774,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double wt = s_Wt[cb * 16 + 4 * (lane >> 4) + r];
-      has[r] = wt > 0.0;
+      has[r] = wt != 0.0;
       inv[r] = has[r] ? (float)(1.0 / wt) : 0.f;
     }
     const int64_t row0 = (int64_t)y * g.nx + x0;
@@ -737,26 +788,38 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15) : my_ch + 64 * h + q;
         if (ch >= C) continue;
         const float sc = (kForm == kF16S || is_fp8(kForm)) ? a.scale[ch] : 1.f;
-        float v[4];
+        float v[4], wc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          float t = acc[cb][4 * h + q][r] * inv[r];
-          if (kForm == kF16S || is_fp8(kForm)) t *= sc;
-          v[r] = has[r] ? t : qnan;
+          if constexpr (kMask) {
+            // the channel's own weight sum (FP32 accumulation of FP32 weights)
+            wc[r] = accw[cb][4 * h + q][r];
+            v[r] = (wc[r] != 0.f) ? acc[cb][4 * h + q][r] / wc[r] : qnan;
+          } else {
+            float t = acc[cb][4 * h + q][r] * inv[r];
+            if (kForm == kF16S || is_fp8(kForm)) t *= sc;
+            v[r] = has[r] ? t : qnan;
+          }
         }
         float* dst = a.cube + ch * G + row0;
+        float* wdst = kMask ? a.wcube + ch * G + row0 : nullptr;
         if (full) {
           *(floatx4*)dst = floatx4{v[0], v[1], v[2], v[3]};
+          if (kMask && wdst) *(floatx4*)wdst = floatx4{wc[0], wc[1], wc[2], wc[3]};
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            if (x0 + r < g.nx) dst[r] = v[r];
+            if (x0 + r < g.nx) {
+              dst[r] = v[r];
+              if (kMask && wdst) wdst[r] = wc[r];
+            }
         }
       }
   }
 }
 
-template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide>
+template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide, bool kGen = false,
+          bool kMask = false>
 __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   __shared__ GatherSmem sm;
   // XCD-aware order: the hardware deals consecutive workgroups to the eight
@@ -767,7 +830,7 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   const int local = blockIdx.x - slab * per_slab;
   const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
   if (tile >= a.ntiles) return;
-  gather_tile<kForm, kQW, kVec, kPacked, kWide>(a, tile, slab, sm);
+  gather_tile<kForm, kQW, kVec, kPacked, kWide, true, kGen, kMask>(a, tile, slab, sm);
 }
 
 // Few channels (C <= 8) for a 256-thread workgroup: one lane per cell, the
@@ -778,7 +841,7 @@ __device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& 
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const GridGeom& g = a.g;
   const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
-  const CellVec cell = cell_vec(g, ix, iy);
+  const CellVec cell = cell_at(a.cells, g, ix, iy);
   const uint32_t total =
       stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
   const int C = (int)a.C;
@@ -810,7 +873,7 @@ __device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& 
       for (int k = 0; k < kmax; ++k) {
         const double c2 = chord2(cell, wxyz[k]);
         if (c2 <= a.c2R) {
-          const double w = pair_weight64(c2, a.wscale);
+          const double w = pair_weight64(c2, a.kern.wscale);
           wsum += w;
 #pragma unroll
           for (int c = 0; c < 8; ++c) acc[c] += w * (double)wspec[k * 8 + c];
@@ -840,7 +903,7 @@ __device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& 
   if (a.wmap) a.wmap[cellidx] = (float)wsum;
 #pragma unroll
   for (int c = 0; c < 8; ++c)
-    if (c < C) a.cube[c * G + cellidx] = (wsum > 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
+    if (c < C) a.cube[c * G + cellidx] = (wsum != 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
 }
 
 // Persistent batch kernel (FP32 spectra).  The item space concatenates the
@@ -904,37 +967,52 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
 
 // ---------------------------------------------------------------------------
 // Few channels (C <= 8) and pair counting: one lane per cell of the 8 x 8
-// tile, candidates staged 64 at a time, FP32 weights summed in FP64.
+// tile, candidates staged 64 at a time, weights summed in FP64.
 // A map of few tiles gives too few waves to hide the latency of the
 // candidate loads, so the candidates of a tile can be split over nsplit
 // workgroups (blockIdx.y takes every nsplit-th staged block of 64); each
-// then writes its FP64 partial sums to part[split][kCM + 1][tile * 64 +
-// lane] (the channel sums, then W) and k_cells_finish adds them in split
-// order.  nsplit = 1 writes the map directly.
+// then writes its FP64 partial sums to part[split][kSlots][tile * 64 + lane]
+// (the channel sums, then W, or with flags the channel weight sums) and
+// k_cells_finish adds them in split order.  nsplit = 1 writes the map
+// directly.  kMask: a non-finite value is a flag, left out of its channel's
+// sums (numerator and weights); the per-channel weights go to wcube.
 // ---------------------------------------------------------------------------
-template <int kCM, bool kCount>
+template <int kCM, bool kMask>
+struct CellSlots {
+  static constexpr int kW = kMask ? kCM : 1;  // weight sums per cell
+  static constexpr int kN = kCM + kW;         // partial sums per cell
+};
+
+template <int kCM, bool kCount, bool kMask = false>
 __global__ void __launch_bounds__(64) k_gather_cells(
-    const double4* __restrict__ xyz, const uint32_t* __restrict__ perm,
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ nranges, int maxr,
-    const float* __restrict__ spectra, int C, GridGeom g, int ntx, double c2R,
-    double wscale, float* __restrict__ cube, float* __restrict__ wmap,
+    const double4* __restrict__ cells, const double4* __restrict__ xyz,
+    const uint32_t* __restrict__ perm, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ nranges, int maxr, const float* __restrict__ spectra, int C,
+    GridGeom g, int ntx, double c2R, KernelParams kp, float* __restrict__ cube,
+    float* __restrict__ wmap, float* __restrict__ wcube,
     unsigned long long* __restrict__ pair_count, int nsplit, double* __restrict__ part) {
+  constexpr int kM = kCM > 0 ? kCM : 1;
+  constexpr int kW = CellSlots<kM, kMask>::kW;
   __shared__ uint2 s_rng[kMaxRangesLimit];
   __shared__ uint32_t s_pre[kMaxRangesLimit + 1];
   __shared__ double4 s_xyz[kKB];
-  __shared__ float s_spec[kKB][kCM > 0 ? kCM : 1];
+  __shared__ float s_spec[kKB][kM];
 
   const int tile = blockIdx.x;
   const int lane = threadIdx.x;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
-  const CellVec cell = cell_vec(g, ix, iy);
+  const CellVec cell = cell_at(cells, g, ix, iy);
+  const CellFrame frame = (kp.type == kElliptic) ? cell_frame(cell)
+                                                 : CellFrame{0.0, 0.0, 0.0, 0.0, 0.0};
   const uint32_t total = stage_ranges(ranges + (int64_t)tile * maxr, nranges[tile], s_rng, s_pre);
 
-  double accv[kCM > 0 ? kCM : 1];
+  double accv[kM];
+  double wsum[kW];
 #pragma unroll
-  for (int c = 0; c < (kCM > 0 ? kCM : 1); ++c) accv[c] = 0.0;
-  double wsum = 0.0;
+  for (int c = 0; c < kM; ++c) accv[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < kW; ++c) wsum[c] = 0.0;
   unsigned long long npair = 0;
   uint32_t cur = 0;
   const uint32_t step = (uint32_t)nsplit * kKB;
@@ -946,7 +1024,7 @@ __global__ void __launch_bounds__(64) k_gather_cells(
       if (!kCount) {
         const int64_t row = perm[pos];
 #pragma unroll
-        for (int c = 0; c < kCM; ++c) s_spec[lane][c] = (c < C) ? spectra[row * C + c] : 0.f;
+        for (int c = 0; c < kM; ++c) s_spec[lane][c] = (c < C) ? spectra[row * C + c] : 0.f;
       }
     } else {
       const double nan = __builtin_nan("");
@@ -955,15 +1033,28 @@ __global__ void __launch_bounds__(64) k_gather_cells(
     __syncthreads();
     const int kmax = (int)min<uint32_t>(kKB, total - q0);
     for (int k = 0; k < kmax; ++k) {
-      const double c2 = chord2(cell, s_xyz[k]);
+      const double4 v = s_xyz[k];
+      const double c2 = chord2(cell, v);
       if (c2 <= c2R) {
         if (kCount) {
           ++npair;
         } else {
-          const double w = pair_weight64(c2, wscale);
-          wsum += w;
+          const double w = (kp.type == kGauss) ? pair_weight64(c2, kp.wscale)
+                                               : pair_weight_gen(kp, c2, v, cell, frame);
+          if constexpr (kMask) {
 #pragma unroll
-          for (int c = 0; c < kCM; ++c) accv[c] += w * (double)s_spec[k][c];
+            for (int c = 0; c < kM; ++c) {
+              const float x = s_spec[k][c];
+              if ((__float_as_uint(x) & 0x7F800000u) != 0x7F800000u) {
+                accv[c] += w * (double)x;
+                wsum[c] += w;
+              }
+            }
+          } else {
+            wsum[0] += w;
+#pragma unroll
+            for (int c = 0; c < kM; ++c) accv[c] += w * (double)s_spec[k][c];
+          }
         }
       }
     }
@@ -976,49 +1067,62 @@ __global__ void __launch_bounds__(64) k_gather_cells(
   }
   if (nsplit > 1) {
     const int64_t slots = (int64_t)gridDim.x * kTileCells;
-    double* out = part + (int64_t)blockIdx.y * (kCM + 1) * slots + (int64_t)tile * kTileCells + lane;
+    double* out = part + (int64_t)blockIdx.y * (kM + kW) * slots + (int64_t)tile * kTileCells + lane;
 #pragma unroll
-    for (int c = 0; c < kCM; ++c) out[c * slots] = accv[c];
-    out[kCM * slots] = wsum;
+    for (int c = 0; c < kM; ++c) out[c * slots] = accv[c];
+#pragma unroll
+    for (int c = 0; c < kW; ++c) out[(kM + c) * slots] = wsum[c];
     return;
   }
   if (ix >= g.nx || iy >= g.ny) return;
   const int64_t G = (int64_t)g.nx * g.ny;
   const int64_t cellidx = (int64_t)iy * g.nx + ix;
-  if (wmap) wmap[cellidx] = (float)wsum;
+  if (!kMask && wmap) wmap[cellidx] = (float)wsum[0];
 #pragma unroll
-  for (int c = 0; c < kCM; ++c)
-    if (c < C) cube[c * G + cellidx] = (wsum > 0.0) ? (float)(accv[c] / wsum) : __builtin_nanf("");
+  for (int c = 0; c < kM; ++c) {
+    if (c >= C) continue;
+    const double wc = wsum[kMask ? c : 0];
+    cube[c * G + cellidx] = (wc != 0.0) ? (float)(accv[c] / wc) : __builtin_nanf("");
+    if (kMask && wcube) wcube[c * G + cellidx] = (float)wc;
+  }
 }
 
 // Sum of the nsplit partial sums of every cell, in split order; V and W.
-template <int kCM>
+template <int kCM, bool kMask = false>
 __global__ void __launch_bounds__(256) k_cells_finish(const double* __restrict__ part, int nsplit,
                                                        int ntiles, int C, GridGeom g, int ntx,
                                                        float* __restrict__ cube,
-                                                       float* __restrict__ wmap) {
+                                                       float* __restrict__ wmap,
+                                                       float* __restrict__ wcube) {
+  constexpr int kW = CellSlots<kCM, kMask>::kW;
   const int64_t slots = (int64_t)ntiles * kTileCells;
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= slots) return;
   const int tile = (int)(slot / kTileCells), lane = (int)(slot % kTileCells);
   const int ix = (tile % ntx) * kTileX + (lane & 7), iy = (tile / ntx) * kTileY + (lane >> 3);
   if (ix >= g.nx || iy >= g.ny) return;
-  double accv[kCM];
+  double accv[kCM], wsum[kW];
 #pragma unroll
   for (int c = 0; c < kCM; ++c) accv[c] = 0.0;
-  double wsum = 0.0;
+#pragma unroll
+  for (int c = 0; c < kW; ++c) wsum[c] = 0.0;
   for (int sp = 0; sp < nsplit; ++sp) {
-    const double* in = part + (int64_t)sp * (kCM + 1) * slots + slot;
+    const double* in = part + (int64_t)sp * (kCM + kW) * slots + slot;
 #pragma unroll
     for (int c = 0; c < kCM; ++c) accv[c] += in[c * slots];
-    wsum += in[kCM * slots];
+#pragma unroll
+    for (int c = 0; c < kW; ++c) wsum[c] += in[(kCM + c) * slots];
   }
   const int64_t G = (int64_t)g.nx * g.ny;
   const int64_t cellidx = (int64_t)iy * g.nx + ix;
-  if (wmap) wmap[cellidx] = (float)wsum;
+  if (!kMask && wmap) wmap[cellidx] = (float)wsum[0];
 #pragma unroll
-  for (int c = 0; c < kCM; ++c)
-    if (c < C) cube[c * G + cellidx] = (wsum > 0.0) ? (float)(accv[c] / wsum) : __builtin_nanf("");
+  for (int c = 0; c < kCM; ++c) {
+    if (c >= C) continue;
+    const double wc = wsum[kMask ? c : 0];
+    cube[c * G + cellidx] = (wc != 0.0) ? (float)(accv[c] / wc) : __builtin_nanf("");
+    if (kMask && wcube) wcube[c * G + cellidx] = (float)wc;
+  }
 }
 
 // A map of fewer than kCellsSplitBelow tiles is spread over about
@@ -1029,43 +1133,65 @@ constexpr int kCellsSplitBelow = 1024;
 constexpr int kCellsTargetGroups = 2048;
 constexpr int kCellsMaxSplit = 64;
 
+// Split of a map's candidate lists and the bytes of FP64 partial sums it
+// needs (0 when the gather writes the map directly).
+static int cells_split(unsigned ntiles) {
+  return (ntiles >= (unsigned)kCellsSplitBelow)
+             ? 1
+             : (int)std::min<int64_t>(kCellsMaxSplit, (kCellsTargetGroups + ntiles - 1) / ntiles);
+}
+static size_t cells_part_bytes(int nsplit, int cm, bool mask, unsigned ntiles) {
+  if (nsplit <= 1) return 0;
+  const int slots = cm + (mask ? cm : 1);
+  return sizeof(double) * (size_t)nsplit * slots * ntiles * kTileCells;
+}
+
+// part: caller-provided scratch of cells_part_bytes(...) bytes, or NULL to
+// allocate it stream-ordered here (one workgroup per tile if that fails).
 static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, float* cube,
-                               float* wmap, hipStream_t stream) {
-  const double c2R = support_chord2(p), wscale = weight_scale(p);
+                               float* wmap, float* wcube, bool mask, double* part,
+                               hipStream_t stream) {
+  const double c2R = support_chord2(p);
   const unsigned ntiles = (unsigned)(p->ntx * p->nty);
   const int cm = (C == 1) ? 1 : (C == 2) ? 2 : (C <= 4) ? 4 : 8;
-  int nsplit = (ntiles >= (unsigned)kCellsSplitBelow)
-                   ? 1
-                   : (int)std::min<int64_t>(kCellsMaxSplit,
-                                            (kCellsTargetGroups + ntiles - 1) / ntiles);
-  double* part = nullptr;
-  if (nsplit > 1) {
-    const size_t bytes = sizeof(double) * (size_t)nsplit * (cm + 1) * ntiles * kTileCells;
+  int nsplit = cells_split(ntiles);
+  bool owned = false;
+  if (nsplit > 1 && !part) {
+    const size_t bytes = cells_part_bytes(nsplit, cm, mask, ntiles);
     if (hipMallocAsync((void**)&part, bytes, stream) != hipSuccess) {
       (void)hipGetLastError();  // no room for the partial sums: one workgroup per tile
       part = nullptr;
       nsplit = 1;
+    } else {
+      owned = true;
     }
   }
   const dim3 grid(ntiles, (unsigned)nsplit);
   const unsigned fin_blocks = (unsigned)((ntiles * (int64_t)kTileCells + 255) / 256);
-#define HCG_CELLS(CM)                                                                          \
+#define HCG_CELLS(CM, MASK)                                                                    \
   do {                                                                                         \
-    k_gather_cells<CM, false><<<grid, 64, 0, stream>>>(p->xyz, p->perm, p->ranges, p->nranges, \
-                                                       p->maxr, spec, C, p->grid, p->ntx, c2R, \
-                                                       wscale, cube, wmap, nullptr, nsplit,    \
-                                                       part);                                  \
+    k_gather_cells<CM, false, MASK><<<grid, 64, 0, stream>>>(                                  \
+        p->cells, p->xyz, p->perm, p->ranges, p->nranges, p->maxr, spec, C, p->grid, p->ntx,   \
+        c2R, p->kern, cube, wmap, wcube, nullptr, nsplit, part);                               \
     if (nsplit > 1)                                                                            \
-      k_cells_finish<CM><<<fin_blocks, 256, 0, stream>>>(part, nsplit, (int)ntiles, C,         \
-                                                         p->grid, p->ntx, cube, wmap);         \
+      k_cells_finish<CM, MASK><<<fin_blocks, 256, 0, stream>>>(part, nsplit, (int)ntiles, C,   \
+                                                               p->grid, p->ntx, cube, wmap,    \
+                                                               wcube);                         \
   } while (0)
-  if (cm == 1) HCG_CELLS(1);
-  else if (cm == 2) HCG_CELLS(2);
-  else if (cm == 4) HCG_CELLS(4);
-  else HCG_CELLS(8);
+  if (mask) {
+    if (cm == 1) HCG_CELLS(1, true);
+    else if (cm == 2) HCG_CELLS(2, true);
+    else if (cm == 4) HCG_CELLS(4, true);
+    else HCG_CELLS(8, true);
+  } else {
+    if (cm == 1) HCG_CELLS(1, false);
+    else if (cm == 2) HCG_CELLS(2, false);
+    else if (cm == 4) HCG_CELLS(4, false);
+    else HCG_CELLS(8, false);
+  }
 #undef HCG_CELLS
   const hipError_t le = hipGetLastError();
-  if (part) (void)hipFreeAsync(part, stream);
+  if (owned) (void)hipFreeAsync(part, stream);
   if (le != hipSuccess)
     return fail(HCG_E_DEVICE, "launch of k_gather_cells failed: %s", hipGetErrorString(le));
   return HCG_OK;
@@ -1075,12 +1201,16 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
 // over) a gather takes 256-channel slabs.
 constexpr int64_t kFewGroups = 1024;
 
-template <int kForm, bool kPacked = false>
+template <int kForm, bool kPacked = false, bool kMask = false>
 static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void* spec_lo,
                               const float* scale, int64_t C, float* cube, float* wmap,
-                              hipStream_t stream) {
+                              hipStream_t stream, float* wcube = nullptr) {
   static_assert(!(kPacked && kForm == kF32), "plan-ordered spectra are a low-precision input");
   GatherArgs a;
+  memset(&a, 0, sizeof(a));
+  a.cells = p->cells;
+  a.kern = p->kern;
+  a.wcube = wcube;
   a.xyz = p->xyz;
   a.sentinel = (uint32_t)p->n;
   a.perm = p->perm;
@@ -1096,7 +1226,6 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   a.ntiles = p->ntx * p->nty;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
   a.c2R = support_chord2(p);
-  a.wscale = weight_scale(p);
   a.cube = cube;
   a.wmap = wmap;
   const size_t esz = (kForm == kF32) ? 4 : is_fp8(kForm) ? 1 : 2;
@@ -1110,7 +1239,11 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   // registers allow it, else 256; a map of few tiles takes 256-channel slabs
   // too, for twice the workgroups (512-channel slabs would leave CUs idle)
   const int64_t groups512 = (int64_t)a.ntiles * ((C + 511) / 512);
-  const int qw = (C > 256 && vec && kForm != kBF16Split && groups512 >= kFewGroups) ? 2 : 1;
+  // the other kernel shapes and the flagged form keep to 256-channel slabs
+  // (registers for the cell frame, or for the weight-sum accumulators)
+  const bool gen = p->kern.type != kGauss;
+  const int qw = (C > 256 && vec && kForm != kBF16Split && !gen && !kMask &&
+                  groups512 >= kFewGroups) ? 2 : 1;
   const int64_t slab_ch = 256 * qw;
   const int64_t slabs = (C + slab_ch - 1) / slab_ch;
   const int64_t blocks = slabs * a.tiles_per_xcd * 8;
@@ -1124,6 +1257,26 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
     if (wide) k_gather_mfma<kForm, QW, VEC, kPacked, true><<<grid, block, 0, stream>>>(a); \
     else k_gather_mfma<kForm, QW, VEC, kPacked, false><<<grid, block, 0, stream>>>(a);    \
   } while (0)
+  if (gen || kMask) {
+    // one instance per form and row access: the general distance series,
+    // 256-channel slabs
+    if constexpr (kPacked) {
+      k_gather_mfma<kForm, 1, true, true, true, true, false><<<grid, block, 0, stream>>>(a);
+    } else if constexpr (kMask) {
+      if (vec) {
+        if (gen) k_gather_mfma<kForm, 1, true, false, true, true, true><<<grid, block, 0, stream>>>(a);
+        else k_gather_mfma<kForm, 1, true, false, true, false, true><<<grid, block, 0, stream>>>(a);
+      } else {
+        if (gen) k_gather_mfma<kForm, 1, false, false, true, true, true><<<grid, block, 0, stream>>>(a);
+        else k_gather_mfma<kForm, 1, false, false, true, false, true><<<grid, block, 0, stream>>>(a);
+      }
+    } else {
+      if (vec) k_gather_mfma<kForm, 1, true, false, true, true, false><<<grid, block, 0, stream>>>(a);
+      else k_gather_mfma<kForm, 1, false, false, true, true, false><<<grid, block, 0, stream>>>(a);
+    }
+    HCG_LAUNCH_CHECK("k_gather_mfma");
+    return HCG_OK;
+  }
   if constexpr (kForm != kBF16Split) {
     if (qw == 2) {
       HCG_MFMA(2, true);
@@ -1146,6 +1299,8 @@ GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, floa
                          float* wmap) {
   GatherArgs a;
   memset(&a, 0, sizeof(a));  // padding bytes too: the batch compares tables bytewise
+  a.cells = p->cells;
+  a.kern = p->kern;
   a.xyz = p->xyz;
   a.sentinel = (uint32_t)p->n;
   a.perm = p->perm;
@@ -1162,7 +1317,6 @@ GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, floa
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
   a.vec = (C % 4 == 0 && (uintptr_t)spec % 16 == 0) ? 1 : 0;
   a.c2R = support_chord2(p);
-  a.wscale = weight_scale(p);
   a.cube = cube;
   a.wmap = wmap;
   return a;
@@ -1209,7 +1363,9 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
   hipStream_t stream = (hipStream_t)hip_stream;
   switch (dtype) {
     case HCG_F32:
-      if (nchan <= 8) return launch_cells(p, (const float*)spectra, (int)nchan, cube, weights, stream);
+      if (nchan <= 8)
+        return launch_cells(p, (const float*)spectra, (int)nchan, cube, weights, nullptr, false,
+                            nullptr, stream);
       return launch_mfma<kF32>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
     case HCG_BF16:
       return launch_mfma<kBF16>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
@@ -1226,6 +1382,21 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
                                     chan_scale, nchan, cube, weights, stream);
   }
   return fail(HCG_E_UNSUPPORTED, "hcg_grid: dtype %d", (int)dtype);
+}
+
+extern "C" hcg_status hcg_grid_masked(hcg_plan_t plan, const float* spectra, int64_t nchan,
+                                      float* cube, float* chan_weights, void* hip_stream) {
+  if (!plan) return fail(HCG_E_ARG, "hcg_grid_masked: plan is NULL");
+  if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid_masked: not a live plan");
+  if (!spectra || !cube) return fail(HCG_E_ARG, "hcg_grid_masked: spectra and cube must not be NULL");
+  if (nchan < 1) return fail(HCG_E_ARG, "hcg_grid_masked: nchan must be >= 1");
+  const hcg_plan_s* p = plan;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  if (nchan <= 8)
+    return launch_cells(p, spectra, (int)nchan, cube, nullptr, chan_weights, true, nullptr,
+                        stream);
+  return launch_mfma<kF32, false, true>(p, spectra, nullptr, nullptr, nchan, cube, nullptr,
+                                        stream, chan_weights);
 }
 
 extern "C" hcg_status hcg_packed_bytes(hcg_plan_t plan, int64_t nchan, hcg_dtype dtype,
@@ -1297,10 +1468,9 @@ extern "C" hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats,
     ~Free() { (void)hipFree(q); }
   } fr{dcount};
   HCG_HIP(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), stream));
-  k_gather_cells<0, true><<<ntiles, 64, 0, stream>>>(p->xyz, p->perm, p->ranges, p->nranges,
-                                                     p->maxr, nullptr, 0, p->grid, p->ntx,
-                                                     support_chord2(p), 0.0,
-                                                     nullptr, nullptr, dcount, 1, nullptr);
+  k_gather_cells<0, true><<<ntiles, 64, 0, stream>>>(
+      p->cells, p->xyz, p->perm, p->ranges, p->nranges, p->maxr, nullptr, 0, p->grid, p->ntx,
+      support_chord2(p), p->kern, nullptr, nullptr, nullptr, dcount, 1, nullptr);
   HCG_LAUNCH_CHECK("k_gather_cells<count>");
   unsigned long long pairs = 0;
   HCG_HIP(hipMemcpyAsync(&pairs, dcount, sizeof(pairs), hipMemcpyDeviceToHost, stream));

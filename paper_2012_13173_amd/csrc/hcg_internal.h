@@ -71,10 +71,30 @@ __host__ __device__ inline int64_t hpx_pix2ring(int64_t ns, int64_t p) {
   return lo;
 }
 
-// Device-side grid geometry (degrees, as given by the caller).
+// Device-side grid geometry (degrees, as given by the caller).  A plan whose
+// cells were given by their centres keeps nx, ny here and zeros elsewhere;
+// every gather reads the cell centres from the plan's unit-vector array.
 struct GridGeom {
   int32_t nx, ny;
   double lon0, lat0, dlon, dlat;
+};
+
+// Kernel of the plan (Section 3.6 (iii)): the weight of a pair at distance d
+// (d <= R), all factors precomputed on the host.
+//   kGauss      exp2(d^2 wscale)
+//   kElliptic   exp2(d^2 (a^2 kmaj + b^2 kmin) / (a^2 + b^2)), (a, b) the
+//               sample's offset along the major / minor axis in the tangent
+//               plane of the cell: a = xn cpa + xe spa, b = xe cpa - xn spa
+//               (xe, xn its east / north components); weight 1 at d = 0
+//   kSinc       sin(d sinc_k) / (d sinc_k) exp2(d^2 taper_k)
+enum KernelType : int32_t { kGauss = 0, kElliptic = 1, kSinc = 2 };
+struct KernelParams {
+  int32_t type;
+  int32_t pad_;
+  double wscale;          // Gaussian: -log2(e) / (2 sigma^2)
+  double kmaj, kmin;      // elliptic: -log2(e) / (2 sigma^2) of each axis
+  double cpa, spa;        // elliptic: cos / sin of the major axis' position angle
+  double sinc_k, taper_k; // sinc: pi / b and -log2(e) / a^2
 };
 
 __host__ __device__ inline double cell_lon_deg(const GridGeom& g, int ix) {
@@ -162,7 +182,9 @@ struct hcg_plan_s {
   int32_t key_bits, passes;
   int32_t ring_first, ring_last;
   hcg::GridGeom grid;
+  int32_t centres;     // 1: cells given by their centres (no linear geometry)
   double fwhm_deg, support_deg, sigma_rad, support_rad;
+  hcg::KernelParams kern;
   int32_t ntx, nty, maxr;
   void* arena;
   size_t arena_bytes;
@@ -175,6 +197,7 @@ struct hcg_plan_s {
   uint32_t* nranges;   // [ntiles]
   uint32_t* ncand;     // [ntiles] candidates per tile
   uint32_t* flags;     // [4] device status words
+  double4* cells;      // [ny * nx] unit vectors of the cell centres (NaN: no cell)
 };
 
 namespace hcg {
@@ -193,6 +216,9 @@ size_t radix_sort_temp_bytes(int64_t n);
 
 // Arguments of the gather for one plan and one spectra buffer (gather.hip).
 struct GatherArgs {
+  const double4* cells; // [ny][nx] unit vectors of the cell centres
+  KernelParams kern;
+  float* wcube;         // masked form: per-channel weights [C][ny][nx] or NULL
   const double4* xyz;
   const uint32_t* perm;
   const uint2* ranges;
@@ -207,17 +233,18 @@ struct GatherArgs {
   int ntx, ntiles, tiles_per_xcd;
   int vec;  // rows can be read 4 elements at a time
   double c2R;     // squared chord of the support radius, 4 sin^2(R / 2)
-  double wscale;  // -log2(e) / (2 sigma^2): the weight is exp2(d^2 wscale)
   float* cube;
   float* wmap;
 };
 
 // The host fills GatherArgs tables that kernels index; the layout is fixed
 // (both compilation passes see these checks).
-static_assert(sizeof(GatherArgs) == 160, "GatherArgs layout changed");
-static_assert(offsetof(GatherArgs, sentinel) == 36 && offsetof(GatherArgs, C) == 64 &&
-                  offsetof(GatherArgs, g) == 72 &&
-                  offsetof(GatherArgs, c2R) == 128 && offsetof(GatherArgs, wmap) == 152,
+static_assert(sizeof(KernelParams) == 64, "KernelParams layout changed");
+static_assert(sizeof(GatherArgs) == 232, "GatherArgs layout changed");
+static_assert(offsetof(GatherArgs, kern) == 8 && offsetof(GatherArgs, wcube) == 72 &&
+                  offsetof(GatherArgs, sentinel) == 116 && offsetof(GatherArgs, C) == 144 &&
+                  offsetof(GatherArgs, g) == 152 &&
+                  offsetof(GatherArgs, c2R) == 208 && offsetof(GatherArgs, wmap) == 224,
               "GatherArgs layout changed");
 
 // Batched gather (gather.hip): one work item = (field, tile, channel slab).

@@ -350,39 +350,60 @@ __global__ void k_ring_csr(const uint32_t* __restrict__ keys, int64_t n, int ns,
 }
 
 // ---------------------------------------------------------------------------
+// Cell centres as unit vectors (FP64), one per cell of the target grid: from
+// the linear lon/lat geometry, or from caller arrays of centres (a projected
+// map).  A centre that is not finite or has |lat| > 90 gives a NaN vector: a
+// cell that no sample reaches.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cell_vecs_linear(GridGeom g, double4* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)g.nx * g.ny) return;
+  const CellVec c = cell_vec(g, (int)(i % g.nx), (int)(i / g.nx));
+  out[i] = make_double4(c.x, c.y, c.z, 0.0);
+}
+
+__global__ void __launch_bounds__(256) k_cell_vecs_arrays(const double* __restrict__ lon,
+                                                          const double* __restrict__ lat,
+                                                          int64_t ncell,
+                                                          double4* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const double lo = lon[i], la = lat[i];
+  if (!isfinite(lo) || !isfinite(la) || fabs(la) > 90.0) {
+    const double nan = __builtin_nan("");
+    out[i] = make_double4(nan, nan, nan, 0.0);
+    return;
+  }
+  double sb, cb, sl, cl;
+  sincos(la * kDeg2Rad, &sb, &cb);
+  sincos(lo * kDeg2Rad, &sl, &cl);
+  out[i] = make_double4(cb * cl, cb * sl, sb, 0.0);
+}
+
+// ---------------------------------------------------------------------------
 // a5: candidate ranges per tile of output cells: ring_ranges (sphere.h) for
 // every ring that can hold a sample within R of the tile.
 // ---------------------------------------------------------------------------
 // One wave per tile; lane r handles ring i_lo + r (+64, ...).  Ranges are
-// written in ring order, two slots at most per ring.
-__global__ void __launch_bounds__(256) k_tile_ranges(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ csr, int ns, int ring_first,
-    int ring_last, uint32_t pix_base, GridGeom g, int ntx, int nty, double support_rad, int maxr,
-    uint2* __restrict__ ranges, uint32_t* __restrict__ nranges, uint32_t* __restrict__ ncand,
-    uint32_t* __restrict__ flags) {
+// written in ring order, two slots at most per ring.  The tile is the
+// lon/lat box [lon_a, lon_b] x [lat_a, lat_b] (radians) of its cells, or a
+// point (a degenerate box) with the support widened by the radius of a cap
+// holding its cells; Rs is the (widened, conservative) support.
+__device__ void tile_ranges_wave(const uint32_t* __restrict__ keys,
+                                 const uint32_t* __restrict__ csr, int ns, int ring_first,
+                                 int ring_last, uint32_t pix_base, double lon_a, double lon_b,
+                                 double lat_a, double lat_b, double Rs, int maxr,
+                                 uint2* __restrict__ out, uint32_t* nranges_out,
+                                 uint32_t* ncand_out, uint32_t* __restrict__ flags) {
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile >= ntx * nty) return;
-  const int tx = tile % ntx, ty = tile / ntx;
-  const int ix0 = tx * kTileX, ix1 = min(g.nx, ix0 + kTileX) - 1;
-  const int iy0 = ty * kTileY, iy1 = min(g.ny, iy0 + kTileY) - 1;
-  double lon_a = cell_lon_deg(g, ix0) * kDeg2Rad, lon_b = cell_lon_deg(g, ix1) * kDeg2Rad;
-  double lat_a = cell_lat_deg(g, iy0) * kDeg2Rad, lat_b = cell_lat_deg(g, iy1) * kDeg2Rad;
-  if (lon_a > lon_b) { const double t = lon_a; lon_a = lon_b; lon_b = t; }
-  if (lat_a > lat_b) { const double t = lat_a; lat_a = lat_b; lat_b = t; }
   const double half_pi = 0.5 * kPi;
-  lat_a = fmax(-half_pi, fmin(half_pi, lat_a));
-  lat_b = fmax(-half_pi, fmin(half_pi, lat_b));
-  // conservative support: absorbs rounding of every bound below
-  const double Rs = support_rad * (1.0 + 1e-9) + 1e-12;
-  const double sR = sin(0.5 * Rs);
+  const double sR = sin(0.5 * fmin(Rs, kPi));
   const double hR = sR * sR;
   const double cos_g = cos(fmax(fabs(lat_a), fabs(lat_b)));
   const double z_top = sin(fmin(half_pi, lat_b + Rs));
   const double z_bot = sin(fmax(-half_pi, lat_a - Rs));
   const int i_lo = max(ring_first, (int)floor(hpx_ring_of_z(ns, z_top)) - 2);
   const int i_hi = min(ring_last, (int)ceil(hpx_ring_of_z(ns, z_bot)) + 2);
-  uint2* out = ranges + (int64_t)tile * maxr;
   uint32_t count = 0, total = 0;
   bool overflow = false;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -410,9 +431,99 @@ __global__ void __launch_bounds__(256) k_tile_ranges(
   }
   if (__ballot(overflow) && lane == 0) atomicOr(&flags[0], 1u);
   if (lane == 0) {
-    nranges[tile] = min(count, (uint32_t)maxr);
-    ncand[tile] = total;
+    *nranges_out = min(count, (uint32_t)maxr);
+    *ncand_out = total;
   }
+}
+
+// Linear lon/lat grid: the box of the tile's cell centres.
+__global__ void __launch_bounds__(256) k_tile_ranges(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ csr, int ns, int ring_first,
+    int ring_last, uint32_t pix_base, GridGeom g, int ntx, int nty, double support_rad, int maxr,
+    uint2* __restrict__ ranges, uint32_t* __restrict__ nranges, uint32_t* __restrict__ ncand,
+    uint32_t* __restrict__ flags) {
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntx * nty) return;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int ix0 = tx * kTileX, ix1 = min(g.nx, ix0 + kTileX) - 1;
+  const int iy0 = ty * kTileY, iy1 = min(g.ny, iy0 + kTileY) - 1;
+  double lon_a = cell_lon_deg(g, ix0) * kDeg2Rad, lon_b = cell_lon_deg(g, ix1) * kDeg2Rad;
+  double lat_a = cell_lat_deg(g, iy0) * kDeg2Rad, lat_b = cell_lat_deg(g, iy1) * kDeg2Rad;
+  if (lon_a > lon_b) { const double t = lon_a; lon_a = lon_b; lon_b = t; }
+  if (lat_a > lat_b) { const double t = lat_a; lat_a = lat_b; lat_b = t; }
+  const double half_pi = 0.5 * kPi;
+  lat_a = fmax(-half_pi, fmin(half_pi, lat_a));
+  lat_b = fmax(-half_pi, fmin(half_pi, lat_b));
+  // conservative support: absorbs rounding of every bound below
+  const double Rs = support_rad * (1.0 + 1e-9) + 1e-12;
+  tile_ranges_wave(keys, csr, ns, ring_first, ring_last, pix_base, lon_a, lon_b, lat_a, lat_b, Rs,
+                   maxr, ranges + (int64_t)tile * maxr, &nranges[tile], &ncand[tile], flags);
+}
+
+// Cells given by their centres: per tile (one wave), the cap around the
+// normalised mean of its cells' unit vectors that holds them all; caps[t] =
+// (centre lon, centre lat, radius) in radians, radius < 0 for a tile
+// without cells.  The largest radius goes to *rmax (as the bits of a
+// non-negative double, which order like the values).
+__global__ void __launch_bounds__(256) k_tile_caps(const double4* __restrict__ cells, int nx,
+                                                   int ny, int ntx, int nty,
+                                                   double4* __restrict__ caps,
+                                                   unsigned long long* __restrict__ rmax) {
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntx * nty) return;
+  const int x = (tile % ntx) * kTileX + (lane & 7), y = (tile / ntx) * kTileY + (lane >> 3);
+  double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (x < nx && y < ny) v = cells[(int64_t)y * nx + x];
+  const bool valid = (x < nx && y < ny) && v.x == v.x;
+  double sx = valid ? v.x : 0.0, sy = valid ? v.y : 0.0, sz = valid ? v.z : 0.0;
+  for (int o = 1; o < 64; o <<= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+    sz += __shfl_xor(sz, o);
+  }
+  const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
+  // a tile of cells spread over a hemisphere or more has no useful centre:
+  // take any and the whole sphere as its cap
+  const bool degenerate = !(nrm > 1e-6);
+  const double cx = degenerate ? 0.0 : sx / nrm, cy = degenerate ? 0.0 : sy / nrm,
+               cz = degenerate ? 1.0 : sz / nrm;
+  double c2 = 0.0;
+  if (valid) {
+    const double dx = v.x - cx, dy = v.y - cy, dz = v.z - cz;
+    c2 = dx * dx + dy * dy + dz * dz;
+  }
+  for (int o = 1; o < 64; o <<= 1) c2 = fmax(c2, __shfl_xor(c2, o));
+  const bool any = __ballot(valid) != 0ull;
+  if (lane == 0) {
+    double r = 2.0 * asin(fmin(0.5 * sqrt(c2), 1.0));
+    if (degenerate) r = kPi;
+    if (!any) r = -1.0;
+    caps[tile] = make_double4(atan2(cy, cx), asin(fmax(-1.0, fmin(1.0, cz))), r, 0.0);
+    if (r > 0.0) atomicMax(rmax, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_tile_ranges_cap(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ csr, int ns, int ring_first,
+    int ring_last, uint32_t pix_base, const double4* __restrict__ caps, int ntiles,
+    double support_rad, int maxr, uint2* __restrict__ ranges, uint32_t* __restrict__ nranges,
+    uint32_t* __restrict__ ncand, uint32_t* __restrict__ flags) {
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const double4 cap = caps[tile];
+  if (cap.z < 0.0) {
+    if ((threadIdx.x & 63) == 0) {
+      nranges[tile] = 0u;
+      ncand[tile] = 0u;
+    }
+    return;
+  }
+  // every cell is within cap.z of the centre, so every sample within R of a
+  // cell is within R + cap.z of it (triangle inequality); slack for rounding
+  const double Rs = (support_rad + cap.z) * (1.0 + 1e-9) + 1e-12;
+  tile_ranges_wave(keys, csr, ns, ring_first, ring_last, pix_base, cap.x, cap.x, cap.y, cap.y, Rs,
+                   maxr, ranges + (int64_t)tile * maxr, &nranges[tile], &ncand[tile], flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,70 +593,165 @@ extern "C" hcg_status hcg_sort_keys(const uint32_t* keys_in, int64_t n, int32_t 
   return HCG_OK;
 }
 
-extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_deg,
-                               int64_t n, const hcg_grid_desc* grid, double fwhm_deg,
-                               double support_deg, const hcg_opts* opts, void* hip_stream) {
-  if (!out) return fail(HCG_E_ARG, "hcg_plan: out is NULL");
-  *out = nullptr;
-  if (!lon_deg || !lat_deg || !grid) return fail(HCG_E_ARG, "hcg_plan: NULL pointer");
-  if (n < 1 || n >= (int64_t(1) << 31)) return fail(HCG_E_ARG, "hcg_plan: n must be in 1..2^31-1");
-  if (grid->nx < 1 || grid->ny < 1) return fail(HCG_E_ARG, "hcg_plan: grid nx, ny must be >= 1");
-  if ((int64_t)grid->nx * grid->ny > INT32_MAX) return fail(HCG_E_ARG, "hcg_plan: grid too large");
+namespace {
+
+// What a plan's target and kernel come down to once the arguments are
+// checked: the linear grid or the caller's centre arrays, the kernel's
+// precomputed factors and the sigma that picks the automatic nside.
+struct PlanTarget {
+  const hcg_grid_desc* grid;  // linear lon/lat grid, or NULL
+  const double* clon;         // or: device centre arrays [ny][nx]
+  const double* clat;
+  int32_t nx, ny;
+};
+
+hcg_status check_grid(const hcg_grid_desc* grid, const char* who) {
+  if (grid->nx < 1 || grid->ny < 1) return fail(HCG_E_ARG, "%s: grid nx, ny must be >= 1", who);
+  if ((int64_t)grid->nx * grid->ny > INT32_MAX) return fail(HCG_E_ARG, "%s: grid too large", who);
   if (!std::isfinite(grid->lon0_deg) || !std::isfinite(grid->lat0_deg) ||
       !std::isfinite(grid->dlon_deg) || !std::isfinite(grid->dlat_deg) || grid->dlon_deg == 0.0 ||
       grid->dlat_deg == 0.0)
-    return fail(HCG_E_ARG, "hcg_plan: grid origin and steps must be finite, steps non-zero");
-  {
-    const double la = grid->lat0_deg - 0.5 * (grid->ny - 1) * grid->dlat_deg;
-    const double lb = grid->lat0_deg + 0.5 * (grid->ny - 1) * grid->dlat_deg;
-    if (std::fabs(la) > 90.0 || std::fabs(lb) > 90.0)
-      return fail(HCG_E_ARG, "hcg_plan: grid cell latitudes leave [-90, 90]");
+    return fail(HCG_E_ARG, "%s: grid origin and steps must be finite, steps non-zero", who);
+  const double la = grid->lat0_deg - 0.5 * (grid->ny - 1) * grid->dlat_deg;
+  const double lb = grid->lat0_deg + 0.5 * (grid->ny - 1) * grid->dlat_deg;
+  if (std::fabs(la) > 90.0 || std::fabs(lb) > 90.0)
+    return fail(HCG_E_ARG, "%s: grid cell latitudes leave [-90, 90]", who);
+  return HCG_OK;
+}
+
+double sigma_of_fwhm(double fwhm_deg) {
+  return fwhm_deg * kDeg2Rad / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+}
+
+// Kernel factors (Section 3.6 (iii)) and the width that sets the automatic
+// nside: sigma of the Gaussian, of the minor axis of the elliptical one, and
+// half the smaller of the sinc's zero and taper widths.
+hcg_status kernel_params(const hcg_kernel* k, const char* who, KernelParams* kp,
+                         double* sigma_nside, double* fwhm_nominal) {
+  const double l2e = 1.4426950408889634;
+  memset(kp, 0, sizeof(*kp));
+  kp->type = k->type;
+  auto bad = [&](double v) { return !(v > 0.0) || !std::isfinite(v); };
+  switch (k->type) {
+    case HCG_KERNEL_GAUSS: {
+      if (bad(k->fwhm_deg)) return fail(HCG_E_ARG, "%s: fwhm must be > 0", who);
+      const double sg = sigma_of_fwhm(k->fwhm_deg);
+      kp->wscale = -l2e / (2.0 * sg * sg);
+      *sigma_nside = sg;
+      *fwhm_nominal = k->fwhm_deg;
+      return HCG_OK;
+    }
+    case HCG_KERNEL_ELLIPTIC_GAUSS: {
+      if (bad(k->fwhm_deg) || bad(k->fwhm_minor_deg) || !std::isfinite(k->pa_deg))
+        return fail(HCG_E_ARG, "%s: elliptical kernel needs fwhm, fwhm_minor > 0 and a finite pa", who);
+      const double sa = sigma_of_fwhm(k->fwhm_deg), sb = sigma_of_fwhm(k->fwhm_minor_deg);
+      kp->kmaj = -l2e / (2.0 * sa * sa);
+      kp->kmin = -l2e / (2.0 * sb * sb);
+      kp->cpa = std::cos(k->pa_deg * kDeg2Rad);
+      kp->spa = std::sin(k->pa_deg * kDeg2Rad);
+      kp->wscale = kp->kmaj;
+      *sigma_nside = std::min(sa, sb);
+      *fwhm_nominal = k->fwhm_deg;
+      return HCG_OK;
+    }
+    case HCG_KERNEL_TAPERED_SINC: {
+      if (bad(k->sinc_deg) || bad(k->taper_deg))
+        return fail(HCG_E_ARG, "%s: tapered sinc needs sinc_deg, taper_deg > 0", who);
+      const double b = k->sinc_deg * kDeg2Rad, a = k->taper_deg * kDeg2Rad;
+      kp->sinc_k = kPi / b;
+      kp->taper_k = -l2e / (a * a);
+      *sigma_nside = 0.5 * std::min(a, b);
+      *fwhm_nominal = k->sinc_deg;
+      return HCG_OK;
+    }
+    default:
+      return fail(HCG_E_UNSUPPORTED, "%s: unknown kernel type %d", who, (int)k->type);
   }
-  if (!(fwhm_deg > 0.0) || !std::isfinite(fwhm_deg)) return fail(HCG_E_ARG, "hcg_plan: fwhm must be > 0");
+}
+
+hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_deg, int64_t n,
+                      const PlanTarget& tg, const hcg_kernel* kernel, double support_deg,
+                      const hcg_opts* opts, void* hip_stream, const char* who) {
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(HCG_E_ARG, "%s: n must be in 1..2^31-1", who);
   if (!(support_deg >= 0.0) || !(support_deg < 90.0))
-    return fail(HCG_E_ARG, "hcg_plan: support must be in [0, 90) degrees");
+    return fail(HCG_E_ARG, "%s: support must be in [0, 90) degrees", who);
+  KernelParams kp;
+  double sigma = 0.0, fwhm_nominal = 0.0;
+  hcg_status st = kernel_params(kernel, who, &kp, &sigma, &fwhm_nominal);
+  if (st != HCG_OK) return st;
   hcg_opts o = {};
   if (opts) o = *opts;
   if ((o.tile_x && o.tile_x != kTileX) || (o.tile_y && o.tile_y != kTileY))
-    return fail(HCG_E_UNSUPPORTED, "hcg_plan: only 8 x 8 cell tiles are built");
+    return fail(HCG_E_UNSUPPORTED, "%s: only 8 x 8 cell tiles are built", who);
   if (o.coarsen || o.chan_tile || o.flags)
-    return fail(HCG_E_UNSUPPORTED, "hcg_plan: coarsen, chan_tile and flags must be 0");
-  const double sigma = fwhm_deg * kDeg2Rad / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    return fail(HCG_E_UNSUPPORTED, "%s: coarsen, chan_tile and flags must be 0", who);
   int nside = o.nside ? o.nside : auto_nside(sigma);
   if (!is_pow2(nside) || nside > 16384)
-    return fail(HCG_E_ARG, "hcg_plan: nside %d is not a power of two in 1..16384", nside);
-  hcg_status st = check_device_arch();
+    return fail(HCG_E_ARG, "%s: nside %d is not a power of two in 1..16384", who, nside);
+  st = check_device_arch();
   if (st != HCG_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
-
-  // candidate-range slots per tile: rings in the tile's latitude span + 2R,
-  // two ranges per ring; rings are at least 2/(3 Ns) apart in latitude
-  const double R = support_deg * kDeg2Rad;
-  const double tile_span = (kTileY - 1) * std::fabs(grid->dlat_deg) * kDeg2Rad;
-  const double rings_d = (tile_span + 2.0 * R) / (2.0 / (3.0 * nside)) + 6.0;
-  if (rings_d > kMaxRangesLimit / 2)
-    return fail(HCG_E_UNSUPPORTED,
-                "hcg_plan: support too wide for nside %d (%.0f rings per tile; at most %d)", nside,
-                rings_d, kMaxRangesLimit / 2);
-  const int maxr = 2 * (int)std::ceil(rings_d);
-  const int ntx = (grid->nx + kTileX - 1) / kTileX, nty = (grid->ny + kTileY - 1) / kTileY;
+  const int nx = tg.grid ? tg.grid->nx : tg.nx, ny = tg.grid ? tg.grid->ny : tg.ny;
+  const int ntx = (nx + kTileX - 1) / kTileX, nty = (ny + kTileY - 1) / kTileY;
   const int64_t ntiles = (int64_t)ntx * nty;
+  const int64_t ncell = (int64_t)nx * ny;
+  const double R = support_deg * kDeg2Rad;
 
-  // pass 1: pixels and their range (one small read-back)
-  DevBuf pixbuf, statbuf;
+  // pass 1: pixels and their range (one small read-back); for centre arrays
+  // also the cell vectors and the tile caps, whose largest radius sizes the
+  // candidate-range slots
+  DevBuf pixbuf, statbuf, cellbuf, capbuf;
   HCG_HIP(hipMalloc(&pixbuf.p, sizeof(uint32_t) * n));
-  HCG_HIP(hipMalloc(&statbuf.p, 16));
+  HCG_HIP(hipMalloc(&statbuf.p, 32));
+  if (hipMalloc(&cellbuf.p, sizeof(double4) * ncell) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HCG_E_NOMEM, "%s: cannot allocate the cell vectors", who);
+  }
+  double4* cells = (double4*)cellbuf.p;
+  const unsigned cell_blocks = (unsigned)((ncell + 255) / 256);
+  if (tg.grid) {
+    const GridGeom gg{tg.grid->nx, tg.grid->ny, tg.grid->lon0_deg, tg.grid->lat0_deg,
+                      tg.grid->dlon_deg, tg.grid->dlat_deg};
+    k_cell_vecs_linear<<<cell_blocks, 256, 0, stream>>>(gg, cells);
+    HCG_LAUNCH_CHECK("k_cell_vecs_linear");
+  } else {
+    k_cell_vecs_arrays<<<cell_blocks, 256, 0, stream>>>(tg.clon, tg.clat, ncell, cells);
+    HCG_LAUNCH_CHECK("k_cell_vecs_arrays");
+    HCG_HIP(hipMalloc(&capbuf.p, sizeof(double4) * ntiles));
+    HCG_HIP(hipMemsetAsync((char*)statbuf.p + 16, 0, 8, stream));
+    k_tile_caps<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
+        cells, nx, ny, ntx, nty, (double4*)capbuf.p,
+        (unsigned long long*)((char*)statbuf.p + 16));
+    HCG_LAUNCH_CHECK("k_tile_caps");
+  }
   st = launch_ang2pix(lon_deg, lat_deg, n, nside, (uint32_t*)pixbuf.p, (uint32_t*)statbuf.p, stream);
   if (st != HCG_OK) return st;
-  uint32_t hs[4];
+  uint32_t hs[8];
   HCG_HIP(hipMemcpyAsync(hs, statbuf.p, sizeof(hs), hipMemcpyDeviceToHost, stream));
   HCG_HIP(hipStreamSynchronize(stream));
-  if (hs[2]) return fail(HCG_E_ARG, "hcg_plan: %u sample coordinates are non-finite or |lat| > 90", hs[2]);
+  if (hs[2]) return fail(HCG_E_ARG, "%s: %u sample coordinates are non-finite or |lat| > 90", who, hs[2]);
   const uint32_t pix_base = hs[0], pix_max = hs[1];
   const int ring_first = (int)hpx_pix2ring(nside, pix_base);
   const int ring_last = (int)hpx_pix2ring(nside, pix_max);
   const int nrings = ring_last - ring_first + 1;
   const int key_bits = bit_length(pix_max - pix_base);
+
+  // candidate-range slots per tile: rings in the tile's latitude span + 2R,
+  // two ranges per ring; rings are at least 2/(3 Ns) apart in latitude
+  double tile_span = 0.0;
+  if (tg.grid) {
+    tile_span = (kTileY - 1) * std::fabs(tg.grid->dlat_deg) * kDeg2Rad;
+  } else {
+    double rmax = 0.0;
+    memcpy(&rmax, &hs[4], sizeof(double));
+    tile_span = 2.0 * std::min(rmax, kPi);
+  }
+  const double rings_d = (tile_span + 2.0 * R) / (2.0 / (3.0 * nside)) + 6.0;
+  if (rings_d > kMaxRangesLimit / 2)
+    return fail(HCG_E_UNSUPPORTED,
+                "%s: support or tile too wide for nside %d (%.0f rings per tile; at most %d)", who,
+                nside, rings_d, kMaxRangesLimit / 2);
+  const int maxr = 2 * (int)std::ceil(rings_d);
 
   // plan arena
   size_t off = 0;
@@ -561,16 +767,17 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   const size_t o_nr = take(sizeof(uint32_t) * ntiles);
   const size_t o_nc = take(sizeof(uint32_t) * ntiles);
   const size_t o_flags = take(16);
+  const size_t o_cells = take(sizeof(double4) * ncell);
   const size_t arena_bytes = off;
   DevBuf arena, temp;
   if (hipMalloc(&arena.p, arena_bytes) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(HCG_E_NOMEM, "hcg_plan: cannot allocate %zu bytes for the plan", arena_bytes);
+    return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes for the plan", who, arena_bytes);
   }
   const size_t temp_bytes = radix_sort_temp_bytes(n) + align256(sizeof(uint32_t) * n);
   if (hipMalloc(&temp.p, temp_bytes) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(HCG_E_NOMEM, "hcg_plan: cannot allocate %zu bytes of scratch", temp_bytes);
+    return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes of scratch", who, temp_bytes);
   }
   char* A = (char*)arena.p;
   auto* p = new hcg_plan_s{};
@@ -584,12 +791,17 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   p->passes = (key_bits + 7) / 8;
   p->ring_first = ring_first;
   p->ring_last = ring_last;
-  p->grid = GridGeom{grid->nx, grid->ny, grid->lon0_deg, grid->lat0_deg, grid->dlon_deg,
-                     grid->dlat_deg};
-  p->fwhm_deg = fwhm_deg;
+  if (tg.grid)
+    p->grid = GridGeom{tg.grid->nx, tg.grid->ny, tg.grid->lon0_deg, tg.grid->lat0_deg,
+                       tg.grid->dlon_deg, tg.grid->dlat_deg};
+  else
+    p->grid = GridGeom{nx, ny, 0.0, 0.0, 0.0, 0.0};
+  p->centres = tg.grid ? 0 : 1;
+  p->fwhm_deg = fwhm_nominal;
   p->support_deg = support_deg;
   p->sigma_rad = sigma;
   p->support_rad = R;
+  p->kern = kp;
   p->ntx = ntx;
   p->nty = nty;
   p->maxr = maxr;
@@ -602,11 +814,14 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
   p->nranges = (uint32_t*)(A + o_nr);
   p->ncand = (uint32_t*)(A + o_nc);
   p->flags = (uint32_t*)(A + o_flags);
+  p->cells = (double4*)(A + o_cells);
   struct PlanGuard {
     hcg_plan_s* p;
     ~PlanGuard() { delete p; }
   } guard{p};
 
+  HCG_HIP(hipMemcpyAsync(p->cells, cells, sizeof(double4) * ncell, hipMemcpyDeviceToDevice,
+                         stream));
   // keys relative to the smallest pixel, then the stable sort
   uint32_t* rel = (uint32_t*)((char*)temp.p + radix_sort_temp_bytes(n));
   k_rel_keys<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>((const uint32_t*)pixbuf.p,
@@ -623,17 +838,70 @@ extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const dou
       p->keys, n, nside, ring_first, nrings, pix_base, p->csr);
   HCG_LAUNCH_CHECK("k_ring_csr");
   HCG_HIP(hipMemsetAsync(p->flags, 0, 16, stream));
-  k_tile_ranges<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
-      p->keys, p->csr, nside, ring_first, ring_last, pix_base, p->grid, ntx, nty, R, maxr,
-      p->ranges, p->nranges, p->ncand, p->flags);
-  HCG_LAUNCH_CHECK("k_tile_ranges");
+  if (tg.grid) {
+    k_tile_ranges<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
+        p->keys, p->csr, nside, ring_first, ring_last, pix_base, p->grid, ntx, nty, R, maxr,
+        p->ranges, p->nranges, p->ncand, p->flags);
+    HCG_LAUNCH_CHECK("k_tile_ranges");
+  } else {
+    k_tile_ranges_cap<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
+        p->keys, p->csr, nside, ring_first, ring_last, pix_base, (const double4*)capbuf.p,
+        (int)ntiles, R, maxr, p->ranges, p->nranges, p->ncand, p->flags);
+    HCG_LAUNCH_CHECK("k_tile_ranges_cap");
+  }
   uint32_t fl[4];
   HCG_HIP(hipMemcpyAsync(fl, p->flags, sizeof(fl), hipMemcpyDeviceToHost, stream));
   HCG_HIP(hipStreamSynchronize(stream));
-  if (fl[0]) return fail(HCG_E_DEVICE, "hcg_plan: candidate-range slots overflowed (internal bound)");
+  if (fl[0]) return fail(HCG_E_DEVICE, "%s: candidate-range slots overflowed (internal bound)", who);
   p->arena = arena.release();
   guard.p = nullptr;
   plan_register(p);
   *out = p;
   return HCG_OK;
+}
+
+}  // namespace
+
+extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_deg,
+                               int64_t n, const hcg_grid_desc* grid, double fwhm_deg,
+                               double support_deg, const hcg_opts* opts, void* hip_stream) {
+  if (!out) return fail(HCG_E_ARG, "hcg_plan: out is NULL");
+  *out = nullptr;
+  if (!lon_deg || !lat_deg || !grid) return fail(HCG_E_ARG, "hcg_plan: NULL pointer");
+  hcg_status st = check_grid(grid, "hcg_plan");
+  if (st != HCG_OK) return st;
+  hcg_kernel k{};
+  k.type = HCG_KERNEL_GAUSS;
+  k.fwhm_deg = fwhm_deg;
+  const PlanTarget tg{grid, nullptr, nullptr, grid->nx, grid->ny};
+  return plan_build(out, lon_deg, lat_deg, n, tg, &k, support_deg, opts, hip_stream, "hcg_plan");
+}
+
+extern "C" hcg_status hcg_plan_ex(hcg_plan_t* out, const double* lon_deg, const double* lat_deg,
+                                  int64_t n, const hcg_grid_desc* grid,
+                                  const hcg_cell_centres* centres, const hcg_kernel* kernel,
+                                  double support_deg, const hcg_opts* opts, void* hip_stream) {
+  if (!out) return fail(HCG_E_ARG, "hcg_plan_ex: out is NULL");
+  *out = nullptr;
+  if (!lon_deg || !lat_deg || !kernel) return fail(HCG_E_ARG, "hcg_plan_ex: NULL pointer");
+  if ((grid == nullptr) == (centres == nullptr))
+    return fail(HCG_E_ARG, "hcg_plan_ex: give exactly one of grid and centres");
+  PlanTarget tg{grid, nullptr, nullptr, 0, 0};
+  if (grid) {
+    const hcg_status st = check_grid(grid, "hcg_plan_ex");
+    if (st != HCG_OK) return st;
+    tg.nx = grid->nx;
+    tg.ny = grid->ny;
+  } else {
+    if (!centres->lon_deg || !centres->lat_deg)
+      return fail(HCG_E_ARG, "hcg_plan_ex: NULL centre array");
+    if (centres->nx < 1 || centres->ny < 1 || (int64_t)centres->nx * centres->ny > INT32_MAX)
+      return fail(HCG_E_ARG, "hcg_plan_ex: centres nx, ny out of range");
+    tg.clon = centres->lon_deg;
+    tg.clat = centres->lat_deg;
+    tg.nx = centres->nx;
+    tg.ny = centres->ny;
+  }
+  return plan_build(out, lon_deg, lat_deg, n, tg, kernel, support_deg, opts, hip_stream,
+                    "hcg_plan_ex");
 }

@@ -104,6 +104,10 @@ extern "C" hcg_status hcg_grid_rowthreads(hcg_plan_t plan, const float* spectra,
   if (block < 64 || block > 512 || block % 64 != 0)
     return fail(HCG_E_ARG, "hcg_grid_rowthreads: block must be a multiple of 64 in 64 .. 512");
   const hcg_plan_s* p = plan;
+  // the scheme walks latitude rows of a linear grid with the Gaussian kernel
+  if (p->centres || p->kern.type != kGauss)
+    return fail(HCG_E_UNSUPPORTED,
+                "hcg_grid_rowthreads: needs a plan on a linear grid with the Gaussian kernel");
   const GridGeom g = p->grid;
   const int64_t threads = (int64_t)((g.nx + gamma - 1) / gamma) * g.ny;
   const int64_t blocks = (threads + block - 1) / block;

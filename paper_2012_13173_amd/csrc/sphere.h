@@ -29,6 +29,23 @@ __device__ __forceinline__ CellVec cell_vec(const GridGeom& g, int ix, int iy) {
   return c;
 }
 
+// Unit vector of cell (ix, iy) from the plan's array of cell vectors; NaN
+// outside the grid (never within R).  A cell whose centre the caller gave as
+// non-finite holds NaN in the array.
+__device__ __forceinline__ CellVec cell_at(const double4* __restrict__ cells, const GridGeom& g,
+                                           int ix, int iy) {
+  CellVec c;
+  if (ix >= g.nx || iy >= g.ny) {
+    c.x = c.y = c.z = __builtin_nan("");
+    return c;
+  }
+  const double4 v = cells[(int64_t)iy * g.nx + ix];
+  c.x = v.x;
+  c.y = v.y;
+  c.z = v.z;
+  return c;
+}
+
 // Squared chord |u - v|^2 = 4 sin^2(d/2) between a cell and a sample.
 __device__ __forceinline__ double chord2(const CellVec& c, const double4& v) {
   const double dx = v.x - c.x, dy = v.y - c.y, dz = v.z - c.z;
@@ -62,6 +79,47 @@ __device__ __forceinline__ double dist2_from_chord2(double c2) {
 __device__ __forceinline__ double pair_weight64(double c2, double wscale) {
   const double e = dist2_from_chord2(c2) * wscale;
   return (e > -126.0) ? (double)__builtin_amdgcn_exp2f((float)e) : exp2(e);
+}
+
+// East and north unit vectors of the tangent plane at a cell (east = (-y, x,
+// 0) / rho, north = (-z x, -z y, rho^2) / rho, rho = |(x, y)|); at a pole, the
+// frame of longitude 0.
+struct CellFrame {
+  double ex, ey;      // east (ex, ey, 0)
+  double nx, ny, nz;  // north
+};
+
+__device__ __forceinline__ CellFrame cell_frame(const CellVec& c) {
+  const double rho = sqrt(c.x * c.x + c.y * c.y);
+  if (!(rho > 0.0)) return CellFrame{0.0, 1.0, c.z > 0.0 ? -1.0 : 1.0, 0.0, 0.0};
+  const double r = 1.0 / rho;
+  return CellFrame{-c.y * r, c.x * r, -c.z * c.x * r, -c.z * c.y * r, rho};
+}
+
+// FP64 weight of a pair inside the support for the kernel shapes other than
+// the circular Gaussian (and that one too), evaluated with the FP64 library
+// exponential and sine: the elliptical Gaussian takes the sample's offset
+// (v - c) in the cell's tangent plane, whose direction is the bearing of the
+// great circle from the cell to the sample; the tapered sinc takes d alone.
+__device__ __forceinline__ double pair_weight_gen(const KernelParams& k, double c2,
+                                                  const double4& v, const CellVec& c,
+                                                  const CellFrame& f) {
+  const double d2 = dist2_from_chord2<true>(c2);
+  if (k.type == kElliptic) {
+    const double dx = v.x - c.x, dy = v.y - c.y, dz = v.z - c.z;
+    const double xe = dx * f.ex + dy * f.ey;
+    const double xn = dx * f.nx + dy * f.ny + dz * f.nz;
+    const double a = xn * k.cpa + xe * k.spa, b = xe * k.cpa - xn * k.spa;
+    const double s = a * a + b * b;
+    if (!(s > 0.0)) return 1.0;  // the sample sits on the cell
+    return exp2(d2 * (a * a * k.kmaj + b * b * k.kmin) / s);
+  }
+  if (k.type == kSinc) {
+    const double x = sqrt(d2) * k.sinc_k;
+    const double sinc = (x > 0.0) ? sin(x) / x : 1.0;
+    return sinc * exp2(d2 * k.taper_k);
+  }
+  return exp2(d2 * k.wscale);
 }
 
 // Candidate search in one ring for cells spanning [lon_a, lon_b] x
@@ -143,8 +201,6 @@ inline double support_chord2(const hcg_plan_s* p) {
   const double s = std::sin(0.5 * p->support_rad);
   return 4.0 * s * s;
 }
-inline double weight_scale(const hcg_plan_s* p) {
-  return -1.4426950408889634 / (2.0 * p->sigma_rad * p->sigma_rad);
-}
+inline double weight_scale(const hcg_plan_s* p) { return p->kern.wscale; }
 
 }  // namespace hcg

@@ -265,9 +265,10 @@ def drift_scan_large(device="cpu", seed=SEED0 + 4) -> Workload:
 
 def small_cube(n=20_000, nchan=67, nx=45, ny=37, cell_arcmin=0.75, fwhm_arcmin=3.0,
                seed=SEED0 + 100, device="cpu", lon_c=180.0, lat_c=30.0, nside=None,
-               pad_arcmin=4.0, name="small_cube") -> Workload:
+               pad_arcmin=4.0, name="small_cube", support_sigma=3.0) -> Workload:
     """Uniform positions covering the grid plus ``pad_arcmin`` on every side,
-    N(0,1) spectra with a few lines: a multi-tile, ragged-edge parity case."""
+    N(0,1) spectra with a few lines: a multi-tile, ragged-edge parity case.
+    The support radius is ``support_sigma`` kernel sigmas."""
     w = nx * cell_arcmin * ARCMIN + 2 * pad_arcmin * ARCMIN
     h = ny * cell_arcmin * ARCMIN + 2 * pad_arcmin * ARCMIN
     lon, lat = uniform_positions(n, lon_c, lat_c, w, h, seed, device)
@@ -276,7 +277,7 @@ def small_cube(n=20_000, nchan=67, nx=45, ny=37, cell_arcmin=0.75, fwhm_arcmin=3
     src = add_lines(spec, lon, lat, 4, lon_c, lat_c, w, h, 2.9 * ARCMIN, seed + 2)
     grid = GridDesc(nx, ny, lon_c, lat_c, cell_arcmin * ARCMIN, cell_arcmin * ARCMIN)
     fwhm = fwhm_arcmin * ARCMIN
-    return Workload(name, lon, lat, spec, grid, fwhm, 3.0 * fwhm * FWHM_TO_SIGMA,
+    return Workload(name, lon, lat, spec, grid, fwhm, support_sigma * fwhm * FWHM_TO_SIGMA,
                     nside if nside else nside_for(fwhm), src)
 
 

@@ -48,9 +48,28 @@ def channel_errors(V_gpu, V_ref):
     return np.where(den > 0, num / np.maximum(den, 1e-300), num)
 
 
+def cell_errors(V_gpu, V_ref):
+    """Per-cell error of every channel in units of that channel's RMS over the
+    cells where the reference is finite: |V - V_ref| / rms_c(V_ref)."""
+    V_gpu = np.asarray(V_gpu, dtype=np.float64).reshape(V_gpu.shape[0], -1)
+    V_ref = np.asarray(V_ref, dtype=np.float64).reshape(V_ref.shape[0], -1)
+    ok = ~np.isnan(V_ref)
+    r = np.where(ok, V_ref, 0.0)
+    rms = np.sqrt((r * r).sum(1) / np.maximum(ok.sum(1), 1))
+    d = np.where(ok, np.abs(V_gpu - V_ref), 0.0)
+    return d / np.maximum(rms, 1e-300)[:, None]
+
+
 def assert_cube_close(V_gpu, V_ref, tol, what=""):
+    """Per-channel relative L2 <= tol, and every single cell within
+    10 tol of its channel's RMS (so one bad cell cannot hide in a norm)."""
     e = channel_errors(V_gpu, V_ref)
     assert float(e.max()) <= tol, f"{what}: max per-channel rel L2 {e.max():.3e} > {tol:.1e}"
+    ce = cell_errors(V_gpu, V_ref)
+    worst = np.unravel_index(int(np.argmax(ce)), ce.shape)
+    assert float(ce.max()) <= 10.0 * tol, (
+        f"{what}: cell {worst[1]} channel {worst[0]} off by {ce.max():.3e} x the channel RMS "
+        f"(bound {10 * tol:.1e})")
     return e
 
 

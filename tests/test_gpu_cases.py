@@ -1,0 +1,184 @@
+"""GPU parity cases beyond the basic grid tests, through the C ABI:
+
+* few channels (C <= 8) on maps of >= 1024 tiles, where the one-lane-per-cell
+  gather writes the map directly (no split of the candidate lists);
+* supports of 5 sigma (Section 3.6 (iii) allows 3 to 5 sigma) in the FP32 form
+  and every low-precision form, input order and plan-ordered;
+* a non-finite spectrum value stays near its sample: padding of a tile's
+  candidate list never multiplies it, so it reaches only tiles that list the
+  sample as a candidate -- cells within R + the 8 x 8 tile's diagonal + a
+  HEALPix pixel (exactly the cells within R for C <= 8);
+* the binding refuses spectra whose row count is not the plan's sample count,
+  before any launch.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2012_13173_amd as hcg
+import synth
+from tests.gridcheck import (assert_cube_close, assert_weights_close, gather_cells, run_oracle,
+                             sample_cells, sampled_oracle)
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL_F32 = 1e-5
+
+FORMS = {
+    "f16_scaled": (hcg.HCG_F16_SCALED, 1e-3),
+    "bf16_split": (hcg.HCG_BF16_SPLIT, 5e-5),
+    "fp8e4m3_split": (hcg.HCG_FP8E4M3_SPLIT, 1e-2),
+    "bf16": (hcg.HCG_BF16, 1e-2),
+    "fp8e4m3_scaled": (hcg.HCG_FP8E4M3_SCALED, 1e-1),
+}
+
+
+def _plan(w):
+    return hcg.hcg_plan(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg,
+                        nside=w.nside)
+
+
+def _grid(w, plan, form=hcg.HCG_F32, packed=False, spectra=None):
+    spec = (w.spectra if spectra is None else spectra).to(DEV).contiguous()
+    cube = torch.empty((w.nchan, w.grid.ny, w.grid.nx), dtype=torch.float32, device=DEV)
+    W = torch.empty((w.grid.ny, w.grid.nx), dtype=torch.float32, device=DEV)
+    if form == hcg.HCG_F32:
+        hcg.hcg_grid(plan, spec, cube, W)
+    elif packed:
+        enc, scale = hcg.hcg_quantize_packed(plan, spec, form)
+        hcg.hcg_grid_packed(plan, enc, cube, W, dtype=form, chan_scale=scale)
+    else:
+        enc, scale = hcg.hcg_quantize(spec, form)
+        hcg.hcg_grid(plan, enc, cube, W, dtype=form, chan_scale=scale)
+    torch.cuda.synchronize()
+    return cube, W
+
+
+@pytest.mark.parametrize("nchan", [1, 5])
+def test_few_channels_on_many_tiles(nchan):
+    # 264 x 256 cells = 33 x 32 = 1056 tiles: the direct-write gather
+    w = synth.small_cube(n=250_000, nchan=nchan, nx=264, ny=256, cell_arcmin=0.5, seed=410 + nchan)
+    plan = _plan(w)
+    info = plan.info()
+    assert info["ntiles_x"] * info["ntiles_y"] >= 1024
+    print(f"C={nchan}: {info['ntiles_x'] * info['ntiles_y']} tiles", flush=True)
+    cube, W = _grid(w, plan)
+    plan.destroy()
+    groups = sample_cells(w.grid, seed=7 + nchan, patches=4, patch=12)
+    cells = np.concatenate(groups)
+    ref = [sampled_oracle(w, c) for c in groups]
+    Vr = np.concatenate([v for v, _ in ref])
+    Wr = np.concatenate([x for _, x in ref])
+    V, Wg = gather_cells(cube, W, cells)
+    assert_cube_close(V.T, Vr.T, TOL_F32, f"C={nchan}, 1056 tiles")
+    assert_weights_close(Wg, Wr)
+
+
+@pytest.mark.parametrize("nchan", [1, 67, 300])
+def test_five_sigma_support_every_form(nchan):
+    w = synth.small_cube(n=15_000, nchan=nchan, nx=29, ny=19, support_sigma=5.0, seed=430)
+    Vr, Wr, _ = run_oracle(w)
+    plan = _plan(w)
+    cube, W = _grid(w, plan)
+    e = assert_cube_close(cube.cpu().numpy(), Vr, TOL_F32, f"f32 5 sigma C={nchan}")
+    print(f"{'f32':>15s} C={nchan:4d} 5 sigma: max {e.max():.2e}", flush=True)
+    assert_weights_close(W.cpu().numpy(), Wr)
+    for name, (form, tol) in FORMS.items():
+        for packed in (False, True):
+            cube, W = _grid(w, plan, form, packed)
+            what = f"{'packed ' if packed else ''}{name} 5 sigma C={nchan}"
+            e = assert_cube_close(cube.cpu().numpy(), Vr, tol, what)
+            print(f"{what}: max {e.max():.2e}", flush=True)
+            assert_weights_close(W.cpu().numpy(), Wr)
+    plan.destroy()
+
+
+def _dist_to(w, lon0, lat0):
+    """[ny, nx] great-circle distance (degrees) of every cell centre to a point."""
+    g = w.grid
+    ix = np.arange(g.nx)
+    iy = np.arange(g.ny)
+    cl = np.radians(g.lon0 + (ix - (g.nx - 1) / 2) * g.dlon)[None, :]
+    cb = np.radians(g.lat0 + (iy - (g.ny - 1) / 2) * g.dlat)[:, None]
+    l0, b0 = math.radians(lon0), math.radians(lat0)
+    h = np.sin((cb - b0) / 2) ** 2 + np.cos(cb) * math.cos(b0) * np.sin((cl - l0) / 2) ** 2
+    return np.degrees(2 * np.arcsin(np.sqrt(np.minimum(h, 1.0))))
+
+
+@pytest.mark.parametrize("nchan", [1, 40])
+def test_non_finite_value_stays_near_its_sample(nchan):
+    # sample 0 sits near a corner; its value is NaN in every channel
+    w = synth.small_cube(n=20_000, nchan=nchan, nx=48, ny=40, seed=450)
+    g = w.grid
+    w.lon[0] = g.lon0 - 0.4 * g.nx * g.dlon
+    w.lat[0] = g.lat0 - 0.4 * g.ny * g.dlat
+    spec = w.spectra.clone()
+    spec[0] = float("nan")
+    plan = _plan(w)
+    dist = _dist_to(w, float(w.lon[0]), float(w.lat[0]))
+    R = w.support_deg
+    # matrix-core forms: a tile that lists sample 0 as a candidate has its
+    # cells within R + its diagonal (7 sqrt(2) cells) + a pixel of sample 0
+    pix = math.degrees(math.sqrt(4 * math.pi / (12.0 * w.nside ** 2)))
+    reach = R + 7 * math.sqrt(2) * g.dlat + 2 * pix
+    empty = np.isnan(_grid(w, plan)[0].cpu().numpy()[0])  # cells without samples
+    forms = [("f32", hcg.HCG_F32)] + ([] if nchan <= 8 else
+                                      [(k, v[0]) for k, v in FORMS.items()])
+    for name, form in forms:
+        cube, _ = _grid(w, plan, form, spectra=spec)
+        V = cube.cpu().numpy()
+        bad = np.isnan(V).any(0) & ~empty
+        if nchan <= 8:
+            # one lane per cell in FP64: exactly the cells within R
+            assert np.array_equal(bad, dist <= R), name
+        else:
+            assert bad.any(), name
+            assert dist[bad].max() <= reach, f"{name}: NaN at {dist[bad].max():.4f} deg > {reach:.4f}"
+        print(f"{name}: {int(bad.sum())} cells reached, farthest {dist[bad].max():.4f} deg "
+              f"(R {R:.4f})", flush=True)
+    plan.destroy()
+
+
+def test_spectra_row_count_is_checked_before_any_launch():
+    w = synth.small_cube(n=3000, nchan=12, nx=10, ny=10, seed=470)
+    plan = _plan(w)
+    cube = torch.empty((12, 10, 10), dtype=torch.float32, device=DEV)
+    short = w.spectra[:-1].to(DEV).contiguous()
+    with pytest.raises(ValueError):
+        hcg.hcg_grid(plan, short, cube)
+    enc, scale = hcg.hcg_quantize(short, hcg.HCG_BF16_SPLIT)
+    with pytest.raises(ValueError):
+        hcg.hcg_grid(plan, enc, cube, dtype=hcg.HCG_BF16_SPLIT)
+    plan.destroy()
+    b = hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)])
+    with pytest.raises(ValueError):
+        hcg.hcg_grid_batch(b, [short], [cube])
+    with pytest.raises(ValueError):
+        hcg.hcg_grid_batch(b, [w.spectra.to(DEV)], [cube],
+                           [torch.empty((9, 10), dtype=torch.float32, device=DEV)])
+    b.destroy()
+
+
+def test_batch_with_a_wide_support_field():
+    # one field of support 0.64 deg (FWHM 30', 3 sigma) makes the persistent
+    # kernel take the long distance series; the narrow fields must not change
+    ws = [synth.small_cube(n=6000, nchan=24, nx=20, ny=16, seed=481, name="narrow24"),
+          synth.small_cube(n=9000, nchan=1, nx=18, ny=18, seed=482, fwhm_arcmin=30.0,
+                           cell_arcmin=10.0, pad_arcmin=40.0, name="wide1"),
+          synth.small_cube(n=9000, nchan=96, nx=16, ny=14, seed=483, fwhm_arcmin=30.0,
+                           cell_arcmin=10.0, pad_arcmin=40.0, lat_c=-50.0, name="wide96"),
+          synth.small_cube(n=5000, nchan=3, nx=9, ny=11, seed=484, name="narrow3")]
+    assert ws[1].support_deg >= 0.57 and ws[2].support_deg >= 0.57
+    b = hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+                            for w in ws])
+    cubes = [torch.empty((w.nchan, w.grid.ny, w.grid.nx), device=DEV) for w in ws]
+    wts = [torch.empty((w.grid.ny, w.grid.nx), device=DEV) for w in ws]
+    hcg.hcg_grid_batch(b, [w.spectra.to(DEV) for w in ws], cubes, wts)
+    torch.cuda.synchronize()
+    for w, c, x in zip(ws, cubes, wts):
+        Vr, Wr, _ = run_oracle(w)
+        assert_cube_close(c.cpu().numpy(), Vr, TOL_F32, w.name)
+        assert_weights_close(x.cpu().numpy(), Wr)
+    b.destroy()
