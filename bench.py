@@ -11,7 +11,12 @@ The metric is sample*channel updates per second, N * C / t_step.
 
 Printed: one JSON line with the metric, a roofline record of the dominant
 kernel (the gather, timed with HIP events on its stream) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  The same line carries
+the low-precision forms on this workload and, under "c2", the many-channel
+drift scan (1,976,000 samples x 8,192 channels -> 400 x 400) on which the
+metric's "FP32 gather vs BF16-MFMA at <= 1e-3" is stated: the FP32 gather,
+FP16 x channel scale and BF16 hi+lo, each with its per-channel error against
+the oracle, whether it meets its budget, and its encoding time.
 """
 from __future__ import annotations
 
@@ -33,6 +38,19 @@ import synth  # noqa: E402
 
 MFMA_FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+# error budgets per form (largest per-channel relative L2 against the oracle):
+# FP32 1e-5; the 16-bit matrix-core forms 1e-3; the FP8 forms 1e-2
+BUDGET = {"f32": 1e-5, "bf16": 1e-3, "f16_scaled": 1e-3, "bf16_split": 1e-3,
+          "fp8e4m3_scaled": 1e-2, "fp8e4m3_split": 1e-2}
+# bytes per spectrum element stored by each form (planes x element size)
+ELEM_BYTES = {"f32": 4, "bf16": 2, "f16_scaled": 2, "bf16_split": 4, "fp8e4m3_scaled": 1,
+              "fp8e4m3_split": 2}
+# The paper's context (Section 1): about 21 CPU-hours per TB of raw data on a
+# 16-core CPU; 1 TB of FP32 values is 2.5e11 sample*channel values.
+PAPER_CONTEXT = {"cpu_hours_per_TB": 21.0, "cpu_cores": 16,
+                 "sample_channel_updates_per_s": 2.5e11 / (21.0 * 3600.0),
+                 "note": "context only (the paper's multi-core CPU gridding of FAST data, "
+                         "wall-clock reading; not a measurement of this build)"}
 GATHER_SRC = os.path.join(ROOT, "paper_2012_13173_amd", "csrc", "gather.hip")
 
 
@@ -71,7 +89,7 @@ def oracle_sample(w, budget_s=15.0, patch=32, max_patches=40, seed=7):
     lon = w.lon.cpu().numpy()
     lat = w.lat.cpu().numpy()
     rng = np.random.default_rng(seed)
-    t_total, cells, refs = 0.0, [], []
+    t_total, cells, refs, pairs = 0.0, [], [], []
     R = w.support_deg
     for _ in range(max_patches):
         x0 = int(rng.integers(0, g.nx - patch + 1))
@@ -86,27 +104,32 @@ def oracle_sample(w, budget_s=15.0, patch=32, max_patches=40, seed=7):
                          & (lon >= clon.min() - m / coslat) & (lon <= clon.max() + m / coslat))[0]
         rows = w.spectra.index_select(0, torch.from_numpy(sel).to(w.spectra.device)).cpu().numpy()
         t0 = time.perf_counter()
-        V, W, _ = oracle.grid_cells(lon[sel], lat[sel], rows, g, w.fwhm_deg, R, c)
+        V, W, npair = oracle.grid_cells(lon[sel], lat[sel], rows, g, w.fwhm_deg, R, c)
         t_total += time.perf_counter() - t0
         cells.append(c)
         refs.append(V)
+        pairs.append(npair)
         if t_total >= budget_s:
             break
     return {"cells": np.concatenate(cells), "V": np.concatenate(refs), "t": t_total,
-            "cores": cores, "patch": patch, "patches": len(cells)}
+            "pairs": int(np.concatenate(pairs).sum()), "cores": cores, "patch": patch,
+            "patches": len(cells)}
 
 
-def cpu_baseline(w, samp):
-    """The oracle's rate on the sample, extrapolated to the whole grid."""
+def cpu_baseline(w, samp, total_pairs):
+    """The oracle's rate on the sample, extrapolated to the whole grid by pair
+    work: t_sample x (sum over all cells of their samples within R) / (the
+    same sum over the sampled cells)."""
     g = w.grid
     done = samp["cells"].size
-    t_full = samp["t"] * g.ncells / done
+    t_full = samp["t"] * total_pairs / max(samp["pairs"], 1)
     return {"value": w.n * w.nchan / t_full, "unit": "sample*channel updates/s",
             "cores": samp["cores"], "kind": "oracle",
             "sample": f"{done} of {g.ncells} cells ({samp['patches']} random "
-                      f"{samp['patch']}x{samp['patch']}-cell patches), all {w.nchan} channels, "
-                      f"FP64 bucketed oracle, {samp['t']:.1f} s measured, whole-grid time "
-                      f"extrapolated by cell count ({t_full:.0f} s)"}
+                      f"{samp['patch']}x{samp['patch']}-cell patches, {samp['pairs']} of "
+                      f"{total_pairs} pairs within R), all {w.nchan} channels, FP64 bucketed "
+                      f"oracle, {samp['t']:.1f} s measured, whole-grid time extrapolated by "
+                      f"pair count ({t_full:.0f} s)"}
 
 
 def sampled_errors(cube, samp):
@@ -120,6 +143,165 @@ def sampled_errors(cube, samp):
     d = np.where(ok, gv - V, 0.0)
     r = np.where(ok, V, 0.0)
     return np.sqrt((d * d).sum(0) / (r * r).sum(0))
+
+
+FORM_CODE = {"bf16": hcg.HCG_BF16, "f16_scaled": hcg.HCG_F16_SCALED,
+             "bf16_split": hcg.HCG_BF16_SPLIT, "fp8e4m3_scaled": hcg.HCG_FP8E4M3_SCALED,
+             "fp8e4m3_split": hcg.HCG_FP8E4M3_SPLIT}
+
+
+def algorithmic_bytes(w, form, packed):
+    """Bytes a gather launch must move at least: the spectra once (in the
+    form's storage, plan-ordered encodings with their padding to groups of 8
+    samples and 16 channels), the sorted unit vectors and permutation once
+    (36 B per sample) and the cube once."""
+    C = w.nchan
+    if packed:
+        spec = ELEM_BYTES[form] * 8 * ((w.n + 7) // 8) * ((C + 15) // 16 * 16)
+    else:
+        spec = ELEM_BYTES[form] * w.n * C
+    return float(spec + 36 * w.n + 4 * C * w.grid.ncells)
+
+
+def time_events(run, reps=3):
+    stream = torch.cuda.current_stream()
+    run()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def run_forms(w, order_forms, packed_forms, grid_avg, samp, errs):
+    """The matrix-core precision forms on one plan of ``w``: input-order
+    encodings (hcg_quantize + hcg_grid) and plan-ordered ones
+    (hcg_quantize_packed + hcg_grid_packed); gather times by HIP events,
+    encoding times beside, errors against the oracle sample into ``errs``."""
+    g = w.grid
+    dev = w.spectra.device
+    stream = torch.cuda.current_stream()
+    updates = w.n * w.nchan
+    plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
+    out_cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=dev)
+    forms = {}
+
+    def rates(rec, form, packed, ms):
+        alg = algorithmic_bytes(w, form, packed)
+        rec["algorithmic_hbm_bytes"] = alg
+        rec["hbm_frac_of_peak_algorithmic"] = alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    for name in order_forms:
+        form = FORM_CODE[name]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        enc, scale = hcg.hcg_quantize(w.spectra, form)
+        e1.record(stream)
+        ms = time_events(lambda: hcg.hcg_grid(plan, enc, out_cube, dtype=form, chan_scale=scale))
+        enc_ms = e0.elapsed_time(e1)
+        forms[name] = {"grid_ms": ms, "encode_ms": enc_ms,
+                       "grid_updates_per_s": updates / (ms * 1e-3),
+                       "speedup_vs_f32_grid": grid_avg / ms,
+                       "speedup_vs_f32_grid_incl_encode": grid_avg / (ms + enc_ms)}
+        rates(forms[name], name, False, ms)
+        del enc
+        if samp is not None:
+            errs[name] = sampled_errors(out_cube, samp)
+        log(f"form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 gather), "
+            f"encode {enc_ms:.2f} ms")
+    # the same forms encoded once in the plan's sorted order
+    for name in packed_forms:
+        form = FORM_CODE[name]
+        enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
+        del enc, scale  # the timed call below reuses the cached allocation
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
+        e1.record(stream)
+        ms = time_events(lambda: hcg.hcg_grid_packed(plan, enc, out_cube, dtype=form,
+                                                     chan_scale=scale))
+        enc_ms = e0.elapsed_time(e1)
+        key = "packed_" + name
+        forms[key] = {"grid_ms": ms, "encode_ms": enc_ms,
+                      "grid_updates_per_s": updates / (ms * 1e-3),
+                      "speedup_vs_f32_grid": grid_avg / ms,
+                      "speedup_vs_f32_grid_incl_encode": grid_avg / (ms + enc_ms)}
+        rates(forms[key], name, True, ms)
+        hbm = measured_traffic(w.name, key)
+        if hbm:
+            forms[key]["measured_hbm_bytes_per_launch"] = hbm
+            forms[key]["measured_hbm_GBps"] = hbm / (ms * 1e-3) / 1e9
+        del enc
+        if samp is not None:
+            errs[key] = sampled_errors(out_cube, samp)
+        log(f"plan-ordered form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 "
+            f"gather), encode {enc_ms:.2f} ms")
+    plan.destroy()
+    del out_cube
+    return forms
+
+
+def add_errors(forms, errs):
+    """Per-form error record: largest and median per-channel relative L2 on
+    the oracle sample, and whether the largest meets the form's budget."""
+    for k, e in errs.items():
+        rec = forms.setdefault(k, {})
+        base = k[len("packed_"):] if k.startswith("packed_") else k
+        rec["rel_l2_max_over_channels"] = float(e.max())
+        rec["rel_l2_median_over_channels"] = float(np.median(e))
+        rec["budget"] = BUDGET[base]
+        rec["meets_budget"] = bool(e.max() <= BUDGET[base])
+
+
+def run_c2(oracle_budget_s=8.0):
+    """The metric's many-channel configuration: 1,976,000 samples x 8,192
+    channels -> 400 x 400 cells (the FP32 gather, FP16 x channel scale, BF16
+    and BF16 hi+lo, input order and plan-ordered), every form against the
+    oracle on sampled cells."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = synth.drift_scan_8192(device=dev)
+    torch.cuda.synchronize()
+    log(f"c2: synthesised {w.n} samples x {w.nchan} channels in {time.perf_counter() - t0:.1f} s")
+    g = w.grid
+    plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
+    stats = plan.stats()
+    cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=dev)
+    ms = time_events(lambda: hcg.hcg_grid(plan, w.spectra, cube))
+    plan.destroy()
+    updates = w.n * w.nchan
+    log(f"c2: FP32 gather {ms:.2f} ms")
+    errs = {}
+    samp = None
+    if oracle_budget_s > 0:
+        samp = oracle_sample(w, budget_s=oracle_budget_s, patch=16)
+        errs["f32"] = sampled_errors(cube, samp)
+    del cube
+    torch.cuda.empty_cache()
+    forms = {"f32": {"grid_ms": ms, "grid_updates_per_s": updates / (ms * 1e-3),
+                     "pair_updates_per_s": stats["pairs"] * w.nchan / (ms * 1e-3),
+                     "tflops": 2.0 * stats["pairs"] * w.nchan / (ms * 1e-3) / 1e12}}
+    forms.update(run_forms(w, ["f16_scaled", "bf16_split", "bf16"],
+                           ["f16_scaled", "bf16_split", "bf16"], ms, samp, errs))
+    add_errors(forms, errs)
+    best = None
+    for k, r in forms.items():
+        if k != "f32" and r.get("meets_budget") and BUDGET.get(k.replace("packed_", "")) == 1e-3:
+            if best is None or r["grid_ms"] < forms[best]["grid_ms"]:
+                best = k
+    out = {"workload": w.name, "n_samples": w.n, "nchan": w.nchan, "grid": [g.nx, g.ny],
+           "pairs": stats["pairs"], "forms": forms,
+           "fastest_form_within_1e-3": best,
+           "speedup_of_fastest_within_1e-3": (ms / forms[best]["grid_ms"]) if best else None}
+    if samp is not None:
+        out["oracle_sample"] = (f"{samp['cells'].size} cells ({samp['patches']} patches of "
+                                f"16x16), all {w.nchan} channels")
+    del w
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_host_stream(w, slabs, samp, pageable_slab=256):
@@ -372,6 +554,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the low-precision forms")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the 8,192-channel leg of the default workload")
     ap.add_argument("--workload", default="drift_scan",
                     choices=["drift_scan", "drift_scan_8192", "large", "batch"],
                     help="drift_scan: 9.12M samples x 1024 channels -> 600 x 600 (default); "
@@ -468,83 +652,23 @@ def main():
     if args.host_stream:
         host_stream = run_host_stream(w, [int(x) for x in args.host_stream.split(",")], samp)
 
-    # the matrix-core precision forms on the same plan (encoding not timed,
-    # reported beside for the plan-ordered encodings)
+    # the matrix-core precision forms on the same plan (encoding timed beside)
     order_forms = {
-        "drift_scan": [("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
-                       ("bf16_split", hcg.HCG_BF16_SPLIT),
-                       ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED),
-                       ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT)],
-        "drift_scan_8192": [("bf16", hcg.HCG_BF16), ("f16_scaled", hcg.HCG_F16_SCALED),
-                            ("bf16_split", hcg.HCG_BF16_SPLIT)],
-        "large": [("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED),
-                  ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT)],
+        "drift_scan": ["bf16", "f16_scaled", "bf16_split", "fp8e4m3_scaled", "fp8e4m3_split"],
+        "drift_scan_8192": ["bf16", "f16_scaled", "bf16_split"],
+        "large": ["fp8e4m3_scaled", "fp8e4m3_split"],
     }[args.workload]
     packed_forms = {
-        "drift_scan": [("f16_scaled", hcg.HCG_F16_SCALED), ("bf16_split", hcg.HCG_BF16_SPLIT),
-                       ("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT), ("bf16", hcg.HCG_BF16),
-                       ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED)],
-        "drift_scan_8192": [("f16_scaled", hcg.HCG_F16_SCALED), ("bf16_split", hcg.HCG_BF16_SPLIT),
-                            ("bf16", hcg.HCG_BF16)],
-        "large": [("fp8e4m3_split", hcg.HCG_FP8E4M3_SPLIT),
-                  ("fp8e4m3_scaled", hcg.HCG_FP8E4M3_SCALED), ("f16_scaled", hcg.HCG_F16_SCALED)],
+        "drift_scan": ["f16_scaled", "bf16_split", "fp8e4m3_split", "bf16", "fp8e4m3_scaled"],
+        "drift_scan_8192": ["f16_scaled", "bf16_split", "bf16"],
+        "large": ["fp8e4m3_split", "fp8e4m3_scaled", "f16_scaled"],
     }[args.workload]
     forms = {}
     if not args.no_forms:
         if samp is not None and args.workload != "drift_scan":
             del cube  # the FP32 cube's errors are taken; make room for the forms' cubes
             torch.cuda.empty_cache()
-        plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
-        out_cube = torch.empty((w.nchan, g.ny, g.nx), dtype=torch.float32, device=dev)
-
-        def time_form(run):
-            run()
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in range(3)]
-            for a, b in evs:
-                a.record(stream)
-                run()
-                b.record(stream)
-            torch.cuda.synchronize()
-            return float(np.mean([a.elapsed_time(b) for a, b in evs]))
-
-        for name, form in order_forms:
-            enc, scale = hcg.hcg_quantize(w.spectra, form)
-            ms = time_form(lambda: hcg.hcg_grid(plan, enc, out_cube, dtype=form, chan_scale=scale))
-            forms[name] = {"grid_ms": ms, "grid_updates_per_s": updates / (ms * 1e-3),
-                           "speedup_vs_f32_grid": grid_avg / ms}
-            del enc
-            if samp is not None:
-                errs[name] = sampled_errors(out_cube, samp)
-            log(f"form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 gather)")
-        # the same forms encoded once in the plan's sorted order
-        for name, form in packed_forms:
-            enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
-            del enc, scale  # the timed call below reuses the cached allocation
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            enc, scale = hcg.hcg_quantize_packed(plan, w.spectra, form)
-            e1.record(stream)
-            ms = time_form(lambda: hcg.hcg_grid_packed(plan, enc, out_cube, dtype=form,
-                                                       chan_scale=scale))
-            enc_ms = e0.elapsed_time(e1)
-            key = "packed_" + name
-            forms[key] = {"grid_ms": ms, "encode_ms": enc_ms,
-                          "grid_updates_per_s": updates / (ms * 1e-3),
-                          "speedup_vs_f32_grid": grid_avg / ms,
-                          "speedup_vs_f32_grid_incl_encode": grid_avg / (ms + enc_ms)}
-            hbm = measured_traffic(w.name, key)
-            if hbm:
-                forms[key]["hbm_bytes_per_launch"] = hbm
-                forms[key]["hbm_GBps"] = hbm / (ms * 1e-3) / 1e9
-                forms[key]["hbm_frac_of_peak"] = hbm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-            del enc
-            if samp is not None:
-                errs[key] = sampled_errors(out_cube, samp)
-            log(f"plan-ordered form {name}: gather {ms:.2f} ms ({grid_avg / ms:.2f}x the FP32 "
-                f"gather), encode {enc_ms:.2f} ms")
-        plan.destroy()
-        del out_cube
+        forms = run_forms(w, order_forms, packed_forms, grid_avg, samp, errs)
     flops = 2.0 * stats["pairs"] * w.nchan
     achieved = flops / (grid_avg * 1e-3) / 1e12
     traffic = measured_traffic(w.name)
@@ -570,8 +694,8 @@ def main():
         "pair_updates_per_s": stats["pairs"] * w.nchan / (grid_avg * 1e-3),
         "pairs": stats["pairs"],
         "candidates": stats["candidates"],
-        "roofline": {"kernel": "hcg::k_gather_mfma<0, 2, true, false, false> (FP32, 512-channel "
-                               "slabs, input order, narrow support)",
+        "roofline": {"kernel": "hcg::k_gather_mfma<0, 2, true, false, false, false, false> "
+                               "(FP32, 512-channel slabs, input order, narrow support)",
                      "bound": "mfma", "achieved": achieved,
                      "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": traffic,
@@ -580,20 +704,24 @@ def main():
                      "traffic_GBps": (traffic / (grid_avg * 1e-3) / 1e9) if traffic else None,
                      "algorithmic_flops_per_launch": flops},
     }
+    out["paper_context"] = PAPER_CONTEXT
     if samp is not None:
-        cb = cpu_baseline(w, samp)
+        cb = cpu_baseline(w, samp, stats["pairs"])
         out["cpu_baseline"] = cb
-        for k, e in errs.items():
-            rec = forms.setdefault(k, {"grid_ms": grid_avg, "grid_updates_per_s":
-                                       updates / (grid_avg * 1e-3), "speedup_vs_f32_grid": 1.0})
-            rec["rel_l2_max_over_channels"] = float(e.max())
-            rec["rel_l2_median_over_channels"] = float(np.median(e))
+        forms.setdefault("f32", {"grid_ms": grid_avg, "grid_updates_per_s":
+                                 updates / (grid_avg * 1e-3), "speedup_vs_f32_grid": 1.0})
+        add_errors(forms, errs)
         log(f"cpu baseline {cb['value']:.3g} /s on {cb['cores']} cores ({samp['t']:.1f} s); "
             "sampled errors " + ", ".join(f"{k} {e.max():.2e}" for k, e in errs.items()))
     if forms:
         out["forms"] = forms
     if host_stream:
         out["host_stream"] = host_stream
+    if args.workload == "drift_scan" and not args.no_c2:
+        del w, wmap
+        cube = None
+        torch.cuda.empty_cache()
+        out["c2"] = run_c2(0.0 if args.no_cpu_baseline else 8.0)
     print(json.dumps(out), flush=True)
 
 
