@@ -497,12 +497,16 @@ typedef struct {
   double support_deg;
 } hcg_field_desc;
 
-/* The data of one field for hcg_grid_batch (FP32 spectra). */
+/* The data of one field for hcg_grid_batch: the spectra in any storage form
+ * of hcg_grid (input sample order; the split dtypes hold the hi plane, then
+ * the lo plane), with the channel scales of the scaled forms. */
 typedef struct {
-  const float* spectra; /* device float32 [n][nchan], input sample order */
-  int64_t nchan;        /* >= 1 */
-  float* cube;          /* device float32 [nchan][ny][nx] */
-  float* weights;       /* device float32 [ny][nx] or NULL */
+  const void* spectra;     /* device, dtype storage [n][nchan] ([2][n][nchan] split) */
+  int64_t nchan;           /* >= 1 */
+  int32_t dtype;           /* hcg_dtype */
+  const float* chan_scale; /* device float [nchan] for the scaled dtypes, else NULL */
+  float* cube;             /* device float32 [nchan][ny][nx] */
+  float* weights;          /* device float32 [ny][nx] or NULL */
 } hcg_field_data;
 
 /*
@@ -519,20 +523,25 @@ hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_des
                           const hcg_opts* opts, void* hip_stream);
 
 /*
- * hcg_grid_batch -- Eq. (1) for every field of the batch in one launch.
- *   data  host array [nfields] in the order given to hcg_plan_batch.
- * Every (field, tile, channel slab) is a work item; a persistent kernel of
- * two workgroups per CU pops the items, ordered largest-cost first, from a
- * shared counter.  The first call may run the batch several times to
- * autotune (same results every time); it then captures the launch in a
- * hipGraph that later calls replay.  Pointers and channel counts may change
- * between calls (the device tables are rewritten before the replay; the
- * rewrite waits for the previous launch, on whichever stream it ran).
- * Asynchronous on hip_stream after the first call (which synchronises).
- * Errors: HCG_E_ARG (NULL pointers, nchan < 1), HCG_E_STATE (not a live
- * batch), HCG_E_NOMEM, HCG_E_DEVICE.  Calls on one batch must not overlap
- * on the host (one thread at a time); the outputs of successive calls are
- * written in call order.
+ * hcg_grid_batch -- Eq. (1) for every field of the batch in one graph launch.
+ *   data  host array [nfields] in the order given to hcg_plan_batch; fields
+ *         may use different storage forms.
+ * Every (field, tile, channel slab) is a work item.  Items are grouped by
+ * kernel class (the few-channel FP32 gather, and the matrix-core gather of
+ * each storage form); per class, a persistent kernel of two workgroups per
+ * CU pops the items, ordered largest-cost first, from per-XCD counters.  The
+ * first call may run the batch several times to autotune the channel slab
+ * and the field order (same results every time); it then captures the
+ * classes' launches in one hipGraph that later calls replay.  Pointers,
+ * forms and channel counts may change between calls (the device tables are
+ * rewritten before the replay, and the graph captured again when the
+ * classes change; the rewrite waits for the previous launch, on whichever
+ * stream it ran).  Asynchronous on hip_stream after the first call (which
+ * synchronises).  Errors: HCG_E_ARG (NULL pointers, nchan < 1, chan_scale
+ * missing for a scaled dtype or given for another), HCG_E_UNSUPPORTED
+ * (unknown dtype), HCG_E_STATE (not a live batch), HCG_E_NOMEM,
+ * HCG_E_DEVICE.  Calls on one batch must not overlap on the host (one thread
+ * at a time); the outputs of successive calls are written in call order.
  */
 hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* data, void* hip_stream);
 

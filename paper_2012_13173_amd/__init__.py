@@ -93,6 +93,7 @@ class FieldDescC(ctypes.Structure):
 
 class FieldDataC(ctypes.Structure):
     _fields_ = [("spectra", ctypes.c_void_p), ("nchan", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("chan_scale", ctypes.c_void_p),
                 ("cube", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
 
 
@@ -557,25 +558,34 @@ def hcg_plan_batch(fields, chan_tile: int = 0, nside: int = 0, stream=None) -> B
     return Batch(handle, [f[2] for f in fields], [int(f[0].shape[0]) for f in fields])
 
 
-def hcg_grid_batch(batch: Batch, spectra, cubes, weights=None, stream=None) -> None:
-    """Grids every field: ``spectra[i]`` [n_i, C_i] float32 into ``cubes[i]``
-    [C_i, ny_i, nx_i] (and ``weights[i]`` [ny_i, nx_i] or None).  The tensors
-    must stay alive until the work has run."""
+def hcg_grid_batch(batch: Batch, spectra, cubes, weights=None, dtypes=None, chan_scales=None,
+                   stream=None) -> None:
+    """Grids every field: ``spectra[i]`` ([n_i, C_i], or [2, n_i, C_i] for the
+    split forms, in the storage of ``dtypes[i]``, FP32 by default) into
+    ``cubes[i]`` [C_i, ny_i, nx_i] (and ``weights[i]`` [ny_i, nx_i] or None);
+    ``chan_scales[i]`` for the scaled forms.  The tensors must stay alive
+    until the work has run."""
     nf = len(batch.grids)
     if len(spectra) != nf or len(cubes) != nf:
         raise ValueError(f"need {nf} spectra and cubes")
     weights = weights if weights is not None else [None] * nf
+    dtypes = dtypes if dtypes is not None else [HCG_F32] * nf
+    chan_scales = chan_scales if chan_scales is not None else [None] * nf
     arr = (FieldDataC * nf)()
     for i in range(nf):
-        g, sp, cb = batch.grids[i], spectra[i], cubes[i]
-        if sp.dim() != 2 or int(sp.shape[0]) != batch.ns[i]:
-            raise ValueError(f"field {i}: spectra must be [{batch.ns[i]}, nchan]")
-        C = int(sp.shape[1])
+        g, sp, cb, dt = batch.grids[i], spectra[i], cubes[i], int(dtypes[i])
+        sdt, prefix = _FORM_STORAGE[dt]
+        if (sp.dim() != 2 + len(prefix) or tuple(sp.shape[:len(prefix)]) != prefix
+                or int(sp.shape[-2]) != batch.ns[i]):
+            raise ValueError(f"field {i}: spectra must be "
+                             f"[{', '.join(map(str, prefix + (batch.ns[i], 'nchan')))}]")
+        C = int(sp.shape[-1])
         if tuple(cb.shape) != (C, g.ny, g.nx):
             raise ValueError(f"field {i}: cube must be [{C}, {g.ny}, {g.nx}]")
         if weights[i] is not None and tuple(weights[i].shape) != (g.ny, g.nx):
             raise ValueError(f"field {i}: weights must be [{g.ny}, {g.nx}]")
-        arr[i] = FieldDataC(_dptr(sp, torch.float32, "spectra"), C,
+        arr[i] = FieldDataC(_dptr(sp, sdt, "spectra"), C, dt,
+                            _dptr(chan_scales[i], torch.float32, "chan_scale"),
                             _dptr(cb, torch.float32, "cube"),
                             _dptr(weights[i], torch.float32, "weights"))
     _check(load().hcg_grid_batch(batch.handle, arr, _stream(stream)), "hcg_grid_batch")

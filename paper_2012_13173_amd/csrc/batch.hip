@@ -1,18 +1,22 @@
-// Batches of independent maps in one persistent launch.
+// Batches of independent maps in one graph-captured launch of persistent
+// kernels.
 //
 // hcg_plan_batch builds one plan per field (same device steps as hcg_plan).
-// hcg_grid_batch makes every (field, tile, channel slab) a work item: the
-// fields' item ranges are concatenated in a chosen field order (by estimated
-// cost, candidates x channels, largest first, or as given) and the kernel
-// decodes an item index through a small per-field segment table.  One launch
-// of a persistent kernel runs them all; its workgroups pop items from per-XCD
-// counters over contiguous eighths of the item space and steal from the
-// other eighths at the end.  The counter reset and the launch are captured
-// once in a hipGraph and replayed; the argument and segment tables live in
-// device memory and are rewritten before a replay when pointers or channel
-// counts change.  On the first call an autotuner times the channel slab (256
-// or 512 channels) and the field order and keeps the fastest; the choice can
-// be cached on disk (HCG_TUNE_CACHE=<file>).
+// hcg_grid_batch makes every (field, tile, channel slab) a work item.  Items
+// are grouped by kernel class -- the few-channel FP32 gather, and the
+// matrix-core gather of each storage form -- and each class has one
+// persistent kernel that runs all of its fields: the fields' item ranges are
+// concatenated in a chosen field order (by estimated cost, candidates x
+// channels, largest first, or as given) and the kernel decodes an item index
+// through a small per-field segment table.  Its workgroups pop items from
+// per-XCD counters over contiguous eighths of the class's item space and
+// steal from the other eighths at the end.  The counter resets and the
+// class launches are captured once in a hipGraph and replayed; the argument
+// and segment tables live in device memory and are rewritten before a replay
+// when pointers, forms or channel counts change.  On the first call an
+// autotuner times the channel slab (256 or 512 channels) and the field order
+// and keeps the fastest; the choice can be cached on disk
+// (HCG_TUNE_CACHE=<file>).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -21,13 +25,164 @@
 #include <string>
 #include <vector>
 
-#include "hcg_internal.h"
+#include "gather_tile.h"
 
-using namespace hcg;
+namespace hcg {
+
+// Kernel classes of the batch: the matrix-core gather of each storage form
+// (the hcg_dtype values) and the few-channel FP32 gather.
+constexpr int kClsCells = 6;
+constexpr int kClasses = 7;
+
+// ctl: [0..7] next item of each XCD's segment, [8] item count, [9] segment
+// count.  The item space of a class is cut into eight contiguous segments,
+// one per XCD (the hardware deals workgroups to the XCDs in turn, so
+// workgroup b starts on XCD b % 8); a workgroup pops items from its own
+// XCD's segment -- neighbouring tiles of one field, sharing candidate rows in
+// that XCD's L2 -- and, once it is empty, from the others.
+__device__ __forceinline__ uint32_t batch_seg_begin(uint32_t total, int x) {
+  return (uint32_t)(((uint64_t)total * (uint32_t)x) / kBatchXcds);
+}
+
+__global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
+  const uint32_t total = ctl[8];
+  for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
+}
+
+template <int kCls, int kQW, bool kWide>
+__global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
+                                                         const BatchSeg* __restrict__ segs,
+                                                         uint32_t* __restrict__ ctl) {
+  __shared__ GatherSmem sm;
+  __shared__ uint32_t s_item;
+  const uint32_t total = ctl[8];
+  const uint32_t nseg = ctl[9];
+  const int home = (int)(blockIdx.x % kBatchXcds);
+  int k = 0;  // segments visited so far (thread 0 only)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t it = 0xFFFFFFFFu;
+      while (k < kBatchXcds) {
+        const int x = (home + k) % kBatchXcds;
+        const uint32_t i = atomicAdd(&ctl[x], 1u);
+        if (i < batch_seg_begin(total, x + 1)) { it = i; break; }
+        ++k;
+      }
+      s_item = it;
+    }
+    __syncthreads();
+    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it == 0xFFFFFFFFu) break;
+    // the last segment whose base is <= it
+    uint32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    const uint32_t local = it - sg.base;
+    const uint32_t slab = local / sg.ntiles;
+    const uint32_t tile = local - slab * sg.ntiles;
+    const GatherArgs& a = fields[sg.field];  // read on demand (scalar loads)
+    if constexpr (kCls == kClsCells) {
+      gather_cells_tile_wg(a, (int)tile, sm);
+    } else if constexpr (kCls == kBF16Split) {  // 256-channel slabs only (registers)
+      if (a.vec) gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
+      else gather_tile<kBF16Split, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
+    } else {
+      if (a.vec) gather_tile<kCls, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
+      else gather_tile<kCls, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
+    }
+    __syncthreads();
+  }
+}
 
 namespace {
-constexpr uint64_t kBatchMagic = 0x48434742'41544331ull;  // "HCGBATC1"
+
+template <int kCls>
+void launch_cls(int qw, bool wide, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
+                int nblocks, hipStream_t stream) {
+  if (qw == 2 && wide) k_gather_batch<kCls, 2, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  else if (qw == 2) k_gather_batch<kCls, 2, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  else if (wide) k_gather_batch<kCls, 1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+  else k_gather_batch<kCls, 1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
 }
+
+hcg_status launch_class(int cls, int qw, bool wide, const GatherArgs* fields,
+                        const BatchSeg* segs, uint32_t* ctl, int nblocks, hipStream_t stream) {
+  k_batch_reset<<<1, 1, 0, stream>>>(ctl);
+  HCG_LAUNCH_CHECK("k_batch_reset");
+  switch (cls) {
+    case kClsCells:
+      if (wide) k_gather_batch<kClsCells, 1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+      else k_gather_batch<kClsCells, 1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+      break;
+    case kBF16Split:
+      if (wide) k_gather_batch<kBF16Split, 1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+      else k_gather_batch<kBF16Split, 1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+      break;
+    case kF32: launch_cls<kF32>(qw, wide, fields, segs, ctl, nblocks, stream); break;
+    case kBF16: launch_cls<kBF16>(qw, wide, fields, segs, ctl, nblocks, stream); break;
+    case kF16S: launch_cls<kF16S>(qw, wide, fields, segs, ctl, nblocks, stream); break;
+    case kFP8S: launch_cls<kFP8S>(qw, wide, fields, segs, ctl, nblocks, stream); break;
+    default: launch_cls<kFP8Split>(qw, wide, fields, segs, ctl, nblocks, stream); break;
+  }
+  HCG_LAUNCH_CHECK("k_gather_batch");
+  return HCG_OK;
+}
+
+// Element size and planes of each storage form (input sample order).
+size_t form_elem(int dtype) {
+  return dtype == HCG_F32 ? 4 : (dtype == HCG_FP8E4M3_SCALED || dtype == HCG_FP8E4M3_SPLIT) ? 1 : 2;
+}
+bool form_scaled(int dtype) {
+  return dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED || dtype == HCG_FP8E4M3_SPLIT;
+}
+bool form_split(int dtype) { return dtype == HCG_BF16_SPLIT || dtype == HCG_FP8E4M3_SPLIT; }
+
+// Kernel class of a field's data.
+int field_class(const hcg_field_data& d) {
+  return (d.dtype == HCG_F32 && d.nchan <= 8) ? kClsCells : (int)d.dtype;
+}
+
+// Gather arguments of one field: the plan's arrays, the spectra in the form's
+// storage (the low plane of a split form follows the high plane), the
+// channel scales, the outputs.
+GatherArgs make_field_args(const hcg_plan_s* p, const hcg_field_data& d) {
+  GatherArgs a;
+  memset(&a, 0, sizeof(a));  // padding bytes too: the tables are compared bytewise
+  a.cells = p->cells;
+  a.kern = p->kern;
+  a.xyz = p->xyz;
+  a.sentinel = (uint32_t)p->n;
+  a.perm = p->perm;
+  a.ranges = p->ranges;
+  a.nranges = p->nranges;
+  a.maxr = p->maxr;
+  a.spec = d.spectra;
+  const size_t esz = form_elem(d.dtype);
+  a.spec_lo = form_split(d.dtype) ? (const char*)d.spectra + esz * (size_t)p->n * d.nchan : nullptr;
+  a.scale = d.chan_scale;
+  a.C = d.nchan;
+  a.g = p->grid;
+  a.ntx = p->ntx;
+  a.ntiles = p->ntx * p->nty;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.vec = (d.nchan % 4 == 0 && (uintptr_t)d.spectra % (4 * esz) == 0 &&
+           (!a.spec_lo || (uintptr_t)a.spec_lo % (4 * esz) == 0)) ? 1 : 0;
+  a.c2R = support_chord2(p);
+  a.cube = d.cube;
+  a.wmap = d.weights;
+  return a;
+}
+
+constexpr uint64_t kBatchMagic = 0x48434742'41544332ull;  // "HCGBATC2"
+
+}  // namespace
+}  // namespace hcg
+
+using namespace hcg;
 
 struct hcg_batch_s {
   uint64_t magic = kBatchMagic;
@@ -37,13 +192,14 @@ struct hcg_batch_s {
   std::vector<std::vector<uint32_t>> ncand;  // per field, per tile
   hcg_opts opts{};
   GatherArgs* d_fields = nullptr;  // [nfields]
-  BatchSeg* d_segs = nullptr;  // [nfields]
-  uint32_t* d_ctl = nullptr;   // kBatchCtl words
+  BatchSeg* d_segs = nullptr;      // [kClasses][nfields]
+  uint32_t* d_ctl = nullptr;       // [kClasses][kBatchCtl]
   std::vector<GatherArgs> h_fields;
   std::vector<int64_t> built_C;
-  std::vector<int> built_vec;
+  std::vector<int> built_vec, built_cls;
   int built_qw = 0, built_order = -1;
-  uint32_t nitems = 0;
+  uint32_t nitems[kClasses] = {};
+  bool wide[kClasses] = {};
   int qw = 0, cost_order = 1;
   bool tuned = false;
   double tune_ms[4] = {0, 0, 0, 0};
@@ -81,8 +237,9 @@ void free_batch(hcg_batch_s* b) {
   delete b;
 }
 
-// Item segments for slab width 256 * qw (256 for fields whose rows cannot be
-// read four elements at a time; one item per tile for C <= 8).
+// Item segments of every class for slab width 256 * qw (256 for the BF16
+// hi+lo form and for fields whose rows cannot be read four elements at a
+// time; one item per tile for the few-channel class).
 hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int cost_order,
                        hipStream_t stream) {
   const size_t nf = b->plans.size();
@@ -90,13 +247,16 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
   std::vector<BatchSeg> seg(nf);
   for (size_t f = 0; f < nf; ++f) {
     const int64_t C = data[f].nchan;
-    const int64_t width = (C <= 8) ? C : (b->built_vec[f] ? 256 * qw : 256);
-    const int64_t slabs = (C <= 8) ? 1 : (C + width - 1) / width;
+    const int cls = b->built_cls[f];
+    const bool cells = cls == kClsCells;
+    const int64_t width =
+        cells ? C : ((b->built_vec[f] && cls != kBF16Split) ? 256 * qw : 256);
+    const int64_t slabs = cells ? 1 : (C + width - 1) / width;
     const std::vector<uint32_t>& nc = b->ncand[f];
     double cand = 0.0;
     for (uint32_t v : nc) cand += v;
     // candidates x channels, plus the output writes
-    cost[f] = cand * (C <= 8 ? 8.0 : (double)std::max<int64_t>(C, 64)) +
+    cost[f] = cand * (cells ? 8.0 : (double)std::max<int64_t>(C, 64)) +
               64.0 * (double)nc.size() * (double)C;
     seg[f] = BatchSeg{0u, (uint32_t)nc.size(), (uint32_t)slabs, (uint32_t)f};
   }
@@ -105,33 +265,48 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
   if (cost_order)
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-  std::vector<BatchSeg> host(nf);
-  uint64_t base = 0;
-  for (size_t k = 0; k < nf; ++k) {
-    host[k] = seg[order[k]];
-    host[k].base = (uint32_t)base;
-    base += (uint64_t)host[k].ntiles * host[k].slabs;
-    if (base >= 0xFFFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
+  std::vector<BatchSeg> host((size_t)kClasses * nf);
+  std::vector<uint32_t> ctl((size_t)kClasses * kBatchCtl, 0u);
+  for (int c = 0; c < kClasses; ++c) {
+    uint64_t base = 0;
+    uint32_t nseg = 0;
+    bool wide = false;
+    for (size_t k = 0; k < nf; ++k) {
+      const size_t f = order[k];
+      if (b->built_cls[f] != c) continue;
+      BatchSeg sg = seg[f];
+      sg.base = (uint32_t)base;
+      host[(size_t)c * nf + nseg++] = sg;
+      base += (uint64_t)sg.ntiles * sg.slabs;
+      if (base >= 0xFFFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
+      wide = wide || !(b->h_fields[f].c2R < kNarrowChord2);
+    }
+    b->nitems[c] = (uint32_t)base;
+    b->wide[c] = wide;
+    ctl[(size_t)c * kBatchCtl + 8] = (uint32_t)base;
+    ctl[(size_t)c * kBatchCtl + 9] = nseg;
   }
-  b->nitems = (uint32_t)base;
-  HCG_HIP(hipMemcpyAsync(b->d_segs, host.data(), sizeof(BatchSeg) * nf, hipMemcpyHostToDevice,
-                         stream));
-  uint32_t ctl[kBatchCtl] = {0};
-  ctl[8] = b->nitems;
-  ctl[9] = (uint32_t)nf;
-  HCG_HIP(hipMemcpyAsync(b->d_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, stream));
+  HCG_HIP(hipMemcpyAsync(b->d_segs, host.data(), sizeof(BatchSeg) * host.size(),
+                         hipMemcpyHostToDevice, stream));
+  HCG_HIP(hipMemcpyAsync(b->d_ctl, ctl.data(), sizeof(uint32_t) * ctl.size(),
+                         hipMemcpyHostToDevice, stream));
   HCG_HIP(hipStreamSynchronize(stream));  // the host arrays above go out of scope
   b->built_qw = qw;
   b->built_order = cost_order;
   return HCG_OK;
 }
 
+// One persistent launch (after its counter reset) per class that has items.
 hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
-  hcg_status st = launch_batch_reset(b->d_ctl, stream);
-  if (st != HCG_OK) return st;
-  bool wide = false;
-  for (const GatherArgs& f : b->h_fields) wide = wide || !(f.c2R < kNarrowChord2);
-  return launch_batch(b->qw, wide, b->d_fields, b->d_segs, b->d_ctl, b->nblocks, stream);
+  const size_t nf = b->plans.size();
+  for (int c = 0; c < kClasses; ++c) {
+    if (!b->nitems[c]) continue;
+    const hcg_status st = launch_class(c, b->qw, b->wide[c], b->d_fields,
+                                       b->d_segs + (size_t)c * nf,
+                                       b->d_ctl + (size_t)c * kBatchCtl, b->nblocks, stream);
+    if (st != HCG_OK) return st;
+  }
+  return HCG_OK;
 }
 
 std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {
@@ -149,6 +324,7 @@ std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {
     mix(p->sigma_rad);
     mix(p->support_rad);
     mix((double)data[f].nchan);
+    mix((double)data[f].dtype);
   }
   char buf[32];
   snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
@@ -226,8 +402,8 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
   }
   b->nblocks = 2 * cus;  // two 256-thread workgroups per CU
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||
-      hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields) != hipSuccess ||
-      hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl) != hipSuccess ||
+      hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields * kClasses) != hipSuccess ||
+      hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl * kClasses) != hipSuccess ||
       hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
@@ -251,20 +427,30 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
   hcg_batch_s* b = batch;
   hipStream_t stream = (hipStream_t)hip_stream;
   const size_t nf = b->plans.size();
+  for (size_t f = 0; f < nf; ++f) {
+    const hcg_field_data& d = data[f];
+    if (!d.spectra || !d.cube) return fail(HCG_E_ARG, "hcg_grid_batch: field %zu: NULL spectra or cube", f);
+    if (d.nchan < 1) return fail(HCG_E_ARG, "hcg_grid_batch: field %zu: nchan must be >= 1", f);
+    if (d.dtype < HCG_F32 || d.dtype > HCG_FP8E4M3_SPLIT)
+      return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: field %zu: unknown dtype %d", f, (int)d.dtype);
+    if (form_scaled(d.dtype) != (d.chan_scale != nullptr))
+      return fail(HCG_E_ARG, "hcg_grid_batch: field %zu: chan_scale is required for the scaled "
+                  "dtypes and must be NULL for the others", f);
+  }
   // the tables below are rewritten on this stream: wait for the last launch,
   // whichever stream it ran on
   if (b->launched) HCG_HIP(hipStreamWaitEvent(stream, b->done, 0));
   // argument table
   bool layout_changed = b->built_C.size() != nf;
   std::vector<GatherArgs> fresh(nf);
-  std::vector<int> vecs(nf);
+  std::vector<int> vecs(nf), clss(nf);
   for (size_t f = 0; f < nf; ++f) {
     const hcg_field_data& d = data[f];
-    if (!d.spectra || !d.cube) return fail(HCG_E_ARG, "hcg_grid_batch: field %zu: NULL spectra or cube", f);
-    if (d.nchan < 1) return fail(HCG_E_ARG, "hcg_grid_batch: field %zu: nchan must be >= 1", f);
-    fresh[f] = make_f32_args(b->plans[f], d.spectra, d.nchan, d.cube, d.weights);
-    vecs[f] = (d.nchan % 4 == 0 && (uintptr_t)d.spectra % 16 == 0) ? 1 : 0;
-    if (!layout_changed && (b->built_C[f] != d.nchan || b->built_vec[f] != vecs[f]))
+    fresh[f] = make_field_args(b->plans[f], d);
+    vecs[f] = fresh[f].vec;
+    clss[f] = field_class(d);
+    if (!layout_changed && (b->built_C[f] != d.nchan || b->built_vec[f] != vecs[f] ||
+                            b->built_cls[f] != clss[f]))
       layout_changed = true;
   }
   if (memcmp(fresh.data(), b->h_fields.data(), sizeof(GatherArgs) * nf) != 0) {
@@ -275,6 +461,7 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
   if (layout_changed) {
     b->built_C.resize(nf);
     b->built_vec = vecs;
+    b->built_cls = clss;
     for (size_t f = 0; f < nf; ++f) b->built_C[f] = data[f].nchan;
     b->built_qw = 0;  // force a rebuild
   }
@@ -318,11 +505,14 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     }
     b->tuned = true;
   }
-  if (b->built_qw != b->qw || b->built_order != b->cost_order) {
+  const bool rebuilt = b->built_qw != b->qw || b->built_order != b->cost_order;
+  if (rebuilt) {
     st = build_items(b, data, b->qw, b->cost_order, stream);
     if (st != HCG_OK) return st;
   }
-  if (!b->exec || b->graph_qw != b->qw) {
+  // the graph holds one launch per class with items: capture again when the
+  // set of classes, their narrow/wide kernels or the slab width changed
+  if (!b->exec || b->graph_qw != b->qw || rebuilt) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     HCG_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -364,7 +554,9 @@ extern "C" hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info
   info->cost_order = batch->cost_order;
   info->tuned = batch->tuned ? 1 : 0;
   info->graph_captured = batch->exec ? 1 : 0;
-  info->items = batch->nitems;
+  int64_t items = 0;
+  for (int c = 0; c < kClasses; ++c) items += batch->nitems[c];
+  info->items = items;
   info->persistent_blocks = batch->nblocks;
   for (int k = 0; k < 4; ++k) info->tune_ms[k] = batch->tune_ms[k];
   return HCG_OK;

@@ -28,795 +28,9 @@
 #include <cmath>
 #include <vector>
 
-#include "hcg_internal.h"
-#include "sphere.h"
+#include "gather_tile.h"
 
 namespace hcg {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-constexpr int kKB = 64;             // candidates staged per block
-
-// FP32 weight of a pair inside the support: the exponent -d^2 log2(e) /
-// (2 sigma^2) is formed in FP64 and evaluated with the hardware base-2
-// exponential (v_exp_f32; the exponent lies in [-6.5, 0] for a 3 sigma
-// support and [-18, 0] for 5 sigma, so no result is subnormal).
-template <bool kWide>
-__device__ __forceinline__ float pair_weight(double c2, double wscale) {
-  return __builtin_amdgcn_exp2f((float)(dist2_from_chord2<kWide>(c2) * wscale));
-}
-
-// bit q (q < 8) of the result: any of bits 4q .. 4q + 3 of x
-__device__ __forceinline__ uint32_t any_of_nibbles(uint32_t x) {
-  x |= x >> 1;
-  x |= x >> 2;
-  x &= 0x11111111u;
-  x = (x | (x >> 3)) & 0x03030303u;
-  x = (x | (x >> 6)) & 0x000F000Fu;
-  return (x | (x >> 12)) & 0xFFu;
-}
-// bit q (q < 4) of the result: any of bits 8q .. 8q + 7 of x
-__device__ __forceinline__ uint32_t any_of_bytes(uint32_t x) {
-  x |= x >> 1;
-  x |= x >> 2;
-  x |= x >> 4;
-  x &= 0x01010101u;
-  x = (x | (x >> 7)) & 0x00030003u;
-  return (x | (x >> 14)) & 0xFu;
-}
-
-// Centres and coarse thresholds of the four 4 x 4 cell blocks of tile (tx,
-// ty); called by threads 0..63 (block t / 16, cell t % 16).  The centre is
-// the normalised mean of the block's cells inside the grid; a candidate can
-// only be within R of a cell of the block if it is within R + h of the
-// centre (h: the largest centre-to-cell distance; triangle inequality), so
-// the threshold is the squared chord of R + h, with slack for rounding.  A
-// block without cells gets threshold -1 (never marked).
-__device__ void block_centres(const GatherArgs& a, int tx, int ty, int t, double4* ctr) {
-  const GridGeom& g = a.g;
-  const int cb = t >> 4, i = t & 15;
-  const int x = tx * kTileX + (cb & 1) * 4 + (i & 3), y = ty * kTileY + (cb >> 1) * 4 + (i >> 2);
-  const bool in_grid = x < g.nx && y < g.ny;
-  const CellVec v = cell_at(a.cells, g, x, y);
-  const bool valid = in_grid && v.x == v.x;  // a cell without a centre is left out
-  double sx = valid ? v.x : 0.0, sy = valid ? v.y : 0.0, sz = valid ? v.z : 0.0;
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-    sx += __shfl_xor(sx, o);
-    sy += __shfl_xor(sy, o);
-    sz += __shfl_xor(sz, o);
-  }
-  const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
-  const CellVec c{sx / nrm, sy / nrm, sz / nrm};
-  double hc2 = valid ? chord2(c, make_double4(v.x, v.y, v.z, 0.0)) : 0.0;
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) hc2 = fmax(hc2, __shfl_xor(hc2, o));
-  const double R = 2.0 * asin(fmin(0.5 * sqrt(a.c2R), 1.0));
-  const double h = 2.0 * asin(fmin(0.5 * sqrt(hc2), 1.0));
-  const double sh = sin(0.5 * fmin(R + h, kPi));
-  double thr = 4.0 * sh * sh * (1.0 + 1e-9) + 1e-15;
-  if (!(nrm > 0.0)) thr = -1.0;
-  if (i == 0) ctr[cb] = make_double4(c.x, c.y, c.z, thr);
-}
-
-// Loads the tile's candidate ranges into LDS with exclusive prefix sums;
-// returns the total candidate count.  blockDim.x threads take part.
-// With npad > 0 (the sample count rounded up to a multiple of 8) every range
-// is widened to whole groups of 8 sorted positions, capped at npad, and cut
-// where it would overlap the previous one (the plan's ranges are disjoint
-// and increasing), so that every aligned group of 8 candidates is one group
-// of the plan-ordered spectra.  Samples added this way lie outside the
-// plan's ranges, hence beyond R of every cell of the tile: weight 0.
-__device__ uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32_t nr, uint2* s_rng,
-                                 uint32_t* s_pre, uint32_t npad = 0) {
-  const int nt = blockDim.x;
-  for (uint32_t r = threadIdx.x; r < nr; r += nt) s_rng[r] = ranges[r];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0, end = 0;
-    for (uint32_t r = 0; r < nr; ++r) {
-      if (npad) {
-        const uint2 v = s_rng[r];
-        const uint32_t lo = max(v.x & ~7u, end);
-        const uint32_t hi = max(lo, min((v.y + 7u) & ~7u, npad));
-        s_rng[r] = make_uint2(lo, hi);
-        end = hi;
-      }
-      s_pre[r] = acc;
-      acc += s_rng[r].y - s_rng[r].x;
-    }
-    s_pre[nr] = acc;
-  }
-  __syncthreads();
-  return s_pre[nr];
-}
-
-// Sorted position of candidate q; *cur is a monotone cursor over ranges.
-__device__ __forceinline__ uint32_t cand_pos(uint32_t q, const uint2* s_rng, const uint32_t* s_pre,
-                                             uint32_t* cur) {
-  uint32_t r = *cur;
-  while (q >= s_pre[r + 1]) ++r;
-  *cur = r;
-  return s_rng[r].x + (q - s_pre[r]);
-}
-
-// ---------------------------------------------------------------------------
-// Storage forms of the spectra and of the weights on the matrix cores.
-// ---------------------------------------------------------------------------
-enum Form : int { kF32 = 0, kBF16 = 1, kBF16Split = 2, kF16S = 3, kFP8S = 4, kFP8Split = 5 };
-
-constexpr bool is_fp8(int f) { return f == kFP8S || f == kFP8Split; }
-constexpr bool is_split(int f) { return f == kBF16Split || f == kFP8Split; }
-
-// The FP8 forms encode 256 w: the weights (0.011 .. 1 at a 3 sigma support)
-// then sit in E4M3's normal range, where the relative rounding step is 2^-3
-// everywhere.  The factor is a power of two and cancels in U / W~.
-constexpr float kW8Scale = 256.f;
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
-
-// ---------------------------------------------------------------------------
-// Many channels: matrix-core contraction per staged block of 64 candidates.
-//
-// Workgroup = 4 waves, tile = 8 x 8 cells = four 4 x 4 cell blocks (MFMA M =
-// 16 cells), channel slab = 4 waves x 64 QW channels.  Per block:
-//  - weights: wave w computes the FP64 weights of cell block w for the 64
-//    candidates (one cell per lane), rounds them to the operand type and
-//    writes them to LDS in the A-operand layout; one bit per (cell block,
-//    k-step) marks a non-zero sub-block;
-//  - contraction: wave w streams its channels of the block's candidate rows
-//    from HBM into B operands and issues the MFMAs of the non-zero
-//    sub-blocks for all four cell blocks.
-// Operand layouts (lane l, i = l % 16, g = l / 16):
-//   FP32  v_mfma_f32_16x16x4_f32: A = w(cell i, cand 4s + g), B = spectrum of
-//         cand 4s + g at channel 4i + q (MFMA q of a 64-channel group);
-//   16-bit / FP8 16x16x32: A = w(cell i, cands 32s + 8g .. +7) packed, B = the
-//         same 8 candidates at channel 4i + q, repacked from 8-byte (16-bit)
-//         or 4-byte (FP8) row loads.
-// Output D[i][j]: lane l, register r holds cell 4 (l/16) + r of the block and
-// channel 4 (l % 16) + q of the group.
-// ---------------------------------------------------------------------------
-
-template <int kForm>
-struct FormTraits;
-template <>
-struct FormTraits<kF32> { static constexpr int kK = 4; };
-template <>
-struct FormTraits<kBF16> { static constexpr int kK = 32; };
-template <>
-struct FormTraits<kBF16Split> { static constexpr int kK = 32; };
-template <>
-struct FormTraits<kF16S> { static constexpr int kK = 32; };
-template <>
-struct FormTraits<kFP8S> { static constexpr int kK = 32; };
-template <>
-struct FormTraits<kFP8Split> { static constexpr int kK = 32; };
-
-// E4M3 codes of the weights (256 w <= 256, and its remainder) go through the
-// conversion instructions (f32_to_e4m3_cvt), one instruction each.
-template <int kForm>
-__device__ __forceinline__ uint32_t enc_w(float w) {
-  if (kForm == kF16S) return f32_to_f16(w);
-  if (is_fp8(kForm)) return f32_to_e4m3_cvt(w * kW8Scale);
-  return f32_to_bf16(w);
-}
-template <int kForm>
-__device__ __forceinline__ float dec_w(uint32_t c) {
-  if (kForm == kF16S) return f16_to_f32(c);
-  if (is_fp8(kForm)) return e4m3_cvt_to_f32(c);  // in units of 1 / kW8Scale
-  return bf16_to_f32(c);
-}
-
-// the 16-bit element q (0..3) of an 8-byte load
-__device__ __forceinline__ uint32_t elem16(uint2 d, int q) {
-  const uint32_t w = (q < 2) ? d.x : d.y;
-  return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
-}
-
-// LDS of one workgroup of the gather (shared by the per-plan kernel and the
-// persistent batch kernel).
-struct GatherSmem {
-  uint2 rng[kMaxRangesLimit];
-  uint32_t pre[kMaxRangesLimit + 1];
-  double4 xyz[kKB];
-  double4 ctr[4];  // cell-block centres and coarse thresholds
-  uint32_t row[kKB];
-  uint4 Araw[1024];
-  uint32_t nz[4];
-  double Wt[kTileCells];
-};
-
-// B operand of one 16-channel MFMA tile from the plan-ordered spectra: 8
-// sorted samples of one channel (16 bytes for the 16-bit forms, 8 for FP8).
-template <int kForm>
-struct PackedB {
-  using T = uint4;
-};
-template <>
-struct PackedB<kFP8S> {
-  using T = uint2;
-};
-template <>
-struct PackedB<kFP8Split> {
-  using T = uint2;
-};
-
-// One (tile, channel slab) of the contraction; all 256 threads take part.
-// kPacked: the spectra are plan-ordered, [ceil(n/8)][C][8] elements per plane
-// (hcg_quantize_packed), so a lane's B operand (8 consecutive sorted samples
-// of one channel) is one load and the loads of a block are issued before its
-// weights are computed.
-// kGen: a kernel shape other than the circular Gaussian (FP64 weights through
-// pair_weight_gen).  kMask (FP32, input order): a non-finite spectrum value is
-// a flag -- it is replaced by 0 in the product and its sample is left out of
-// that channel's weight sum, accumulated by a second contraction with the
-// 0/1 flags as the B operand.
-template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide, bool kAhead = true,
-          bool kGen = false, bool kMask = false>
-__device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int slab,
-                                            GatherSmem& sm) {
-  static_assert(!kMask || (kForm == kF32 && !kPacked), "flags are an FP32 input-order form");
-  constexpr int kK = FormTraits<kForm>::kK;
-  constexpr int kNS = kKB / kK;  // k-steps per staged block
-  uint2* s_rng = sm.rng;
-  uint32_t* s_pre = sm.pre;
-  double4* s_xyz = sm.xyz;
-  uint32_t* s_row = sm.row;
-  uint4* s_Araw = sm.Araw;
-  uint32_t* s_nz = sm.nz;
-  double* s_Wt = sm.Wt;
-
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
-  const int tx = tile % a.ntx, ty = tile / a.ntx;
-  const GridGeom& g = a.g;
-  const int64_t C = a.C;
-  const int64_t G = (int64_t)g.nx * g.ny;
-
-  const int ci = lane & 15;
-  const int my_x = tx * kTileX + (wave & 1) * 4 + (ci & 3);
-  const int my_y = ty * kTileY + (wave >> 1) * 4 + (ci >> 2);
-  const CellVec cell = cell_at(a.cells, g, my_x, my_y);
-  const CellFrame frame = kGen ? cell_frame(cell) : CellFrame{0.0, 0.0, 0.0, 0.0, 0.0};
-  // weight of this lane's cell and a staged candidate inside the support
-  auto weight = [&](double c2, const double4& v) -> float {
-    if constexpr (kGen) return (float)pair_weight_gen(a.kern, c2, v, cell, frame);
-    else return pair_weight<kWide>(c2, a.kern.wscale);
-  };
-
-  const uint32_t total =
-      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre,
-                   kPacked ? (a.sentinel + 7u) & ~7u : 0u);
-  if (tid < 64) block_centres(a, tx, ty, tid, sm.ctr);
-
-  floatx4 acc[4][4 * kQW];
-  floatx4 accw[kMask ? 4 : 1][kMask ? 4 * kQW : 1];  // flagged form: channel weight sums
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-    for (int q = 0; q < 4 * kQW; ++q) {
-      acc[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if constexpr (kMask) accw[cb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-  double wsum = 0.0;   // FP64 sum of the unrounded weights (this lane's share)
-  double wtsum = 0.0;  // FP64 sum of the weights as used in the products
-  uint32_t cur = 0;
-  const int64_t c_w = (int64_t)slab * (256 * kQW) + wave * (64 * kQW);
-  const int64_t my_ch = c_w + 4 * (lane & 15);  // + 64 h + q
-  // FP32: 64-channel groups of this wave that hold a channel < C (uniform);
-  // the others issue no products (a wave past the last channel still
-  // computes its cell block's weights for the others)
-  const int hlive = (int)min<int64_t>(kQW, max<int64_t>(0, (C - c_w + 63) / 64));
-
-  float* sA32 = (float*)s_Araw;                // [4][16][64]
-  uint4* sA16 = s_Araw;                        // [4][kNS][64] (+ lo plane after)
-  uint2* sA8 = (uint2*)s_Araw;                 // [4][kNS][64]
-
-  // Candidate staging runs one block ahead (kAhead): wave 0 loads the next
-  // block's unit vectors and rows (or groups) into registers while the
-  // current block is processed, and stores them to LDS at the top of the next
-  // iteration.  Without kAhead (fewer registers) it loads them there.
-  double nx = 0.0, ny = 0.0, nz = 0.0;
-  uint32_t nrow = 0u;
-  // Padding past the last candidate has weight 0 (a NaN position) and the
-  // row or group of the last candidate, which shares the matrix-core step
-  // with every padding candidate that is ever multiplied: a non-finite
-  // spectrum value then reaches no cell through padding (0 x NaN) that it
-  // would not reach through its own candidate.
-  uint32_t pad_row = 0u;
-  if (total > 0u) {
-    uint32_t c0 = 0u;
-    const uint32_t last = cand_pos(total - 1u, s_rng, s_pre, &c0);
-    pad_row = kPacked ? last >> 3 : a.perm[last];
-  }
-  pad_row = __builtin_amdgcn_readfirstlane(pad_row);
-  auto fetch = [&](uint32_t qb) {
-    if (tid < kKB) {
-      const uint32_t q = qb + tid;
-      if (q < total) {
-        const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
-        const double4 v = a.xyz[pos];
-        nx = v.x;
-        ny = v.y;
-        nz = v.z;
-        nrow = kPacked ? pos >> 3 : a.perm[pos];  // group of 8 sorted samples, or row
-      } else {
-        nx = ny = nz = __builtin_nan("");
-        nrow = pad_row;
-      }
-    }
-  };
-  if (kAhead) fetch(0);
-  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
-    if (!kAhead) fetch(q0);
-    if (tid < kKB) {
-      s_xyz[tid] = make_double4(nx, ny, nz, 0.0);
-      if (!kPacked) s_row[tid] = nrow;
-      else if ((tid & 7) == 0) s_row[tid >> 3] = nrow;
-    }
-    __syncthreads();
-    if (kAhead && q0 + kKB < total) fetch(q0 + kKB);
-
-    // plan-ordered spectra: issue the block's B loads now (the first k-step
-    // only where registers are short), so that they are in flight while the
-    // weights are computed
-    using BT = typename PackedB<kForm>::T;
-    constexpr int kNJ = kPacked ? 4 * kQW : 1;
-    constexpr int kNSP = kPacked ? kNS : 1;
-    constexpr int kEarly = (kQW == 1 || kForm == kFP8S) ? kNSP : 1;
-    BT bq[kNSP][kNJ];
-    BT bql[kNSP][kNJ];
-    // Plan-ordered planes hold Cp = C rounded up to 16 channels, so a
-    // 16-channel tile is read whole; a tile past Cp reads the last tile
-    // instead (a uniform clamp: its products only reach channels >= C, which
-    // are not stored).
-    auto load_b = [&](int ks) {
-      const int64_t Cp = (C + 15) & ~int64_t(15);
-      const int64_t at = (int64_t)s_row[4 * ks + (lane >> 4)] * Cp + (lane & 15);
-      const BT* hi = (const BT*)a.spec + at;
-      const BT* lo = (const BT*)a.spec_lo + at;
-#pragma unroll
-      for (int j = 0; j < kNJ; ++j) {
-        const int64_t cj = min<int64_t>(c_w + 16 * j, Cp - 16);
-        bq[ks][j] = hi[cj];
-        if (is_split(kForm)) bql[ks][j] = lo[cj];
-      }
-    };
-    if constexpr (kPacked) {
-#pragma unroll
-      for (int ks = 0; ks < kEarly; ++ks) load_b(ks);
-    }
-    // input-order 16-bit and FP8 spectra: the first k-step's raw row pieces
-    // are loaded before the weights as well (repacked where they are used)
-    constexpr bool kEarlyRaw = !kPacked && kVec && (kForm == kBF16 || kForm == kF16S ||
-                                                    kForm == kFP8S);
-    uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
-    uint32_t e8[(kEarlyRaw && is_fp8(kForm)) ? kQW : 1][8];
-    if constexpr (kEarlyRaw) {
-#pragma unroll
-      for (int h = 0; h < kQW; ++h) {
-        const int64_t ch = my_ch + 64 * h;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int64_t row = s_row[8 * (lane >> 4) + t];
-          if constexpr (is_fp8(kForm)) {
-            const uint8_t* src = (const uint8_t*)a.spec + row * C + ch;
-            e8[h][t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
-          } else {
-            const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
-            e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
-          }
-        }
-      }
-    }
-    // FP32: the first kDepth k-steps' rows are loaded before the weights too
-    constexpr int kDepth = kWide ? 4 : 6;
-    floatx4 b[kForm == kF32 ? kDepth : 1][kQW];
-    auto load = [&](int ks, floatx4* dst) {
-      const float* spec = (const float*)a.spec;
-      const int64_t row = s_row[4 * ks + (lane >> 4)];
-#pragma unroll
-      for (int h = 0; h < kQW; ++h) {
-        const int64_t ch = my_ch + 64 * h;
-        const float* src = spec + row * C + ch;
-        if (kVec) {
-          dst[h] = (ch + 3 < C) ? *(const floatx4*)src : floatx4{0.f, 0.f, 0.f, 0.f};
-        } else {
-          dst[h].x = (ch + 0 < C) ? src[0] : 0.f;
-          dst[h].y = (ch + 1 < C) ? src[1] : 0.f;
-          dst[h].z = (ch + 2 < C) ? src[2] : 0.f;
-          dst[h].w = (ch + 3 < C) ? src[3] : 0.f;
-        }
-      }
-    };
-    if constexpr (kForm == kF32) {
-#pragma unroll
-      for (int d = 0; d < kDepth; ++d) load(d, b[d]);
-    }
-
-    // ---- weights of cell block `wave`, in the A-operand layout.  A coarse
-    // test against the block's centre (lane l: candidate l) marks the
-    // fragments (k-steps) that can hold a pair within R; only those are
-    // evaluated exactly.  Unmarked fragments are never multiplied.
-    uint32_t nzbits = 0;
-    {
-      const double4 c = sm.ctr[wave];
-      const double c2c = chord2(CellVec{c.x, c.y, c.z}, s_xyz[lane]);
-      const uint64_t bm = __ballot(c2c <= c.w);
-      const uint32_t lo = (uint32_t)bm, hi = (uint32_t)(bm >> 32);
-      if (kForm == kF32) {
-        uint32_t pm = any_of_nibbles(lo) | (any_of_nibbles(hi) << 8);
-        while (pm) {
-          const int ks = __builtin_ctz(pm);
-          pm &= pm - 1u;
-          const double4 sv = s_xyz[4 * ks + (lane >> 4)];
-          const double c2 = chord2(cell, sv);
-          float wf = 0.f;
-          if (c2 <= a.c2R) wf = weight(c2, sv);
-          wsum += (double)wf;
-          sA32[(wave * kNS + ks) * 64 + lane] = wf;
-          if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
-        }
-      } else {
-        // bit 4 s + j: 8-candidate group j of k-step s
-        const uint32_t gm = any_of_bytes(lo) | (any_of_bytes(hi) << 4);
-        uint32_t pm = ((gm & 15u) ? 1u : 0u) | ((gm >> 4) ? 2u : 0u);
-        const int grp = lane >> 4;
-        while (pm) {
-          const int ks = __builtin_ctz(pm);
-          pm &= pm - 1u;
-          // codes packed as they are made: 16-bit forms two per word, FP8 four
-          uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
-          if ((gm >> (4 * ks + grp)) & 1u) {
-            const int k0 = kK * ks + 8 * grp;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const double4 sv = s_xyz[k0 + t];
-              const double c2 = chord2(cell, sv);
-              uint32_t h = 0u, l = 0u;
-              if (c2 <= a.c2R) {
-                const float wf = weight(c2, sv);
-                h = enc_w<kForm>(wf);
-                double eff = (double)dec_w<kForm>(h);
-                if (kForm == kBF16Split) {
-                  l = f32_to_bf16(wf - dec_w<kForm>(h));
-                  eff += (double)bf16_to_f32(l);
-                } else if (kForm == kFP8Split) {
-                  l = f32_to_e4m3_cvt(wf * kW8Scale - dec_w<kForm>(h));
-                  eff += (double)e4m3_cvt_to_f32(l);
-                }
-                wsum += (double)wf;
-                wtsum += eff;
-              }
-              if (is_fp8(kForm)) {
-                hw[t >> 2] |= h << (8 * (t & 3));
-                if (kForm == kFP8Split) lw[t >> 2] |= l << (8 * (t & 3));
-              } else {
-                hw[t >> 1] |= h << (16 * (t & 1));
-                if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
-              }
-            }
-          }
-          uint32_t any;
-          const int slot = (wave * kNS + ks) * 64 + lane;
-          const int slot_lo = 4 * kNS * 64 + slot;
-          if (is_fp8(kForm)) {
-            sA8[slot] = make_uint2(hw[0], hw[1]);
-            any = hw[0] | hw[1];
-            if (kForm == kFP8Split) {
-              sA8[slot_lo] = make_uint2(lw[0], lw[1]);
-              any |= lw[0] | lw[1];
-            }
-          } else {
-            sA16[slot] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            any = hw[0] | hw[1] | hw[2] | hw[3];
-            if (kForm == kBF16Split) {
-              sA16[slot_lo] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-              any |= lw[0] | lw[1] | lw[2] | lw[3];
-            }
-          }
-          if (__ballot(any != 0u)) nzbits |= 1u << ks;
-        }
-      }
-    }
-    if (lane == 0) s_nz[wave] = nzbits;
-    __syncthreads();
-
-    // ---- contraction over the block
-    const uint32_t nzc[4] = {s_nz[0], s_nz[1], s_nz[2], s_nz[3]};
-    if constexpr (kForm == kF32) {
-#pragma unroll
-      for (int ks = 0; ks < kNS; ++ks) {
-        floatx4 cb_b[kQW];
-        floatx4 cb_m[kMask ? kQW : 1];
-#pragma unroll
-        for (int h = 0; h < kQW; ++h) {
-          cb_b[h] = b[ks % kDepth][h];
-          if constexpr (kMask) {
-            // flags: a non-finite value becomes 0 in the product and 0 in
-            // the channel's weight operand
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const bool fin = (__float_as_uint(cb_b[h][e]) & 0x7F800000u) != 0x7F800000u;
-              cb_m[h][e] = fin ? 1.f : 0.f;
-              cb_b[h][e] = fin ? cb_b[h][e] : 0.f;
-            }
-          }
-        }
-        if (ks + kDepth < kNS) load(ks + kDepth, b[ks % kDepth]);
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          if ((nzc[cb] >> ks) & 1u) {
-            const float av = sA32[(cb * kNS + ks) * 64 + lane];
-#pragma unroll
-            for (int h = 0; h < kQW; ++h) {
-              if (h >= hlive) continue;
-              acc[cb][4 * h + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].x, acc[cb][4 * h + 0], 0, 0, 0);
-              acc[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].y, acc[cb][4 * h + 1], 0, 0, 0);
-              acc[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].z, acc[cb][4 * h + 2], 0, 0, 0);
-              acc[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_b[h].w, acc[cb][4 * h + 3], 0, 0, 0);
-              if constexpr (kMask) {
-                accw[cb][4 * h + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].x, accw[cb][4 * h + 0], 0, 0, 0);
-                accw[cb][4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].y, accw[cb][4 * h + 1], 0, 0, 0);
-                accw[cb][4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].z, accw[cb][4 * h + 2], 0, 0, 0);
-                accw[cb][4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, cb_m[h].w, accw[cb][4 * h + 3], 0, 0, 0);
-              }
-            }
-          }
-        }
-      }
-    } else if constexpr (kPacked) {
-#pragma unroll
-      for (int ks = 0; ks < kNS; ++ks) {
-        // the k-steps not loaded early are loaded once the previous k-step's
-        // products are issued (registers); the scheduler may not merge them
-        __builtin_amdgcn_sched_barrier(0);
-        if (ks >= kEarly) load_b(ks);
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          if (!((nzc[cb] >> ks) & 1u)) continue;
-          if constexpr (is_fp8(kForm)) {
-            const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
-            const long A = (long)(((uint64_t)av.y << 32) | av.x);
-            long Al = 0;
-            if (kForm == kFP8Split) {
-              const uint2 al = sA8[(4 * kNS + cb * kNS + ks) * 64 + lane];
-              Al = (long)(((uint64_t)al.y << 32) | al.x);
-            }
-#pragma unroll
-            for (int j = 0; j < kNJ; ++j) {
-              floatx4& c = acc[cb][j];
-              const long B = (long)(((uint64_t)bq[ks][j].y << 32) | bq[ks][j].x);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
-              if (kForm == kFP8Split) {
-                const long Bl = (long)(((uint64_t)bql[ks][j].y << 32) | bql[ks][j].x);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, Bl, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
-              }
-            }
-          } else {
-            const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
-            uint4 al = make_uint4(0u, 0u, 0u, 0u);
-            if (kForm == kBF16Split) al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
-#pragma unroll
-            for (int j = 0; j < kNJ; ++j) {
-              floatx4& c = acc[cb][j];
-              if (kForm == kF16S) {
-                c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
-                                                          __builtin_bit_cast(halfx8, bq[ks][j]),
-                                                          c, 0, 0, 0);
-              } else {
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                           __builtin_bit_cast(bf16x8, bq[ks][j]),
-                                                           c, 0, 0, 0);
-                if (kForm == kBF16Split) {
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                             __builtin_bit_cast(bf16x8, bql[ks][j]),
-                                                             c, 0, 0, 0);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
-                                                             __builtin_bit_cast(bf16x8, bq[ks][j]),
-                                                             c, 0, 0, 0);
-                }
-              }
-            }
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int ks = 0; ks < kNS; ++ks) {
-        const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
-        if (!((any >> ks) & 1u)) continue;
-        // one 64-channel group at a time: B fragments of 8 candidates (rows)
-        // x 4 channels, then the MFMAs of every non-zero cell block
-#pragma unroll
-        for (int h = 0; h < kQW; ++h) {
-          const int64_t ch = my_ch + 64 * h;
-          uint32_t fb[4][4];   // [q][dword] (16-bit) or [q][0..1] (FP8)
-          uint32_t fbl[4][4];  // low plane (split form)
-          if (is_fp8(kForm)) {
-#pragma unroll
-            for (int plane = 0; plane < (kForm == kFP8Split ? 2 : 1); ++plane) {
-              const uint8_t* spec = (const uint8_t*)(plane ? a.spec_lo : a.spec);
-              uint32_t d[8];
-#pragma unroll
-              for (int t = 0; t < 8; ++t) {
-                const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
-                const uint8_t* src = spec + row * C + ch;
-                if (kEarlyRaw && ks == 0) {
-                  d[t] = e8[kEarlyRaw ? h : 0][t];
-                } else if (kVec) {
-                  d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
-                } else {
-                  d[t] = 0u;
-#pragma unroll
-                  for (int e = 0; e < 4; ++e)
-                    if (ch + e < C) d[t] |= (uint32_t)src[e] << (8 * e);
-                }
-              }
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const uint32_t v0 = ((d[0] >> (8 * q)) & 0xFFu) | (((d[1] >> (8 * q)) & 0xFFu) << 8) |
-                                    (((d[2] >> (8 * q)) & 0xFFu) << 16) |
-                                    (((d[3] >> (8 * q)) & 0xFFu) << 24);
-                const uint32_t v1 = ((d[4] >> (8 * q)) & 0xFFu) | (((d[5] >> (8 * q)) & 0xFFu) << 8) |
-                                    (((d[6] >> (8 * q)) & 0xFFu) << 16) |
-                                    (((d[7] >> (8 * q)) & 0xFFu) << 24);
-                if (plane) {
-                  fbl[q][0] = v0;
-                  fbl[q][1] = v1;
-                } else {
-                  fb[q][0] = v0;
-                  fb[q][1] = v1;
-                }
-              }
-            }
-          } else {
-#pragma unroll
-            for (int plane = 0; plane < (kForm == kBF16Split ? 2 : 1); ++plane) {
-              const uint16_t* spec = (const uint16_t*)(plane ? a.spec_lo : a.spec);
-              uint2 d[8];
-#pragma unroll
-              for (int t = 0; t < 8; ++t) {
-                const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
-                const uint16_t* src = spec + row * C + ch;
-                if (kEarlyRaw && ks == 0 && plane == 0) {
-                  d[t] = e16[kEarlyRaw ? h : 0][t];
-                } else if (kVec) {
-                  d[t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
-                } else {
-                  const uint32_t e0 = (ch + 0 < C) ? src[0] : 0u, e1 = (ch + 1 < C) ? src[1] : 0u;
-                  const uint32_t e2 = (ch + 2 < C) ? src[2] : 0u, e3 = (ch + 3 < C) ? src[3] : 0u;
-                  d[t] = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
-                }
-              }
-#pragma unroll
-              for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                  const uint32_t v = elem16(d[2 * m], q) | (elem16(d[2 * m + 1], q) << 16);
-                  if (plane) fbl[q][m] = v; else fb[q][m] = v;
-                }
-            }
-          }
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb) {
-            if (!((nzc[cb] >> ks) & 1u)) continue;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              floatx4& c = acc[cb][4 * h + q];
-              if (is_fp8(kForm)) {
-                const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
-                const long A = (long)(((uint64_t)av.y << 32) | av.x);
-                const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
-                if (kForm == kFP8Split) {
-                  // W_hi S_lo + W_lo S_hi (the W_lo S_lo term is below the budget)
-                  const uint2 al = sA8[(4 * kNS + cb * kNS + ks) * 64 + lane];
-                  const long Al = (long)(((uint64_t)al.y << 32) | al.x);
-                  const long Bl = (long)(((uint64_t)fbl[q][1] << 32) | fbl[q][0]);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, Bl, c, 0, 0, 0);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
-                }
-              } else {
-                const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
-                const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
-                if (kForm == kF16S) {
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
-                                                            __builtin_bit_cast(halfx8, bv), c, 0, 0, 0);
-                } else {
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                             __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
-                  if (kForm == kBF16Split) {
-                    const uint4 al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
-                    const uint4 bl = make_uint4(fbl[q][0], fbl[q][1], fbl[q][2], fbl[q][3]);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                               __builtin_bit_cast(bf16x8, bl), c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al),
-                                                               __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
-                  }
-                }
-              }
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  // weight sums of cell block `wave`: reduce the four lanes sharing a cell
-  if (kForm == kF32) wtsum = wsum;  // the FP32 form multiplies the weights as they are
-  wsum += __shfl_xor(wsum, 16);
-  wsum += __shfl_xor(wsum, 32);
-  wtsum += __shfl_xor(wtsum, 16);
-  wtsum += __shfl_xor(wtsum, 32);
-  if (lane < 16) {
-    s_Wt[wave * 16 + lane] = wtsum;
-    if (!kMask && a.wmap && slab == 0 && my_x < g.nx && my_y < g.ny)
-      a.wmap[(int64_t)my_y * g.nx + my_x] = (float)wsum;
-  }
-  __syncthreads();
-
-  // A lane's four cells r = 0..3 of a cell block are consecutive in x: one
-  // 16-byte store per channel where rows and the cube allow it (a 4-byte
-  // store costs a whole 32-byte write in HBM), else one store per cell.
-  const float qnan = __builtin_nanf("");
-  const bool st4 = (g.nx % 4 == 0) && (((uintptr_t)a.cube & 15u) == 0);
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    const int y = ty * kTileY + (cb >> 1) * 4 + (lane >> 4);
-    const int x0 = tx * kTileX + (cb & 1) * 4;
-    if (y >= g.ny || x0 >= g.nx) continue;
-    float inv[4];
-    bool has[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double wt = s_Wt[cb * 16 + 4 * (lane >> 4) + r];
-      has[r] = wt != 0.0;
-      inv[r] = has[r] ? (float)(1.0 / wt) : 0.f;
-    }
-    const int64_t row0 = (int64_t)y * g.nx + x0;
-    const bool full = st4 && x0 + 3 < g.nx;
-#pragma unroll
-    for (int h = 0; h < kQW; ++h)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        // accumulator 4 h + q: channel 4 (lane % 16) + 64 h + q, or for the
-        // plan-ordered spectra lane % 16 + 16 (4 h + q)
-        const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15) : my_ch + 64 * h + q;
-        if (ch >= C) continue;
-        const float sc = (kForm == kF16S || is_fp8(kForm)) ? a.scale[ch] : 1.f;
-        float v[4], wc[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if constexpr (kMask) {
-            // the channel's own weight sum (FP32 accumulation of FP32 weights)
-            wc[r] = accw[cb][4 * h + q][r];
-            v[r] = (wc[r] != 0.f) ? acc[cb][4 * h + q][r] / wc[r] : qnan;
-          } else {
-            float t = acc[cb][4 * h + q][r] * inv[r];
-            if (kForm == kF16S || is_fp8(kForm)) t *= sc;
-            v[r] = has[r] ? t : qnan;
-          }
-        }
-        float* dst = a.cube + ch * G + row0;
-        float* wdst = kMask ? a.wcube + ch * G + row0 : nullptr;
-        if (full) {
-          *(floatx4*)dst = floatx4{v[0], v[1], v[2], v[3]};
-          if (kMask && wdst) *(floatx4*)wdst = floatx4{wc[0], wc[1], wc[2], wc[3]};
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (x0 + r < g.nx) {
-              dst[r] = v[r];
-              if (kMask && wdst) wdst[r] = wc[r];
-            }
-        }
-      }
-  }
-}
 
 template <int kForm, int kQW, bool kVec, bool kPacked, bool kWide, bool kGen = false,
           bool kMask = false>
@@ -831,138 +45,6 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
   const int tile = (local & 7) * a.tiles_per_xcd + (local >> 3);
   if (tile >= a.ntiles) return;
   gather_tile<kForm, kQW, kVec, kPacked, kWide, true, kGen, kMask>(a, tile, slab, sm);
-}
-
-// Few channels (C <= 8) for a 256-thread workgroup: one lane per cell, the
-// four waves take every fourth block of 64 candidates and their FP64 partial
-// sums are added at the end.
-__device__ void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& sm) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = tile % a.ntx, ty = tile / a.ntx;
-  const GridGeom& g = a.g;
-  const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
-  const CellVec cell = cell_at(a.cells, g, ix, iy);
-  const uint32_t total =
-      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
-  const int C = (int)a.C;
-  const float* spec = (const float*)a.spec;
-  double4* wxyz = (double4*)sm.Araw + wave * kKB;                      // [4][64]
-  float* wspec = (float*)((double4*)sm.Araw + 4 * kKB) + wave * kKB * 8;  // [4][64][8]
-  double acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-  double wsum = 0.0;
-  uint32_t cur = 0;
-  const uint32_t nblk = (total + kKB - 1) / kKB;
-  for (uint32_t b0 = 0; b0 < nblk; b0 += 4) {
-    const uint32_t blk = b0 + wave;
-    const uint32_t q = blk * kKB + lane;
-    if (blk < nblk && q < total) {
-      const uint32_t pos = cand_pos(q, sm.rng, sm.pre, &cur);
-      wxyz[lane] = a.xyz[pos];
-      const int64_t row = a.perm[pos];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) wspec[lane * 8 + c] = (c < C) ? spec[row * C + c] : 0.f;
-    } else {
-      const double nan = __builtin_nan("");
-      wxyz[lane] = make_double4(nan, nan, nan, nan);
-    }
-    __syncthreads();
-    if (blk < nblk) {
-      const int kmax = (int)min<uint32_t>(kKB, total - blk * kKB);
-      for (int k = 0; k < kmax; ++k) {
-        const double c2 = chord2(cell, wxyz[k]);
-        if (c2 <= a.c2R) {
-          const double w = pair_weight64(c2, a.kern.wscale);
-          wsum += w;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) acc[c] += w * (double)wspec[k * 8 + c];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  double* red = (double*)sm.Araw;  // [9][64]
-  for (int w = 1; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) red[c * 64 + lane] = acc[c];
-      red[8 * 64 + lane] = wsum;
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] += red[c * 64 + lane];
-      wsum += red[8 * 64 + lane];
-    }
-    __syncthreads();
-  }
-  if (wave != 0 || ix >= g.nx || iy >= g.ny) return;
-  const int64_t G = (int64_t)g.nx * g.ny;
-  const int64_t cellidx = (int64_t)iy * g.nx + ix;
-  if (a.wmap) a.wmap[cellidx] = (float)wsum;
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-    if (c < C) a.cube[c * G + cellidx] = (wsum != 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
-}
-
-// Persistent batch kernel (FP32 spectra).  The item space concatenates the
-// fields' (slab, tile) grids in the host's field order; it is cut into eight
-// contiguous segments, one per XCD (the hardware deals workgroups to the XCDs
-// in turn, so workgroup b starts on XCD b % 8).  A workgroup pops items from
-// its own XCD's segment -- neighbouring tiles of one field, sharing candidate
-// rows in that XCD's L2 -- and, once it is empty, from the others.
-// ctl: [0..7] next item of each segment, [8] item count, [9] segment count.
-__device__ __forceinline__ uint32_t batch_seg_begin(uint32_t total, int x) {
-  return (uint32_t)(((uint64_t)total * (uint32_t)x) / kBatchXcds);
-}
-
-__global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
-  const uint32_t total = ctl[8];
-  for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
-}
-
-template <int kQW, bool kWide>
-__global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
-                                                         const BatchSeg* __restrict__ segs,
-                                                         uint32_t* __restrict__ ctl) {
-  __shared__ GatherSmem sm;
-  __shared__ uint32_t s_item;
-  const uint32_t total = ctl[8];
-  const uint32_t nseg = ctl[9];
-  const int home = (int)(blockIdx.x % kBatchXcds);
-  int k = 0;  // segments visited so far (thread 0 only)
-  for (;;) {
-    if (threadIdx.x == 0) {
-      uint32_t it = 0xFFFFFFFFu;
-      while (k < kBatchXcds) {
-        const int x = (home + k) % kBatchXcds;
-        const uint32_t i = atomicAdd(&ctl[x], 1u);
-        if (i < batch_seg_begin(total, x + 1)) { it = i; break; }
-        ++k;
-      }
-      s_item = it;
-    }
-    __syncthreads();
-    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (it == 0xFFFFFFFFu) break;
-    // the last segment whose base is <= it
-    uint32_t lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
-    }
-    const BatchSeg sg = segs[lo];
-    const uint32_t local = it - sg.base;
-    const uint32_t slab = local / sg.ntiles;
-    const uint32_t tile = local - slab * sg.ntiles;
-    const GatherArgs& a = fields[sg.field];  // read on demand (scalar loads)
-    if (a.C <= 8) gather_cells_tile_wg(a, (int)tile, sm);
-    else if (a.vec) gather_tile<kF32, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
-    else gather_tile<kF32, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);  // 256-channel slabs
-    __syncthreads();
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1292,53 +374,6 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   }
 #undef HCG_MFMA
   HCG_LAUNCH_CHECK("k_gather_mfma");
-  return HCG_OK;
-}
-
-GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
-                         float* wmap) {
-  GatherArgs a;
-  memset(&a, 0, sizeof(a));  // padding bytes too: the batch compares tables bytewise
-  a.cells = p->cells;
-  a.kern = p->kern;
-  a.xyz = p->xyz;
-  a.sentinel = (uint32_t)p->n;
-  a.perm = p->perm;
-  a.ranges = p->ranges;
-  a.nranges = p->nranges;
-  a.maxr = p->maxr;
-  a.spec = spec;
-  a.spec_lo = nullptr;
-  a.scale = nullptr;
-  a.C = C;
-  a.g = p->grid;
-  a.ntx = p->ntx;
-  a.ntiles = p->ntx * p->nty;
-  a.tiles_per_xcd = (a.ntiles + 7) / 8;
-  a.vec = (C % 4 == 0 && (uintptr_t)spec % 16 == 0) ? 1 : 0;
-  a.c2R = support_chord2(p);
-  a.cube = cube;
-  a.wmap = wmap;
-  return a;
-}
-
-hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream) {
-  k_batch_reset<<<1, 1, 0, stream>>>(ctl);
-  HCG_LAUNCH_CHECK("k_batch_reset");
-  return HCG_OK;
-}
-
-hcg_status launch_batch(int qw, bool wide, const GatherArgs* fields, const BatchSeg* segs,
-                        uint32_t* ctl, int nblocks, hipStream_t stream) {
-  if (qw == 2 && wide)
-    k_gather_batch<2, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  else if (qw == 2)
-    k_gather_batch<2, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  else if (wide)
-    k_gather_batch<1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  else
-    k_gather_batch<1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  HCG_LAUNCH_CHECK("k_gather_batch");
   return HCG_OK;
 }
 

@@ -260,14 +260,6 @@ struct BatchSeg {
 };
 constexpr int kBatchXcds = 8;
 constexpr int kBatchCtl = 16;
-GatherArgs make_f32_args(const hcg_plan_s* p, const float* spec, int64_t C, float* cube,
-                         float* wmap);
-hcg_status launch_batch_reset(uint32_t* ctl, hipStream_t stream);
-// wide: some field's support has a squared chord >= 1e-4 (radius >= 0.57
-// deg), so the kernel must carry the long series and the arcsine branch of
-// the distance.
-hcg_status launch_batch(int qw, bool wide, const GatherArgs* fields, const BatchSeg* segs,
-                        uint32_t* ctl, int nblocks, hipStream_t stream);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
                              uint32_t* perm_out, void* temp, hipStream_t stream);
 

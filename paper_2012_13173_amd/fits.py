@@ -9,7 +9,10 @@ plate carree projection (CAR) with the reference point on the equator
 (Calabretta & Greisen 2002, the WCS reference the paper gives in Section 2.1):
 CRVAL = (lon0, 0), CDELT = (dlon, dlat) and the reference pixel placed so that
 pixel (ix + 1, iy + 1) is the cell centre lon0 + (ix - (nx-1)/2) dlon,
-lat0 + (iy - (ny-1)/2) dlat.  The third axis is the channel index.
+lat0 + (iy - (ny-1)/2) dlat.  A projected map (``Projection``: CAR, SFL, SIN
+or TAN with CRPIX, CDELT, CRVAL and optionally LONPOLE / LATPOLE, the target
+that ``hcg_wcs_centres`` and ``hcg_plan_ex`` grid onto) is written with its
+own cards.  The third axis is the channel index.
 
 Layout follows the FITS standard 4.0: 80-character ASCII cards in 2880-byte
 header blocks ending with END, data padded to a multiple of 2880 bytes.
@@ -72,11 +75,42 @@ def grid_wcs(grid, ctype=("RA", "DEC")):
     ]
 
 
+class Projection:
+    """A projected map: ``proj`` in CAR, SFL, SIN, TAN; FITS reference pixel
+    ``crpix`` (1-based), ``cdelt`` and ``crval`` in degrees; ``lonpole`` None
+    for its default."""
+
+    def __init__(self, proj, nx, ny, crpix, cdelt, crval, lonpole=None, latpole=90.0):
+        if proj.upper() not in ("CAR", "SFL", "SIN", "TAN"):
+            raise ValueError(f"projection {proj} is not one of CAR, SFL, SIN, TAN")
+        self.proj, self.nx, self.ny = proj.upper(), int(nx), int(ny)
+        self.crpix = (float(crpix[0]), float(crpix[1]))
+        self.cdelt = (float(cdelt[0]), float(cdelt[1]))
+        self.crval = (float(crval[0]), float(crval[1]))
+        self.lonpole = None if lonpole is None else float(lonpole)
+        self.latpole = float(latpole)
+
+
+def projection_wcs(pr: Projection, ctype=("RA", "DEC")):
+    """WCS cards of a projected map."""
+    cards = []
+    for ax in (0, 1):
+        k = str(ax + 1)
+        cards += [_card("CTYPE" + k, ctype[ax].ljust(4, "-") + "-" + pr.proj),
+                  _card("CRPIX" + k, pr.crpix[ax]), _card("CRVAL" + k, pr.crval[ax]),
+                  _card("CDELT" + k, pr.cdelt[ax]), _card("CUNIT" + k, "deg")]
+    if pr.lonpole is not None:
+        cards.append(_card("LONPOLE", pr.lonpole))
+    cards.append(_card("LATPOLE", pr.latpole))
+    return cards
+
+
 def write_cube(path: str, cube, grid, weights=None, bunit: str = "",
                fwhm_deg: float | None = None) -> None:
     """Writes the cube [C][ny][nx] (float32; NaN where W = 0) and optionally W
-    [ny][nx] to ``path``.  ``cube`` and ``weights`` may be numpy arrays or CPU
-    torch tensors."""
+    [ny][nx] to ``path``.  ``grid`` is the linear grid or a ``Projection``.
+    ``cube`` and ``weights`` may be numpy arrays or CPU torch tensors."""
+    wcs_cards = projection_wcs if isinstance(grid, Projection) else grid_wcs
     cube = np.asarray(cube, dtype=np.float32)
     if cube.ndim != 3 or cube.shape[1:] != (grid.ny, grid.nx):
         raise ValueError(f"cube must be [C, {grid.ny}, {grid.nx}]")
@@ -89,7 +123,7 @@ def write_cube(path: str, cube, grid, weights=None, bunit: str = "",
     cards = [_card("SIMPLE", True, "conforms to FITS standard"), _card("BITPIX", -32),
              _card("NAXIS", 3), _card("NAXIS1", grid.nx), _card("NAXIS2", grid.ny),
              _card("NAXIS3", C), _card("EXTEND", weights is not None)]
-    cards += grid_wcs(grid)
+    cards += wcs_cards(grid)
     cards += [_card("CTYPE3", "CHANNEL"), _card("CRPIX3", 1.0), _card("CRVAL3", 0.0),
               _card("CDELT3", 1.0)]
     if bunit:
@@ -103,6 +137,6 @@ def write_cube(path: str, cube, grid, weights=None, bunit: str = "",
             ext = [_card("XTENSION", "IMAGE", "image extension"), _card("BITPIX", -32),
                    _card("NAXIS", 2), _card("NAXIS1", grid.nx), _card("NAXIS2", grid.ny),
                    _card("PCOUNT", 0), _card("GCOUNT", 1), _card("EXTNAME", "WEIGHTS")]
-            ext += grid_wcs(grid)
+            ext += wcs_cards(grid)
             f.write(_header(ext))
             f.write(_data(w))

@@ -82,3 +82,27 @@ def test_shape_errors(tmp_path):
     with pytest.raises(ValueError):
         fits.write_cube(str(tmp_path / "b.fits"), np.zeros((2, 3, 4), np.float32), g,
                         np.zeros((4, 3), np.float32))
+
+
+@pytest.mark.parametrize("proj,crval,lonpole", [("SIN", (120.0, 62.0), None),
+                                                ("TAN", (10.0, -80.0), None),
+                                                ("SFL", (359.9, -35.0), None),
+                                                ("CAR", (200.0, 40.0), 0.0)])
+def test_projected_map_cards(tmp_path, proj, crval, lonpole):
+    pr = fits.Projection(proj, 21, 17, (11.0, 9.5), (-0.01, 0.01), crval, lonpole=lonpole)
+    cube = np.zeros((2, 17, 21), np.float32)
+    path = str(tmp_path / "p.fits")
+    fits.write_cube(path, cube, pr, np.ones((17, 21), np.float32))
+    for h, _ in read_fits(path):
+        assert h["CTYPE1"] == "RA---" + proj and h["CTYPE2"] == "DEC--" + proj
+        assert (h["CRPIX1"], h["CRPIX2"]) == pr.crpix and (h["CDELT1"], h["CDELT2"]) == pr.cdelt
+        assert (h["CRVAL1"], h["CRVAL2"]) == pr.crval and h["LATPOLE"] == 90.0
+        assert h.get("LONPOLE") == lonpole
+        # the cards give back the map's pixel centres through the WCS oracle
+        a = wcs.cell_centres(proj, 21, 17, (h["CRPIX1"], h["CRPIX2"]), (h["CDELT1"], h["CDELT2"]),
+                             (h["CRVAL1"], h["CRVAL2"]), h.get("LONPOLE"), h["LATPOLE"])
+        b = wcs.cell_centres(proj, 21, 17, pr.crpix, pr.cdelt, pr.crval, lonpole, 90.0)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+    with pytest.raises(ValueError):
+        fits.Projection("AIT", 4, 4, (1, 1), (1, 1), (0, 0))

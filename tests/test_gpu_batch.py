@@ -150,3 +150,68 @@ def test_batch_errors():
     b.destroy()
     assert lib.hcg_destroy_batch(handle) == hcg.HCG_E_STATE
     assert lib.hcg_destroy_batch(None) == hcg.HCG_OK
+
+
+# (dtype, budget against the oracle) of the mixed-form batch
+_MIXED = [(hcg.HCG_F32, 1e-5), (hcg.HCG_F16_SCALED, 1e-3), (hcg.HCG_BF16_SPLIT, 5e-5),
+          (hcg.HCG_FP8E4M3_SPLIT, 1e-2), (hcg.HCG_BF16, 1e-2), (hcg.HCG_FP8E4M3_SCALED, 1e-1),
+          (hcg.HCG_F32, 1e-5), (hcg.HCG_F16_SCALED, 1e-3)]
+
+
+def test_mixed_form_batch_matches_oracle_and_single_calls():
+    """Fields in every storage form in one batch: each matches the oracle at
+    its form's budget and the single hcg_grid call of that form; replays
+    after changed data agree."""
+    ws = _fields()
+    ws.append(synth.small_cube(n=6000, nchan=20, nx=14, ny=12, seed=208, name="c20"))
+    forms = [d for d, _ in _MIXED]
+    # the few-channel fields stay FP32 (their own kernel class)
+    forms = [hcg.HCG_F32 if w.nchan <= 8 else f for w, f in zip(ws, forms)]
+    tols = {d: t for d, t in _MIXED}
+    spectra, scales = [], []
+    for w, f in zip(ws, forms):
+        s = w.spectra.to(DEV).contiguous()
+        if f == hcg.HCG_F32:
+            spectra.append(s)
+            scales.append(None)
+        else:
+            enc, sc = hcg.hcg_quantize(s, f)
+            spectra.append(enc)
+            scales.append(sc)
+    b = _plan(ws)
+    cubes, wts = _outputs(ws)
+    hcg.hcg_grid_batch(b, spectra, cubes, wts, dtypes=forms, chan_scales=scales)
+    torch.cuda.synchronize()
+    assert b.info()["graph_captured"] == 1
+    for w, f, sp, sc, cube, W in zip(ws, forms, spectra, scales, cubes, wts):
+        V = cube.cpu().numpy()
+        Vr, Wr, _ = run_oracle(w)
+        assert_cube_close(V, Vr, tols[f], f"{w.name} dtype {f}")
+        assert_weights_close(W.cpu().numpy(), Wr)
+        plan = hcg.hcg_plan(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+        single = torch.empty_like(cube)
+        hcg.hcg_grid(plan, sp, single, dtype=f, chan_scale=sc)
+        torch.cuda.synchronize()
+        plan.destroy()
+        np.testing.assert_allclose(V, single.cpu().numpy(), rtol=1e-6, atol=1e-6,
+                                   err_msg=f"{w.name} dtype {f}")
+    # a replay on changed data (every field scaled by 2 in its own storage)
+    ref = [c.clone() for c in cubes]
+    for sp in spectra:
+        if sp.dtype == torch.uint8:
+            continue  # FP8 codes: scaled through chan_scale below instead
+        sp.mul_(2.0)
+    scales2 = [None if sc is None else (sc * 2.0 if sp.dtype == torch.uint8 else sc)
+               for sc, sp in zip(scales, spectra)]
+    hcg.hcg_grid_batch(b, spectra, cubes, wts, dtypes=forms, chan_scales=scales2)
+    torch.cuda.synchronize()
+    for c, r, w in zip(cubes, ref, ws):
+        torch.testing.assert_close(c, 2.0 * r, rtol=1e-6, atol=1e-6, equal_nan=True, msg=w.name)
+    # a missing scale is refused
+    bad = list(scales2)
+    k = next(i for i, f in enumerate(forms) if f in (hcg.HCG_F16_SCALED, hcg.HCG_FP8E4M3_SCALED,
+                                                    hcg.HCG_FP8E4M3_SPLIT))
+    bad[k] = None
+    with pytest.raises(hcg.HcgError):
+        hcg.hcg_grid_batch(b, spectra, cubes, wts, dtypes=forms, chan_scales=bad)
+    b.destroy()
