@@ -263,6 +263,29 @@ hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan, hcg_dty
                     const float* chan_scale, float* cube, float* weights, void* hip_stream);
 
 /*
+ * hcg_grid_noalloc -- hcg_grid for callers that cannot allocate device
+ * memory during the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels, results and
+ * errors as hcg_grid; it calls no hipMalloc, hipFree or allocating library
+ * routine.  Where hcg_grid takes stream-ordered memory for partial sums (the
+ * FP32 form with nchan <= 8 on maps of fewer than 1024 8 x 8 tiles), this call
+ * uses a static device array of HCG_NOALLOC_SCRATCH_BYTES per device, held by
+ * each device the library runs on until the process ends (every such map
+ * fits: it needs at most about 14 MB); a map that would need more is refused
+ * with HCG_E_UNSUPPORTED.  The partial sums are written whole before they are
+ * read, so nothing carries over from an earlier call.  All calls on one
+ * device share that array: calls of hcg_grid_noalloc that overlap on one
+ * device (on different streams, or from different host threads without
+ * ordering) race and give wrong maps; calls on one stream are ordered and
+ * safe.  The first call on a device looks up the array's device address
+ * once (hipGetSymbolAddress, with that device current).
+ */
+#define HCG_NOALLOC_SCRATCH_BYTES (16u << 20)
+hcg_status hcg_grid_noalloc(hcg_plan_t plan, const void* spectra, int64_t nchan,
+                            hcg_dtype dtype, const float* chan_scale, float* cube,
+                            float* weights, void* hip_stream);
+
+/*
  * hcg_grid_masked -- Eq. (1) with per-channel flags, for data whose flagged
  * values (RFI, Section 4) are non-finite: a NaN or infinite s_n[c] leaves
  * sample n out of channel c, from the numerator and from that channel's

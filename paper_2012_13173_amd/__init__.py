@@ -109,7 +109,7 @@ EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_pl
             "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
             "hcg_destroy_batch", "hcg_get_batch_info", "hcg_quantize_packed", "hcg_grid_packed",
             "hcg_packed_bytes", "hcg_grid_host", "hcg_grid_rowthreads", "hcg_plan_ex",
-            "hcg_grid_masked", "hcg_wcs_centres"]
+            "hcg_grid_masked", "hcg_wcs_centres", "hcg_grid_noalloc"]
 
 _lib = None
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.hcg_plan.argtypes = [ctypes.POINTER(vp), vp, vp, i64, ctypes.POINTER(GridDescC), f64, f64,
                              ctypes.POINTER(OptsC), vp]
     lib.hcg_grid.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    lib.hcg_grid_noalloc.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
     lib.hcg_plan_ex.argtypes = [ctypes.POINTER(vp), vp, vp, i64, ctypes.POINTER(GridDescC),
                                 ctypes.POINTER(CellCentresC), ctypes.POINTER(KernelC), f64,
                                 ctypes.POINTER(OptsC), vp]
@@ -350,6 +351,18 @@ def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None
              dtype: int = HCG_F32, chan_scale=None, stream=None) -> None:
     """Grids ``spectra`` ([n, C], or [2, n, C] for the split forms) into
     ``cube`` [C, ny, nx] (and ``weights`` [ny, nx])."""
+    _grid_call("hcg_grid", plan, spectra, cube, weights, dtype, chan_scale, stream)
+
+
+def hcg_grid_noalloc(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None,
+                     dtype: int = HCG_F32, chan_scale=None, stream=None) -> None:
+    """``hcg_grid`` through the entry point that allocates no device memory
+    (its scratch is a static device array shared by every call on a device:
+    calls that overlap on one device race)."""
+    _grid_call("hcg_grid_noalloc", plan, spectra, cube, weights, dtype, chan_scale, stream)
+
+
+def _grid_call(name, plan, spectra, cube, weights, dtype, chan_scale, stream):
     sdt, prefix = _FORM_STORAGE[dtype]
     if spectra.dim() != 2 + len(prefix) or tuple(spectra.shape[:len(prefix)]) != prefix:
         raise ValueError(f"spectra must be [{', '.join(map(str, prefix + ('n', 'nchan')))}]")
@@ -362,11 +375,11 @@ def hcg_grid(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None
     if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
         raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
     sp = _dptr(spectra, sdt, "spectra")
-    st = load().hcg_grid(plan.handle, sp, C, int(dtype),
-                         _dptr(chan_scale, torch.float32, "chan_scale"),
-                         _dptr(cube, torch.float32, "cube"),
-                         _dptr(weights, torch.float32, "weights"), _stream(stream))
-    _check(st, "hcg_grid")
+    st = getattr(load(), name)(plan.handle, sp, C, int(dtype),
+                               _dptr(chan_scale, torch.float32, "chan_scale"),
+                               _dptr(cube, torch.float32, "cube"),
+                               _dptr(weights, torch.float32, "weights"), _stream(stream))
+    _check(st, name)
 
 
 def _hptr(t, name):

@@ -26,6 +26,7 @@
 //      times the channel scale for the scaled forms), NaN where no sample is
 //      within the support; W map = FP64 sum of the unrounded weights.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "gather_tile.h"
@@ -381,26 +382,82 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
 
 using namespace hcg;
 
-extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan,
-                               hcg_dtype dtype, const float* chan_scale, float* cube,
-                               float* weights, void* hip_stream) {
-  if (!plan) return fail(HCG_E_ARG, "hcg_grid: plan is NULL");
-  if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid: not a live plan");
-  if (!spectra || !cube) return fail(HCG_E_ARG, "hcg_grid: spectra and cube must not be NULL");
-  if (nchan < 1) return fail(HCG_E_ARG, "hcg_grid: nchan must be >= 1");
+namespace hcg {
+
+// Scratch of the entry point that allocates nothing: the FP64 partial sums of
+// the few-channel gather's split candidate lists live in this array, one copy
+// per device for the life of the process.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it passes the device address that hipGetSymbolAddress returns on
+// each device, looked up once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = HCG_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array.
+static hcg_status scratch_address(void** out, const char* where) {
+  int dev = -1;
+  const hipError_t ge = hipGetDevice(&dev);
+  if (ge != hipSuccess) return fail(HCG_E_DEVICE, "%s: hipGetDevice failed: %s", where, hipGetErrorString(ge));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(HCG_E_UNSUPPORTED, "%s: device %d is beyond the %d devices served", where, dev,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HCG_E_DEVICE, "%s: hipGetSymbolAddress of the scratch array failed: %s", where,
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return HCG_OK;
+}
+
+// hcg_grid and hcg_grid_noalloc: the same kernels; with noalloc the
+// few-channel gather's partial sums go to the static scratch array instead of
+// stream-ordered memory.
+static hcg_status grid_dispatch(const char* where, hcg_plan_t plan, const void* spectra,
+                                int64_t nchan, hcg_dtype dtype, const float* chan_scale,
+                                float* cube, float* weights, void* hip_stream, bool noalloc) {
+  if (!plan) return fail(HCG_E_ARG, "%s: plan is NULL", where);
+  if (!plan_is_live(plan)) return fail(HCG_E_STATE, "%s: not a live plan", where);
+  if (!spectra || !cube) return fail(HCG_E_ARG, "%s: spectra and cube must not be NULL", where);
+  if (nchan < 1) return fail(HCG_E_ARG, "%s: nchan must be >= 1", where);
   const bool scaled = (dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED ||
                        dtype == HCG_FP8E4M3_SPLIT);
   if (dtype < HCG_F32 || dtype > HCG_FP8E4M3_SPLIT)
-    return fail(HCG_E_UNSUPPORTED, "hcg_grid: unknown dtype %d", (int)dtype);
-  if (scaled && !chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale is required for this dtype");
-  if (!scaled && chan_scale) return fail(HCG_E_ARG, "hcg_grid: chan_scale must be NULL for this dtype");
+    return fail(HCG_E_UNSUPPORTED, "%s: unknown dtype %d", where, (int)dtype);
+  if (scaled && !chan_scale) return fail(HCG_E_ARG, "%s: chan_scale is required for this dtype", where);
+  if (!scaled && chan_scale) return fail(HCG_E_ARG, "%s: chan_scale must be NULL for this dtype", where);
   const hcg_plan_s* p = plan;
   hipStream_t stream = (hipStream_t)hip_stream;
   switch (dtype) {
     case HCG_F32:
-      if (nchan <= 8)
+      if (nchan <= 8) {
+        double* part = nullptr;
+        if (noalloc) {
+          const unsigned ntiles = (unsigned)(p->ntx * p->nty);
+          const int cm = (nchan == 1) ? 1 : (nchan == 2) ? 2 : (nchan <= 4) ? 4 : 8;
+          const size_t need = cells_part_bytes(cells_split(ntiles), cm, false, ntiles);
+          if (need > kNoAllocScratchBytes)
+            return fail(HCG_E_UNSUPPORTED,
+                        "%s: the partial sums of this map need %zu bytes of scratch, more than "
+                        "the %zu the library holds", where, need, kNoAllocScratchBytes);
+          if (need > 0) {
+            void* s = nullptr;
+            const hcg_status st = scratch_address(&s, where);
+            if (st != HCG_OK) return st;
+            part = (double*)s;
+          }
+        }
         return launch_cells(p, (const float*)spectra, (int)nchan, cube, weights, nullptr, false,
-                            nullptr, stream);
+                            part, stream);
+      }
       return launch_mfma<kF32>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
     case HCG_BF16:
       return launch_mfma<kBF16>(p, spectra, nullptr, nullptr, nchan, cube, weights, stream);
@@ -416,7 +473,23 @@ extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nch
       return launch_mfma<kFP8Split>(p, spectra, (const char*)spectra + (size_t)p->n * nchan,
                                     chan_scale, nchan, cube, weights, stream);
   }
-  return fail(HCG_E_UNSUPPORTED, "hcg_grid: dtype %d", (int)dtype);
+  return fail(HCG_E_UNSUPPORTED, "%s: dtype %d", where, (int)dtype);
+}
+
+}  // namespace hcg
+
+extern "C" hcg_status hcg_grid(hcg_plan_t plan, const void* spectra, int64_t nchan,
+                               hcg_dtype dtype, const float* chan_scale, float* cube,
+                               float* weights, void* hip_stream) {
+  return grid_dispatch("hcg_grid", plan, spectra, nchan, dtype, chan_scale, cube, weights,
+                       hip_stream, false);
+}
+
+extern "C" hcg_status hcg_grid_noalloc(hcg_plan_t plan, const void* spectra, int64_t nchan,
+                                       hcg_dtype dtype, const float* chan_scale, float* cube,
+                                       float* weights, void* hip_stream) {
+  return grid_dispatch("hcg_grid_noalloc", plan, spectra, nchan, dtype, chan_scale, cube,
+                       weights, hip_stream, true);
 }
 
 extern "C" hcg_status hcg_grid_masked(hcg_plan_t plan, const float* spectra, int64_t nchan,
