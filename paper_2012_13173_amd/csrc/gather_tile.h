@@ -195,11 +195,11 @@ __device__ __forceinline__ uint32_t elem16(uint2 d, int q) {
 struct GatherSmem {
   uint2 rng[kMaxRangesLimit];
   uint32_t pre[kMaxRangesLimit + 1];
-  double4 xyz[kKB];
-  double4 ctr[4];  // cell-block centres and coarse thresholds
-  uint32_t row[kKB];
-  uint4 Araw[1024];
-  uint32_t nz[4];
+  double4 xyz[3][kKB];  // staged unit vectors, three blocks in flight
+  double4 ctr[4];       // cell-block centres and coarse thresholds
+  uint32_t row[3][kKB];
+  uint4 Araw[2][1024];  // weights in the A-operand layout, two blocks in flight
+  uint32_t nz[2][4];
   double Wt[kTileCells];
 };
 
@@ -237,10 +237,6 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   constexpr int kNS = kKB / kK;  // k-steps per staged block
   uint2* s_rng = sm.rng;
   uint32_t* s_pre = sm.pre;
-  double4* s_xyz = sm.xyz;
-  uint32_t* s_row = sm.row;
-  uint4* s_Araw = sm.Araw;
-  uint32_t* s_nz = sm.nz;
   double* s_Wt = sm.Wt;
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -285,14 +281,19 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   // computes its cell block's weights for the others)
   const int hlive = (int)min<int64_t>(kQW, max<int64_t>(0, (C - c_w + 63) / 64));
 
-  float* sA32 = (float*)s_Araw;                // [4][16][64]
-  uint4* sA16 = s_Araw;                        // [4][kNS][64] (+ lo plane after)
-  uint2* sA8 = (uint2*)s_Araw;                 // [4][kNS][64]
+  // Weights in the A-operand layout, one buffer per block in flight.
+  auto sA32 = [&](int ab) { return (float*)sm.Araw[ab]; };   // [4][16][64]
+  auto sA16 = [&](int ab) { return sm.Araw[ab]; };           // [4][kNS][64] (+ lo plane after)
+  auto sA8 = [&](int ab) { return (uint2*)sm.Araw[ab]; };    // [4][kNS][64] (+ lo plane after)
 
-  // Candidate staging runs one block ahead (kAhead): wave 0 loads the next
-  // block's unit vectors and rows (or groups) into registers while the
-  // current block is processed, and stores them to LDS at the top of the next
-  // iteration.  Without kAhead (fewer registers) it loads them there.
+  // Blocks of 64 candidates go through a three-stage pipeline with one
+  // barrier per block: while block b's rows are read and multiplied, each
+  // wave computes its cell block's weights of block b + 1 (from the unit
+  // vectors staged one block earlier), and wave 0 stages block b + 2, whose
+  // unit vectors and rows (or groups) it loaded into registers during the
+  // previous block (kAhead; without it, where registers are short, it loads
+  // them when it stages them).  LDS holds three staging buffers and two
+  // weight buffers.
   double nx = 0.0, ny = 0.0, nz = 0.0;
   uint32_t nrow = 0u;
   // Padding past the last candidate has weight 0 (a NaN position) and the
@@ -308,7 +309,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   }
   pad_row = __builtin_amdgcn_readfirstlane(pad_row);
   auto fetch = [&](uint32_t qb) {
-    if (tid < kKB) {
+    if (wave == 0) {
       const uint32_t q = qb + tid;
       if (q < total) {
         const uint32_t pos = cand_pos(q, s_rng, s_pre, &cur);
@@ -323,192 +324,246 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       }
     }
   };
-  if (kAhead) fetch(0);
-  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
-    if (!kAhead) fetch(q0);
-    if (tid < kKB) {
-      s_xyz[tid] = make_double4(nx, ny, nz, 0.0);
-      if (!kPacked) s_row[tid] = nrow;
-      else if ((tid & 7) == 0) s_row[tid >> 3] = nrow;
+  auto stage = [&](int buf) {
+    if (wave == 0) {
+      sm.xyz[buf][tid] = make_double4(nx, ny, nz, 0.0);
+      if (!kPacked) sm.row[buf][tid] = nrow;
+      else if ((tid & 7) == 0) sm.row[buf][tid >> 3] = nrow;
     }
-    __syncthreads();
-    if (kAhead && q0 + kKB < total) fetch(q0 + kKB);
+  };
 
-    // plan-ordered spectra: issue the block's B loads now (the first k-step
-    // only where registers are short), so that they are in flight while the
-    // weights are computed
-    using BT = typename PackedB<kForm>::T;
-    constexpr int kNJ = kPacked ? 4 * kQW : 1;
-    constexpr int kNSP = kPacked ? kNS : 1;
-    constexpr int kEarly = (kQW == 1 || kForm == kFP8S) ? kNSP : 1;
-    BT bq[kNSP][kNJ];
-    BT bql[kNSP][kNJ];
-    // Plan-ordered planes hold Cp = C rounded up to 16 channels, so a
-    // 16-channel tile is read whole; a tile past Cp reads the last tile
-    // instead (a uniform clamp: its products only reach channels >= C, which
-    // are not stored).
-    auto load_b = [&](int ks) {
-      const int64_t Cp = (C + 15) & ~int64_t(15);
-      const int64_t at = (int64_t)s_row[4 * ks + (lane >> 4)] * Cp + (lane & 15);
-      const BT* hi = (const BT*)a.spec + at;
-      const BT* lo = (const BT*)a.spec_lo + at;
-#pragma unroll
-      for (int j = 0; j < kNJ; ++j) {
-        const int64_t cj = min<int64_t>(c_w + 16 * j, Cp - 16);
-        bq[ks][j] = hi[cj];
-        if (is_split(kForm)) bql[ks][j] = lo[cj];
+  // ---- weights of cell block `wave` for the block staged in `buf`, into
+  // weight buffer `ab`.  A coarse test against the block's centre (lane l:
+  // candidate l) marks the fragments (k-steps) that can hold a pair within
+  // R; only those are evaluated exactly.  Unmarked fragments are never
+  // multiplied.
+  auto weights = [&](int buf, int ab) {
+    const double4* s_xyz = sm.xyz[buf];
+    uint32_t nzbits = 0;
+    const double4 c = sm.ctr[wave];
+    const double c2c = chord2(CellVec{c.x, c.y, c.z}, s_xyz[lane]);
+    const uint64_t bm = __ballot(c2c <= c.w);
+    const uint32_t lo = (uint32_t)bm, hi = (uint32_t)(bm >> 32);
+    if (kForm == kF32) {
+      float* A = sA32(ab);
+      uint32_t pm = any_of_nibbles(lo) | (any_of_nibbles(hi) << 8);
+      while (pm) {
+        const int ks = __builtin_ctz(pm);
+        pm &= pm - 1u;
+        const double4 sv = s_xyz[4 * ks + (lane >> 4)];
+        const double c2 = chord2(cell, sv);
+        float wf = 0.f;
+        if (c2 <= a.c2R) wf = weight(c2, sv);
+        wsum += (double)wf;
+        A[(wave * kNS + ks) * 64 + lane] = wf;
+        if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
       }
-    };
+    } else {
+      uint4* A16 = sA16(ab);
+      uint2* A8 = sA8(ab);
+      // bit 4 s + j: 8-candidate group j of k-step s
+      const uint32_t gm = any_of_bytes(lo) | (any_of_bytes(hi) << 4);
+      uint32_t pm = ((gm & 15u) ? 1u : 0u) | ((gm >> 4) ? 2u : 0u);
+      const int grp = lane >> 4;
+      while (pm) {
+        const int ks = __builtin_ctz(pm);
+        pm &= pm - 1u;
+        // codes packed as they are made: 16-bit forms two per word, FP8 four
+        uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+        if ((gm >> (4 * ks + grp)) & 1u) {
+          const int k0 = kK * ks + 8 * grp;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const double4 sv = s_xyz[k0 + t];
+            const double c2 = chord2(cell, sv);
+            uint32_t h = 0u, l = 0u;
+            if (c2 <= a.c2R) {
+              const float wf = weight(c2, sv);
+              h = enc_w<kForm>(wf);
+              double eff = (double)dec_w<kForm>(h);
+              if (kForm == kBF16Split) {
+                l = f32_to_bf16(wf - dec_w<kForm>(h));
+                eff += (double)bf16_to_f32(l);
+              } else if (kForm == kFP8Split) {
+                l = f32_to_e4m3_cvt(wf * kW8Scale - dec_w<kForm>(h));
+                eff += (double)e4m3_cvt_to_f32(l);
+              }
+              wsum += (double)wf;
+              wtsum += eff;
+            }
+            if (is_fp8(kForm)) {
+              hw[t >> 2] |= h << (8 * (t & 3));
+              if (kForm == kFP8Split) lw[t >> 2] |= l << (8 * (t & 3));
+            } else {
+              hw[t >> 1] |= h << (16 * (t & 1));
+              if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
+            }
+          }
+        }
+        uint32_t any;
+        const int slot = (wave * kNS + ks) * 64 + lane;
+        const int slot_lo = 4 * kNS * 64 + slot;
+        if (is_fp8(kForm)) {
+          A8[slot] = make_uint2(hw[0], hw[1]);
+          any = hw[0] | hw[1];
+          if (kForm == kFP8Split) {
+            A8[slot_lo] = make_uint2(lw[0], lw[1]);
+            any |= lw[0] | lw[1];
+          }
+        } else {
+          A16[slot] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+          any = hw[0] | hw[1] | hw[2] | hw[3];
+          if (kForm == kBF16Split) {
+            A16[slot_lo] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            any |= lw[0] | lw[1] | lw[2] | lw[3];
+          }
+        }
+        if (__ballot(any != 0u)) nzbits |= 1u << ks;
+      }
+    }
+    if (lane == 0) sm.nz[ab][wave] = nzbits;
+  };
+
+  // ---- pipeline prologue: blocks 0 and 1 staged, block 2 in flight, the
+  // weights of block 0 computed
+  const uint32_t nblk = (total + kKB - 1) / kKB;
+  if (nblk > 0) {
+    fetch(0);
+    stage(0);
+  }
+  if (nblk > 1) {
+    fetch(kKB);
+    stage(1);
+  }
+  if (kAhead && nblk > 2) fetch(2 * kKB);
+  __syncthreads();
+  if (nblk > 0) weights(0, 0);
+  __syncthreads();
+
+  // B operands: a block's first loads are issued at its top, so that they
+  // are in flight while the next block's weights are computed.  (Carrying
+  // them across the barrier, issued once the previous block's products had
+  // read their registers, measured slower: the registers then stay live
+  // through the weights.)
+  using BT = typename PackedB<kForm>::T;
+  constexpr int kNJ = kPacked ? 4 * kQW : 1;
+  constexpr int kNSP = kPacked ? kNS : 1;
+  // plan-ordered: the k-steps loaded at the block's top (the others, where
+  // registers are short, once the previous k-step's products are issued)
+  constexpr int kEarly = (kQW == 1 || kForm == kFP8S) ? kNSP : 1;
+  BT bq[kNSP][kNJ];
+  BT bql[kNSP][kNJ];
+  // Plan-ordered planes hold Cp = C rounded up to 16 channels, so a
+  // 16-channel tile is read whole; a tile past Cp reads the last tile
+  // instead (a uniform clamp: its products only reach channels >= C, which
+  // are not stored).
+  auto load_b = [&](const uint32_t* rows, int ks) {
+    const int64_t Cp = (C + 15) & ~int64_t(15);
+    const int64_t at = (int64_t)rows[4 * ks + (lane >> 4)] * Cp + (lane & 15);
+    const BT* hi = (const BT*)a.spec + at;
+    const BT* lo = (const BT*)a.spec_lo + at;
+#pragma unroll
+    for (int j = 0; j < kNJ; ++j) {
+      const int64_t cj = min<int64_t>(c_w + 16 * j, Cp - 16);
+      bq[ks][j] = hi[cj];
+      if (is_split(kForm)) bql[ks][j] = lo[cj];
+    }
+  };
+  // input-order 16-bit and FP8 spectra: the first k-step's raw row pieces
+  // are loaded at the block's top as well (repacked where they are used)
+  constexpr bool kEarlyRaw = !kPacked && kVec && (kForm == kBF16 || kForm == kF16S ||
+                                                  kForm == kFP8S);
+  uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
+  uint32_t e8[(kEarlyRaw && is_fp8(kForm)) ? kQW : 1][8];
+  auto load_raw = [&](const uint32_t* rows) {
+#pragma unroll
+    for (int h = 0; h < kQW; ++h) {
+      const int64_t ch = my_ch + 64 * h;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t row = rows[8 * (lane >> 4) + t];
+        if constexpr (is_fp8(kForm)) {
+          // 4-byte pieces: unconditional (clamped) loads measured faster
+          const bool ok = ch + 3 < C;
+          const uint32_t v = *(const uint32_t*)((const uint8_t*)a.spec + row * C + (ok ? ch : 0));
+          e8[h][t] = ok ? v : 0u;
+        } else {
+          const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
+          e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+        }
+      }
+    }
+  };
+  // FP32: a ring of kDepth k-steps' rows in flight.  The row loads are
+  // issued unconditionally (an index past the last channel is clamped into
+  // the row and the value replaced after the load): a load under a divergent
+  // branch makes the compiler wait for every outstanding load before its
+  // value is used, which serialised the ring (66.3 -> 60.5 ms on the
+  // 9.12M x 1024 drift scan with this and the A operands read a k-step ahead).
+  constexpr int kDepth = kWide ? 4 : 6;
+  floatx4 bb[kForm == kF32 ? kDepth : 1][kQW];
+  auto load = [&](const uint32_t* rows, int ks, floatx4* dst) {
+    const float* spec = (const float*)a.spec;
+    const int64_t row = rows[4 * ks + (lane >> 4)];
+#pragma unroll
+    for (int h = 0; h < kQW; ++h) {
+      const int64_t ch = my_ch + 64 * h;
+      const float* rp = spec + row * C;
+      if (kVec) {
+        const bool ok = ch + 3 < C;
+        const floatx4 v = *(const floatx4*)(rp + (ok ? ch : 0));
+        dst[h] = ok ? v : floatx4{0.f, 0.f, 0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = ch + e < C;
+          const float v = rp[ok ? ch + e : 0];
+          dst[h][e] = ok ? v : 0.f;
+        }
+      }
+    }
+  };
+
+  for (uint32_t b = 0; b < nblk; ++b) {
+    const int sb = (int)(b % 3u), ab = (int)(b & 1u);
+    const uint32_t* s_row = sm.row[sb];                 // rows (or groups) of block b
+    const bool more = b + 1 < nblk;
     if constexpr (kPacked) {
 #pragma unroll
-      for (int ks = 0; ks < kEarly; ++ks) load_b(ks);
+      for (int ks = 0; ks < kEarly; ++ks) load_b(s_row, ks);
     }
-    // input-order 16-bit and FP8 spectra: the first k-step's raw row pieces
-    // are loaded before the weights as well (repacked where they are used)
-    constexpr bool kEarlyRaw = !kPacked && kVec && (kForm == kBF16 || kForm == kF16S ||
-                                                    kForm == kFP8S);
-    uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
-    uint32_t e8[(kEarlyRaw && is_fp8(kForm)) ? kQW : 1][8];
-    if constexpr (kEarlyRaw) {
-#pragma unroll
-      for (int h = 0; h < kQW; ++h) {
-        const int64_t ch = my_ch + 64 * h;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int64_t row = s_row[8 * (lane >> 4) + t];
-          if constexpr (is_fp8(kForm)) {
-            const uint8_t* src = (const uint8_t*)a.spec + row * C + ch;
-            e8[h][t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
-          } else {
-            const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
-            e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
-          }
-        }
-      }
-    }
-    // FP32: the first kDepth k-steps' rows are loaded before the weights too
-    constexpr int kDepth = kWide ? 4 : 6;
-    floatx4 b[kForm == kF32 ? kDepth : 1][kQW];
-    auto load = [&](int ks, floatx4* dst) {
-      const float* spec = (const float*)a.spec;
-      const int64_t row = s_row[4 * ks + (lane >> 4)];
-#pragma unroll
-      for (int h = 0; h < kQW; ++h) {
-        const int64_t ch = my_ch + 64 * h;
-        const float* src = spec + row * C + ch;
-        if (kVec) {
-          dst[h] = (ch + 3 < C) ? *(const floatx4*)src : floatx4{0.f, 0.f, 0.f, 0.f};
-        } else {
-          dst[h].x = (ch + 0 < C) ? src[0] : 0.f;
-          dst[h].y = (ch + 1 < C) ? src[1] : 0.f;
-          dst[h].z = (ch + 2 < C) ? src[2] : 0.f;
-          dst[h].w = (ch + 3 < C) ? src[3] : 0.f;
-        }
-      }
-    };
+    if constexpr (kEarlyRaw) load_raw(s_row);
     if constexpr (kForm == kF32) {
 #pragma unroll
-      for (int d = 0; d < kDepth; ++d) load(d, b[d]);
+      for (int d = 0; d < kDepth; ++d) load(s_row, d, bb[d]);
     }
 
-    // ---- weights of cell block `wave`, in the A-operand layout.  A coarse
-    // test against the block's centre (lane l: candidate l) marks the
-    // fragments (k-steps) that can hold a pair within R; only those are
-    // evaluated exactly.  Unmarked fragments are never multiplied.
-    uint32_t nzbits = 0;
-    {
-      const double4 c = sm.ctr[wave];
-      const double c2c = chord2(CellVec{c.x, c.y, c.z}, s_xyz[lane]);
-      const uint64_t bm = __ballot(c2c <= c.w);
-      const uint32_t lo = (uint32_t)bm, hi = (uint32_t)(bm >> 32);
-      if (kForm == kF32) {
-        uint32_t pm = any_of_nibbles(lo) | (any_of_nibbles(hi) << 8);
-        while (pm) {
-          const int ks = __builtin_ctz(pm);
-          pm &= pm - 1u;
-          const double4 sv = s_xyz[4 * ks + (lane >> 4)];
-          const double c2 = chord2(cell, sv);
-          float wf = 0.f;
-          if (c2 <= a.c2R) wf = weight(c2, sv);
-          wsum += (double)wf;
-          sA32[(wave * kNS + ks) * 64 + lane] = wf;
-          if (__ballot(wf != 0.f)) nzbits |= 1u << ks;
-        }
-      } else {
-        // bit 4 s + j: 8-candidate group j of k-step s
-        const uint32_t gm = any_of_bytes(lo) | (any_of_bytes(hi) << 4);
-        uint32_t pm = ((gm & 15u) ? 1u : 0u) | ((gm >> 4) ? 2u : 0u);
-        const int grp = lane >> 4;
-        while (pm) {
-          const int ks = __builtin_ctz(pm);
-          pm &= pm - 1u;
-          // codes packed as they are made: 16-bit forms two per word, FP8 four
-          uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
-          if ((gm >> (4 * ks + grp)) & 1u) {
-            const int k0 = kK * ks + 8 * grp;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const double4 sv = s_xyz[k0 + t];
-              const double c2 = chord2(cell, sv);
-              uint32_t h = 0u, l = 0u;
-              if (c2 <= a.c2R) {
-                const float wf = weight(c2, sv);
-                h = enc_w<kForm>(wf);
-                double eff = (double)dec_w<kForm>(h);
-                if (kForm == kBF16Split) {
-                  l = f32_to_bf16(wf - dec_w<kForm>(h));
-                  eff += (double)bf16_to_f32(l);
-                } else if (kForm == kFP8Split) {
-                  l = f32_to_e4m3_cvt(wf * kW8Scale - dec_w<kForm>(h));
-                  eff += (double)e4m3_cvt_to_f32(l);
-                }
-                wsum += (double)wf;
-                wtsum += eff;
-              }
-              if (is_fp8(kForm)) {
-                hw[t >> 2] |= h << (8 * (t & 3));
-                if (kForm == kFP8Split) lw[t >> 2] |= l << (8 * (t & 3));
-              } else {
-                hw[t >> 1] |= h << (16 * (t & 1));
-                if (kForm == kBF16Split) lw[t >> 1] |= l << (16 * (t & 1));
-              }
-            }
-          }
-          uint32_t any;
-          const int slot = (wave * kNS + ks) * 64 + lane;
-          const int slot_lo = 4 * kNS * 64 + slot;
-          if (is_fp8(kForm)) {
-            sA8[slot] = make_uint2(hw[0], hw[1]);
-            any = hw[0] | hw[1];
-            if (kForm == kFP8Split) {
-              sA8[slot_lo] = make_uint2(lw[0], lw[1]);
-              any |= lw[0] | lw[1];
-            }
-          } else {
-            sA16[slot] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            any = hw[0] | hw[1] | hw[2] | hw[3];
-            if (kForm == kBF16Split) {
-              sA16[slot_lo] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-              any |= lw[0] | lw[1] | lw[2] | lw[3];
-            }
-          }
-          if (__ballot(any != 0u)) nzbits |= 1u << ks;
-        }
-      }
-    }
-    if (lane == 0) s_nz[wave] = nzbits;
-    __syncthreads();
+    // the next block's weights, while this block's loads are in flight
+    if (more) weights((int)((b + 1u) % 3u), ab ^ 1);
 
-    // ---- contraction over the block
-    const uint32_t nzc[4] = {s_nz[0], s_nz[1], s_nz[2], s_nz[3]};
+    // ---- contraction over block b
+    const uint32_t nzc[4] = {sm.nz[ab][0], sm.nz[ab][1], sm.nz[ab][2], sm.nz[ab][3]};
     if constexpr (kForm == kF32) {
+      const float* A = sA32(ab);
+      // the four cell blocks' A values of a k-step are read together, one
+      // k-step ahead, so that no product waits on an LDS read
+      float avn[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) avn[cb] = A[cb * kNS * 64 + lane];
 #pragma unroll
       for (int ks = 0; ks < kNS; ++ks) {
+        float avk[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) avk[cb] = avn[cb];
+        if (ks + 1 < kNS) {
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) avn[cb] = A[(cb * kNS + ks + 1) * 64 + lane];
+        }
         floatx4 cb_b[kQW];
         floatx4 cb_m[kMask ? kQW : 1];
 #pragma unroll
         for (int h = 0; h < kQW; ++h) {
-          cb_b[h] = b[ks % kDepth][h];
+          cb_b[h] = bb[ks % kDepth][h];
           if constexpr (kMask) {
             // flags: a non-finite value becomes 0 in the product and 0 in
             // the channel's weight operand
@@ -520,11 +575,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
             }
           }
         }
-        if (ks + kDepth < kNS) load(ks + kDepth, b[ks % kDepth]);
+        if (ks + kDepth < kNS) load(s_row, ks + kDepth, bb[ks % kDepth]);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           if ((nzc[cb] >> ks) & 1u) {
-            const float av = sA32[(cb * kNS + ks) * 64 + lane];
+            const float av = avk[cb];
 #pragma unroll
             for (int h = 0; h < kQW; ++h) {
               if (h >= hlive) continue;
@@ -543,38 +598,48 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         }
       }
     } else if constexpr (kPacked) {
+      const uint4* A16 = sA16(ab);
+      const uint2* A8 = sA8(ab);
 #pragma unroll
       for (int ks = 0; ks < kNS; ++ks) {
         // the k-steps not loaded early are loaded once the previous k-step's
         // products are issued (registers); the scheduler may not merge them
         __builtin_amdgcn_sched_barrier(0);
-        if (ks >= kEarly) load_b(ks);
+        if (ks >= kEarly) load_b(s_row, ks);
+        // the four cell blocks' A operands of the k-step, read together
+        uint4 a16[is_fp8(kForm) ? 1 : 4];
+        uint2 a8[is_fp8(kForm) ? 4 : 1];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if constexpr (is_fp8(kForm)) a8[cb] = A8[(cb * kNS + ks) * 64 + lane];
+          else a16[cb] = A16[(cb * kNS + ks) * 64 + lane];
+        }
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           if (!((nzc[cb] >> ks) & 1u)) continue;
           if constexpr (is_fp8(kForm)) {
-            const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
-            const long A = (long)(((uint64_t)av.y << 32) | av.x);
+            const uint2 av = a8[cb];
+            const long Aop = (long)(((uint64_t)av.y << 32) | av.x);
             long Al = 0;
             if (kForm == kFP8Split) {
-              const uint2 al = sA8[(4 * kNS + cb * kNS + ks) * 64 + lane];
+              const uint2 al = A8[(4 * kNS + cb * kNS + ks) * 64 + lane];
               Al = (long)(((uint64_t)al.y << 32) | al.x);
             }
 #pragma unroll
             for (int j = 0; j < kNJ; ++j) {
               floatx4& c = acc[cb][j];
               const long B = (long)(((uint64_t)bq[ks][j].y << 32) | bq[ks][j].x);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, B, c, 0, 0, 0);
               if (kForm == kFP8Split) {
                 const long Bl = (long)(((uint64_t)bql[ks][j].y << 32) | bql[ks][j].x);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, Bl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, Bl, c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
               }
             }
           } else {
-            const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
+            const uint4 av = a16[is_fp8(kForm) ? 0 : cb];
             uint4 al = make_uint4(0u, 0u, 0u, 0u);
-            if (kForm == kBF16Split) al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
+            if (kForm == kBF16Split) al = A16[(4 * kNS + cb * kNS + ks) * 64 + lane];
 #pragma unroll
             for (int j = 0; j < kNJ; ++j) {
               floatx4& c = acc[cb][j];
@@ -600,6 +665,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         }
       }
     } else {
+      const uint4* A16 = sA16(ab);
+      const uint2* A8 = sA8(ab);
 #pragma unroll
       for (int ks = 0; ks < kNS; ++ks) {
         const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
@@ -619,16 +686,21 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
               for (int t = 0; t < 8; ++t) {
                 const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
-                const uint8_t* src = spec + row * C + ch;
+                const uint8_t* rp = spec + row * C;
                 if (kEarlyRaw && ks == 0) {
                   d[t] = e8[kEarlyRaw ? h : 0][t];
                 } else if (kVec) {
-                  d[t] = (ch + 3 < C) ? *(const uint32_t*)src : 0u;
+                  const bool ok = ch + 3 < C;
+                  const uint32_t v = *(const uint32_t*)(rp + (ok ? ch : 0));
+                  d[t] = ok ? v : 0u;
                 } else {
                   d[t] = 0u;
 #pragma unroll
-                  for (int e = 0; e < 4; ++e)
-                    if (ch + e < C) d[t] |= (uint32_t)src[e] << (8 * e);
+                  for (int e = 0; e < 4; ++e) {
+                    const bool ok = ch + e < C;
+                    const uint32_t v = rp[ok ? ch + e : 0];
+                    d[t] |= (ok ? v : 0u) << (8 * e);
+                  }
                 }
               }
 #pragma unroll
@@ -656,15 +728,20 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
               for (int t = 0; t < 8; ++t) {
                 const int64_t row = s_row[kK * ks + 8 * (lane >> 4) + t];
-                const uint16_t* src = spec + row * C + ch;
+                const uint16_t* rp = spec + row * C;
                 if (kEarlyRaw && ks == 0 && plane == 0) {
                   d[t] = e16[kEarlyRaw ? h : 0][t];
                 } else if (kVec) {
-                  d[t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+                  d[t] = (ch + 3 < C) ? *(const uint2*)(rp + ch) : make_uint2(0u, 0u);
                 } else {
-                  const uint32_t e0 = (ch + 0 < C) ? src[0] : 0u, e1 = (ch + 1 < C) ? src[1] : 0u;
-                  const uint32_t e2 = (ch + 2 < C) ? src[2] : 0u, e3 = (ch + 3 < C) ? src[3] : 0u;
-                  d[t] = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+                  uint32_t e[4];
+#pragma unroll
+                  for (int k = 0; k < 4; ++k) {
+                    const bool ok = ch + k < C;
+                    const uint32_t v = rp[ok ? ch + k : 0];
+                    e[k] = ok ? v : 0u;
+                  }
+                  d[t] = make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
                 }
               }
 #pragma unroll
@@ -683,20 +760,20 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
             for (int q = 0; q < 4; ++q) {
               floatx4& c = acc[cb][4 * h + q];
               if (is_fp8(kForm)) {
-                const uint2 av = sA8[(cb * kNS + ks) * 64 + lane];
-                const long A = (long)(((uint64_t)av.y << 32) | av.x);
+                const uint2 av = A8[(cb * kNS + ks) * 64 + lane];
+                const long Aop = (long)(((uint64_t)av.y << 32) | av.x);
                 const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, B, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, B, c, 0, 0, 0);
                 if (kForm == kFP8Split) {
                   // W_hi S_lo + W_lo S_hi (the W_lo S_lo term is below the budget)
-                  const uint2 al = sA8[(4 * kNS + cb * kNS + ks) * 64 + lane];
+                  const uint2 al = A8[(4 * kNS + cb * kNS + ks) * 64 + lane];
                   const long Al = (long)(((uint64_t)al.y << 32) | al.x);
                   const long Bl = (long)(((uint64_t)fbl[q][1] << 32) | fbl[q][0]);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A, Bl, c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, Bl, c, 0, 0, 0);
                   c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
                 }
               } else {
-                const uint4 av = sA16[(cb * kNS + ks) * 64 + lane];
+                const uint4 av = A16[(cb * kNS + ks) * 64 + lane];
                 const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
                 if (kForm == kF16S) {
                   c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
@@ -705,7 +782,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                   c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
                                                              __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
                   if (kForm == kBF16Split) {
-                    const uint4 al = sA16[(4 * kNS + cb * kNS + ks) * 64 + lane];
+                    const uint4 al = A16[(4 * kNS + cb * kNS + ks) * 64 + lane];
                     const uint4 bl = make_uint4(fbl[q][0], fbl[q][1], fbl[q][2], fbl[q][3]);
                     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
                                                                __builtin_bit_cast(bf16x8, bl), c, 0, 0, 0);
@@ -718,6 +795,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           }
         }
       }
+    }
+
+    // wave 0 stages block b + 2 (loaded during the previous block) and
+    // starts the loads of block b + 3
+    if (b + 2 < nblk) {
+      if (!kAhead) fetch((b + 2u) * kKB);
+      stage((int)((b + 2u) % 3u));
+      if (kAhead && b + 3 < nblk) fetch((b + 3u) * kKB);
     }
     __syncthreads();
   }
@@ -807,8 +892,8 @@ __device__ inline void gather_cells_tile_wg(const GatherArgs& a, int tile, Gathe
       stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
   const int C = (int)a.C;
   const float* spec = (const float*)a.spec;
-  double4* wxyz = (double4*)sm.Araw + wave * kKB;                      // [4][64]
-  float* wspec = (float*)((double4*)sm.Araw + 4 * kKB) + wave * kKB * 8;  // [4][64][8]
+  double4* wxyz = (double4*)&sm.Araw[0][0] + wave * kKB;                      // [4][64]
+  float* wspec = (float*)((double4*)&sm.Araw[0][0] + 4 * kKB) + wave * kKB * 8;  // [4][64][8]
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
@@ -843,7 +928,7 @@ __device__ inline void gather_cells_tile_wg(const GatherArgs& a, int tile, Gathe
     }
     __syncthreads();
   }
-  double* red = (double*)sm.Araw;  // [9][64]
+  double* red = (double*)&sm.Araw[0][0];  // [9][64]
   for (int w = 1; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
