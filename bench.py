@@ -526,7 +526,7 @@ def run_batch(args):
     ms_bat = timed(batched, args.steps)
     log(f"batched plan+grid: {ms_bat:.1f} ms; grid only: batched {ms_grid_b:.1f} ms vs "
         f"separate {ms_grid_sep:.1f} ms; autotuner {info['tune_ms']} -> slab "
-        f"{info['chan_slab']}, cost order {info['cost_order']}; identical to separate: {same}")
+        f"{info['chan_slab']}, cost order {info['cost_order']}, launch {info['launch']}; identical to separate: {same}")
     out = {
         "metric": "sample*channel updates/s, FP32 gather vs BF16-MFMA at <=1e-3 rel err",
         "value": tot_in / (ms_bat * 1e-3), "unit": "sample*channel updates/s", "n_gpus": 1,
@@ -540,6 +540,7 @@ def run_batch(args):
         "batched_grid_ms": ms_grid_b, "separate_grid_ms": ms_grid_sep,
         "speedup_batched_vs_separate": ms_sep / ms_bat,
         "autotune": {"tune_ms": info["tune_ms"], "chan_slab": info["chan_slab"],
+                     "launch": ["persistent", "work items"][info["launch"]],
                      "cost_order": info["cost_order"], "items": info["items"],
                      "persistent_blocks": info["persistent_blocks"]},
         "batched_equals_separate_for_C_gt_8": same,

@@ -532,15 +532,24 @@ typedef struct {
   float* weights;          /* device float32 [ny][nx] or NULL */
 } hcg_field_data;
 
+/* hcg_opts.flags of hcg_plan_batch: fix the launch strategy of
+ * hcg_grid_batch (at most one; neither = autotuned). */
+#define HCG_BATCH_PERSISTENT 1u /* persistent kernels popping work items */
+#define HCG_BATCH_ITEMS 2u      /* one workgroup per work item */
+
 /*
  * hcg_plan_batch -- one plan per field (the steps of hcg_plan for each).
  *   fields  host array [nfields] (pointers inside are device pointers).
  *   opts    host pointer or NULL.  opts->chan_tile selects the channel slab
- *           of the persistent kernel: 0 = autotune on the first
+ *           of the matrix-core work items: 0 = autotune on the first
  *           hcg_grid_batch call, 256 or 512 = fixed (items ordered by cost);
- *           nside and tile fields apply to every field as in hcg_plan.
+ *           opts->flags may fix the launch strategy (HCG_BATCH_PERSISTENT
+ *           or HCG_BATCH_ITEMS); nside and tile fields apply to every field
+ *           as in hcg_plan.
+ * The plans are built by up to eight host threads, each on a stream of its
+ * own (kept by the library for later calls) that first waits for hip_stream.
  * Synchronous.  Errors as hcg_plan, with the failing field named in the
- * message; nothing leaks on failure.
+ * message (HCG_E_UNSUPPORTED for other flags); nothing leaks on failure.
  */
 hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_desc* fields,
                           const hcg_opts* opts, void* hip_stream);
@@ -551,11 +560,14 @@ hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_des
  *         may use different storage forms.
  * Every (field, tile, channel slab) is a work item.  Items are grouped by
  * kernel class (the few-channel FP32 gather, and the matrix-core gather of
- * each storage form); per class, a persistent kernel of two workgroups per
- * CU pops the items, ordered largest-cost first, from per-XCD counters.  The
- * first call may run the batch several times to autotune the channel slab
- * and the field order (same results every time); it then captures the
- * classes' launches in one hipGraph that later calls replay.  Pointers,
+ * each storage form, for rows read four elements or one at a time); per
+ * class, either a persistent kernel of two workgroups per CU pops the items
+ * from per-XCD counters, or one launch runs one workgroup per item (the
+ * fields' items in turn, each field's tiles dealt to the XCDs in contiguous
+ * eighths).  The first call may run the batch several times to autotune the
+ * channel slab, the field order (largest cost first, or as given) and the
+ * launch strategy (same results every time); it then captures the classes'
+ * launches in one hipGraph that later calls replay.  Pointers,
  * forms and channel counts may change between calls (the device tables are
  * rewritten before the replay, and the graph captured again when the
  * classes change; the rewrite waits for the previous launch, on whichever
@@ -580,8 +592,11 @@ typedef struct {
   int32_t graph_captured;    /* 1 once the launch is captured */
   int32_t persistent_blocks; /* workgroups of the persistent kernel */
   int64_t items;             /* work items of the last build */
-  double tune_ms[4];         /* autotuner timings: (256, cost), (512, cost),
+  double tune_ms[8];         /* autotuner timings, persistent then work-item
+                                launch, each (256, cost), (512, cost),
                                 (256, natural), (512, natural); 0 if skipped */
+  int32_t launch;            /* 0: persistent kernels; 1: one workgroup per item */
+  int32_t reserved;
 } hcg_batch_info;
 
 hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info);

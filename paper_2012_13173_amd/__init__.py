@@ -27,6 +27,7 @@ HCG_OK, HCG_E_ARG, HCG_E_NOMEM, HCG_E_DEVICE, HCG_E_UNSUPPORTED, HCG_E_STATE = r
 HCG_ARR_KEYS, HCG_ARR_PERM, HCG_ARR_RING_CSR, HCG_ARR_TILE_NRANGES, HCG_ARR_TILE_RANGES = range(5)
 HCG_KERNEL_GAUSS, HCG_KERNEL_ELLIPTIC_GAUSS, HCG_KERNEL_TAPERED_SINC = range(3)
 HCG_PROJ_CAR, HCG_PROJ_SFL, HCG_PROJ_SIN, HCG_PROJ_TAN = range(4)
+HCG_BATCH_PERSISTENT, HCG_BATCH_ITEMS = 1, 2
 PROJECTIONS = {"CAR": HCG_PROJ_CAR, "SFL": HCG_PROJ_SFL, "SIN": HCG_PROJ_SIN, "TAN": HCG_PROJ_TAN}
 STATUS_NAMES = {0: "HCG_OK", 1: "HCG_E_ARG", 2: "HCG_E_NOMEM", 3: "HCG_E_DEVICE",
                 4: "HCG_E_UNSUPPORTED", 5: "HCG_E_STATE"}
@@ -101,7 +102,8 @@ class BatchInfoC(ctypes.Structure):
     _fields_ = [("nfields", ctypes.c_int32), ("chan_slab", ctypes.c_int32),
                 ("cost_order", ctypes.c_int32), ("tuned", ctypes.c_int32),
                 ("graph_captured", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
-                ("items", ctypes.c_int64), ("tune_ms", ctypes.c_double * 4)]
+                ("items", ctypes.c_int64), ("tune_ms", ctypes.c_double * 8),
+                ("launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_plan_info",
@@ -555,16 +557,20 @@ class Batch:
             pass
 
 
-def hcg_plan_batch(fields, chan_tile: int = 0, nside: int = 0, stream=None) -> Batch:
+def hcg_plan_batch(fields, chan_tile: int = 0, nside: int = 0, launch: str = "auto",
+                   stream=None) -> Batch:
     """``fields``: sequence of (lon, lat, grid, fwhm_deg, support_deg), lon/lat
-    device float64 tensors (read during the call only)."""
+    device float64 tensors (read during the call only).  ``launch``: "auto"
+    (autotuned), "persistent" or "items" (HCG_BATCH_PERSISTENT /
+    HCG_BATCH_ITEMS)."""
+    flags = {"auto": 0, "persistent": HCG_BATCH_PERSISTENT, "items": HCG_BATCH_ITEMS}[launch]
     arr = (FieldDescC * len(fields))()
     for i, (lon, lat, grid, fwhm, support) in enumerate(fields):
         if int(lat.shape[0]) != int(lon.shape[0]):
             raise ValueError(f"field {i}: lon and lat differ in length")
         arr[i] = FieldDescC(_dptr(lon, torch.float64, "lon"), _dptr(lat, torch.float64, "lat"),
                             int(lon.shape[0]), grid_desc(grid), float(fwhm), float(support))
-    opts = OptsC(int(nside), 0, 0, 0, int(chan_tile), 0)
+    opts = OptsC(int(nside), 0, 0, 0, int(chan_tile), flags)
     handle = ctypes.c_void_p()
     _check(load().hcg_plan_batch(ctypes.byref(handle), len(fields), arr, ctypes.byref(opts),
                                  _stream(stream)), "hcg_plan_batch")

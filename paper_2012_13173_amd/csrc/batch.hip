@@ -22,7 +22,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gather_tile.h"
@@ -30,9 +32,15 @@
 namespace hcg {
 
 // Kernel classes of the batch: the matrix-core gather of each storage form
-// (the hcg_dtype values) and the few-channel FP32 gather.
+// for rows read four channels at a time (the hcg_dtype values), the
+// few-channel FP32 gather, and the matrix-core gather of each form for rows
+// read one element at a time (hcg_dtype + kClsScalarRows).  Each class's
+// persistent kernel compiles one gather path, which keeps it in the
+// registers of two workgroups per CU.
 constexpr int kClsCells = 6;
-constexpr int kClasses = 7;
+constexpr int kPlanThreads = 8;  // host threads building the plans of a batch
+constexpr int kClsScalarRows = 7;
+constexpr int kClasses = 13;
 
 // ctl: [0..7] next item of each XCD's segment, [8] item count, [9] segment
 // count.  The item space of a class is cut into eight contiguous segments,
@@ -87,46 +95,117 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
     const GatherArgs& a = fields[sg.field];  // read on demand (scalar loads)
     if constexpr (kCls == kClsCells) {
       gather_cells_tile_wg(a, (int)tile, sm);
+    } else if constexpr (kCls >= kClsScalarRows) {  // 256-channel slabs
+      gather_tile<kCls - kClsScalarRows, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
     } else if constexpr (kCls == kBF16Split) {  // 256-channel slabs only (registers)
-      if (a.vec) gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
-      else gather_tile<kBF16Split, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
+      gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
     } else {
-      if (a.vec) gather_tile<kCls, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
-      else gather_tile<kCls, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
+      gather_tile<kCls, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
     }
     __syncthreads();
   }
 }
 
+// The work-item launch of a class: one workgroup per item, no counters.  A
+// field's items are its slabs x (tiles rounded up to whole eighths), decoded
+// as in the per-plan gather: consecutive workgroups go to the eight XCDs in
+// turn and XCD x takes the x-th eighth of the field's tiles, so the tiles an
+// XCD runs together are neighbours.  The hardware dispatcher starts the
+// next field's workgroups as the previous field's finish, which fills the
+// tail of each field with work.  Compiled without the persistent loop, the
+// 512-channel kernels keep their registers.
+template <int kCls, int kQW, bool kWide>
+__global__ void __launch_bounds__(256, 2) k_gather_items(const GatherArgs* __restrict__ fields,
+                                                         const BatchSeg* __restrict__ segs,
+                                                         uint32_t nseg) {
+  __shared__ GatherSmem sm;
+  const uint32_t it = blockIdx.x;
+  uint32_t lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
+  }
+  const BatchSeg sg = segs[lo];
+  const uint32_t local = it - sg.base;
+  const GatherArgs& a = fields[sg.field];
+  if constexpr (kCls == kClsCells) {
+    gather_cells_tile_wg(a, (int)local, sm);
+  } else {
+    const uint32_t per_slab = (uint32_t)a.tiles_per_xcd * 8u;
+    const uint32_t slab = local / per_slab;
+    const uint32_t loc = local - slab * per_slab;
+    const uint32_t tile = (loc & 7u) * (uint32_t)a.tiles_per_xcd + (loc >> 3);
+    if (tile >= (uint32_t)a.ntiles) return;
+    if constexpr (kCls >= kClsScalarRows) {
+      gather_tile<kCls - kClsScalarRows, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
+    } else if constexpr (kCls == kBF16Split) {
+      gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
+    } else {
+      gather_tile<kCls, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
+    }
+  }
+}
+
+// Launch strategies of hcg_grid_batch.
+constexpr int kLaunchPersistent = 0;
+constexpr int kLaunchItems = 1;
+
 namespace {
+
+// Launch geometry of one class: the persistent kernel (nblocks workgroups,
+// after its counter reset) or the work-item kernel (one workgroup per item).
+struct ClassLaunch {
+  int strategy;
+  int nblocks;
+  uint32_t nitems, nseg;
+};
+
+template <int kCls, int kQW, bool kWide>
+void launch_one(const ClassLaunch& l, const GatherArgs* fields, const BatchSeg* segs,
+                uint32_t* ctl, hipStream_t stream) {
+  if (l.strategy == kLaunchItems)
+    k_gather_items<kCls, kQW, kWide><<<l.nitems, 256, 0, stream>>>(fields, segs, l.nseg);
+  else
+    k_gather_batch<kCls, kQW, kWide><<<l.nblocks, 256, 0, stream>>>(fields, segs, ctl);
+}
 
 template <int kCls>
 void launch_cls(int qw, bool wide, const GatherArgs* fields, const BatchSeg* segs, uint32_t* ctl,
-                int nblocks, hipStream_t stream) {
-  if (qw == 2 && wide) k_gather_batch<kCls, 2, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  else if (qw == 2) k_gather_batch<kCls, 2, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  else if (wide) k_gather_batch<kCls, 1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-  else k_gather_batch<kCls, 1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
+                const ClassLaunch& l, hipStream_t stream) {
+  // classes with 256-channel slabs only have no 512-channel kernels
+  constexpr bool kSlab512 = kCls < kClsCells && kCls != kBF16Split;
+  if constexpr (kSlab512) {
+    if (qw == 2) {
+      if (wide) launch_one<kCls, 2, true>(l, fields, segs, ctl, stream);
+      else launch_one<kCls, 2, false>(l, fields, segs, ctl, stream);
+      return;
+    }
+  }
+  if (wide) launch_one<kCls, 1, true>(l, fields, segs, ctl, stream);
+  else launch_one<kCls, 1, false>(l, fields, segs, ctl, stream);
 }
 
 hcg_status launch_class(int cls, int qw, bool wide, const GatherArgs* fields,
-                        const BatchSeg* segs, uint32_t* ctl, int nblocks, hipStream_t stream) {
-  k_batch_reset<<<1, 1, 0, stream>>>(ctl);
-  HCG_LAUNCH_CHECK("k_batch_reset");
+                        const BatchSeg* segs, uint32_t* ctl, const ClassLaunch& l,
+                        hipStream_t stream) {
+  if (l.strategy == kLaunchPersistent) {
+    k_batch_reset<<<1, 1, 0, stream>>>(ctl);
+    HCG_LAUNCH_CHECK("k_batch_reset");
+  }
   switch (cls) {
-    case kClsCells:
-      if (wide) k_gather_batch<kClsCells, 1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-      else k_gather_batch<kClsCells, 1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-      break;
-    case kBF16Split:
-      if (wide) k_gather_batch<kBF16Split, 1, true><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-      else k_gather_batch<kBF16Split, 1, false><<<nblocks, 256, 0, stream>>>(fields, segs, ctl);
-      break;
-    case kF32: launch_cls<kF32>(qw, wide, fields, segs, ctl, nblocks, stream); break;
-    case kBF16: launch_cls<kBF16>(qw, wide, fields, segs, ctl, nblocks, stream); break;
-    case kF16S: launch_cls<kF16S>(qw, wide, fields, segs, ctl, nblocks, stream); break;
-    case kFP8S: launch_cls<kFP8S>(qw, wide, fields, segs, ctl, nblocks, stream); break;
-    default: launch_cls<kFP8Split>(qw, wide, fields, segs, ctl, nblocks, stream); break;
+    case kClsCells: launch_cls<kClsCells>(1, wide, fields, segs, ctl, l, stream); break;
+    case kBF16Split: launch_cls<kBF16Split>(1, wide, fields, segs, ctl, l, stream); break;
+    case kF32: launch_cls<kF32>(qw, wide, fields, segs, ctl, l, stream); break;
+    case kBF16: launch_cls<kBF16>(qw, wide, fields, segs, ctl, l, stream); break;
+    case kF16S: launch_cls<kF16S>(qw, wide, fields, segs, ctl, l, stream); break;
+    case kFP8S: launch_cls<kFP8S>(qw, wide, fields, segs, ctl, l, stream); break;
+    case kFP8Split: launch_cls<kFP8Split>(qw, wide, fields, segs, ctl, l, stream); break;
+    case kClsScalarRows + kF32: launch_cls<kClsScalarRows + kF32>(1, wide, fields, segs, ctl, l, stream); break;
+    case kClsScalarRows + kBF16: launch_cls<kClsScalarRows + kBF16>(1, wide, fields, segs, ctl, l, stream); break;
+    case kClsScalarRows + kBF16Split: launch_cls<kClsScalarRows + kBF16Split>(1, wide, fields, segs, ctl, l, stream); break;
+    case kClsScalarRows + kF16S: launch_cls<kClsScalarRows + kF16S>(1, wide, fields, segs, ctl, l, stream); break;
+    case kClsScalarRows + kFP8S: launch_cls<kClsScalarRows + kFP8S>(1, wide, fields, segs, ctl, l, stream); break;
+    default: launch_cls<kClsScalarRows + kFP8Split>(1, wide, fields, segs, ctl, l, stream); break;
   }
   HCG_LAUNCH_CHECK("k_gather_batch");
   return HCG_OK;
@@ -141,9 +220,10 @@ bool form_scaled(int dtype) {
 }
 bool form_split(int dtype) { return dtype == HCG_BF16_SPLIT || dtype == HCG_FP8E4M3_SPLIT; }
 
-// Kernel class of a field's data.
-int field_class(const hcg_field_data& d) {
-  return (d.dtype == HCG_F32 && d.nchan <= 8) ? kClsCells : (int)d.dtype;
+// Kernel class of a field's data (vec: rows read four elements at a time).
+int field_class(const hcg_field_data& d, bool vec) {
+  if (d.dtype == HCG_F32 && d.nchan <= 8) return kClsCells;
+  return vec ? (int)d.dtype : kClsScalarRows + (int)d.dtype;
 }
 
 // Gather arguments of one field: the plan's arrays, the spectra in the form's
@@ -197,12 +277,13 @@ struct hcg_batch_s {
   std::vector<GatherArgs> h_fields;
   std::vector<int64_t> built_C;
   std::vector<int> built_vec, built_cls;
-  int built_qw = 0, built_order = -1;
+  int built_qw = 0, built_order = -1, built_strategy = -1;
   uint32_t nitems[kClasses] = {};
+  uint32_t nseg[kClasses] = {};
   bool wide[kClasses] = {};
-  int qw = 0, cost_order = 1;
+  int qw = 0, cost_order = 1, strategy = kLaunchPersistent;
   bool tuned = false;
-  double tune_ms[4] = {0, 0, 0, 0};
+  double tune_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -217,6 +298,29 @@ namespace {
 
 std::mutex g_batch_mu;
 std::vector<const hcg_batch_s*> g_batches;
+
+// Streams of the threads that build a batch's plans: made once per device
+// (creating a stream costs milliseconds) and kept until the process ends.
+constexpr int kMaxPoolDevices = 64;
+std::mutex g_pool_mu;
+std::vector<hipStream_t> g_pool[kMaxPoolDevices];
+
+// The first n worker streams of `dev` (the current device).
+hcg_status plan_streams(int dev, int n, std::vector<hipStream_t>* out) {
+  if (dev < 0 || dev >= kMaxPoolDevices)
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: device %d is beyond the %d served", dev,
+                kMaxPoolDevices);
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  std::vector<hipStream_t>& pool = g_pool[dev];
+  while ((int)pool.size() < n) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+      return fail(HCG_E_DEVICE, "hcg_plan_batch: cannot create a stream");
+    pool.push_back(s);
+  }
+  out->assign(pool.begin(), pool.begin() + n);
+  return HCG_OK;
+}
 
 bool batch_is_live(const hcg_batch_s* b) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
@@ -239,9 +343,10 @@ void free_batch(hcg_batch_s* b) {
 
 // Item segments of every class for slab width 256 * qw (256 for the BF16
 // hi+lo form and for fields whose rows cannot be read four elements at a
-// time; one item per tile for the few-channel class).
+// time; one item per tile for the few-channel class).  The work-item launch
+// gives a field slabs x (tiles rounded up to whole eighths) items.
 hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int cost_order,
-                       hipStream_t stream) {
+                       int strategy, hipStream_t stream) {
   const size_t nf = b->plans.size();
   std::vector<double> cost(nf);
   std::vector<BatchSeg> seg(nf);
@@ -249,8 +354,7 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
     const int64_t C = data[f].nchan;
     const int cls = b->built_cls[f];
     const bool cells = cls == kClsCells;
-    const int64_t width =
-        cells ? C : ((b->built_vec[f] && cls != kBF16Split) ? 256 * qw : 256);
+    const int64_t width = cells ? C : ((cls < kClsCells && cls != kBF16Split) ? 256 * qw : 256);
     const int64_t slabs = cells ? 1 : (C + width - 1) / width;
     const std::vector<uint32_t>& nc = b->ncand[f];
     double cand = 0.0;
@@ -277,11 +381,15 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
       BatchSeg sg = seg[f];
       sg.base = (uint32_t)base;
       host[(size_t)c * nf + nseg++] = sg;
-      base += (uint64_t)sg.ntiles * sg.slabs;
-      if (base >= 0xFFFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
+      const uint64_t span = (strategy == kLaunchItems && c != kClsCells)
+                                ? (uint64_t)b->h_fields[f].tiles_per_xcd * 8u
+                                : (uint64_t)sg.ntiles;
+      base += span * sg.slabs;
+      if (base >= 0x7FFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_grid_batch: too many items");
       wide = wide || !(b->h_fields[f].c2R < kNarrowChord2);
     }
     b->nitems[c] = (uint32_t)base;
+    b->nseg[c] = nseg;
     b->wide[c] = wide;
     ctl[(size_t)c * kBatchCtl + 8] = (uint32_t)base;
     ctl[(size_t)c * kBatchCtl + 9] = nseg;
@@ -293,6 +401,7 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
   HCG_HIP(hipStreamSynchronize(stream));  // the host arrays above go out of scope
   b->built_qw = qw;
   b->built_order = cost_order;
+  b->built_strategy = strategy;
   return HCG_OK;
 }
 
@@ -301,9 +410,10 @@ hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
   const size_t nf = b->plans.size();
   for (int c = 0; c < kClasses; ++c) {
     if (!b->nitems[c]) continue;
+    const ClassLaunch l{b->strategy, b->nblocks, b->nitems[c], b->nseg[c]};
     const hcg_status st = launch_class(c, b->qw, b->wide[c], b->d_fields,
                                        b->d_segs + (size_t)c * nf,
-                                       b->d_ctl + (size_t)c * kBatchCtl, b->nblocks, stream);
+                                       b->d_ctl + (size_t)c * kBatchCtl, l, stream);
     if (st != HCG_OK) return st;
   }
   return HCG_OK;
@@ -331,26 +441,34 @@ std::string batch_signature(const hcg_batch_s* b, const hcg_field_data* data) {
   return buf;
 }
 
-bool tune_cache_lookup(const std::string& sig, int* qw, int* order) {
+// Tune cache lines: "<signature> <qw> <cost order> <launch strategy>"; lines
+// of another shape are skipped, the last matching line wins.
+bool tune_cache_lookup(const std::string& sig, int* qw, int* order, int* strategy) {
   const char* path = getenv("HCG_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
-  char s[64];
-  int q, o;
+  char line[256], s[64];
+  int q, o, l;
   bool found = false;
-  while (fscanf(f, "%63s %d %d", s, &q, &o) == 3)
-    if (sig == s && (q == 1 || q == 2) && (o == 0 || o == 1)) { *qw = q; *order = o; found = true; }
+  while (fgets(line, sizeof(line), f))
+    if (sscanf(line, "%63s %d %d %d", s, &q, &o, &l) == 4 && sig == s && (q == 1 || q == 2) &&
+        (o == 0 || o == 1) && (l == kLaunchPersistent || l == kLaunchItems)) {
+      *qw = q;
+      *order = o;
+      *strategy = l;
+      found = true;
+    }
   fclose(f);
   return found;
 }
 
-void tune_cache_store(const std::string& sig, int qw, int order) {
+void tune_cache_store(const std::string& sig, int qw, int order, int strategy) {
   const char* path = getenv("HCG_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d\n", sig.c_str(), qw, order);
+  fprintf(f, "%s %d %d %d\n", sig.c_str(), qw, order, strategy);
   fclose(f);
 }
 
@@ -366,45 +484,97 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
   if (opts) o = *opts;
   if (o.chan_tile != 0 && o.chan_tile != 256 && o.chan_tile != 512)
     return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: chan_tile must be 0, 256 or 512");
-  if (o.coarsen || o.flags) return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: coarsen and flags must be 0");
+  if (o.coarsen) return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: coarsen must be 0");
+  if (o.flags & ~(uint32_t)(HCG_BATCH_PERSISTENT | HCG_BATCH_ITEMS) ||
+      (o.flags & HCG_BATCH_PERSISTENT && o.flags & HCG_BATCH_ITEMS))
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: flags may hold one of HCG_BATCH_PERSISTENT "
+                "and HCG_BATCH_ITEMS only");
   hcg_status st = check_device_arch();
   if (st != HCG_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
   auto* b = new hcg_batch_s();
   b->opts = o;
-  hcg_opts po = o;
+  hcg_opts po = o;  // the per-field plans take nside and tile only
   po.chan_tile = 0;
-  for (int32_t f = 0; f < nfields; ++f) {
-    const hcg_field_desc& d = fields[f];
-    hcg_plan_t p = nullptr;
-    st = hcg_plan(&p, d.lon_deg, d.lat_deg, d.n, &d.grid, d.fwhm_deg, d.support_deg, &po,
-                  hip_stream);
-    if (st != HCG_OK) {
-      std::string msg = hcg_last_error();
-      free_batch(b);
-      return fail(st, "hcg_plan_batch: field %d: %s", f, msg.c_str());
-    }
-    b->plans.push_back(p);
-    const size_t nt = (size_t)p->ntx * p->nty;
-    b->ncand.emplace_back(nt);
-    if (hipMemcpyAsync(b->ncand.back().data(), p->ncand, sizeof(uint32_t) * nt,
-                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-      free_batch(b);
-      return fail(HCG_E_DEVICE, "hcg_plan_batch: reading candidate counts failed");
-    }
-  }
+  po.flags = 0;
   int cus = 0;
   if (hipGetDevice(&b->device) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
     free_batch(b);
     return fail(HCG_E_DEVICE, "hcg_plan_batch: device query failed");
   }
+  // The plans are built by up to kPlanThreads host threads, each on a stream
+  // of its own that first waits for the caller's stream (where the
+  // coordinates were written): a plan is a chain of short kernels with a few
+  // host reads, so one plan at a time leaves the GPU mostly idle, and plans
+  // of different fields overlap.  Fields go to the threads largest first.
+  b->plans.assign(nfields, nullptr);
+  b->ncand.resize(nfields);
+  std::vector<hcg_status> fst(nfields, HCG_OK);
+  std::vector<std::string> fmsg(nfields);
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, stream) != hipSuccess) {
+    if (ready) (void)hipEventDestroy(ready);
+    free_batch(b);
+    return fail(HCG_E_DEVICE, "hcg_plan_batch: event on the caller's stream failed");
+  }
+  std::vector<int32_t> order(nfields);
+  for (int32_t f = 0; f < nfields; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return fields[x].n > fields[y].n; });
+  const int nthreads = std::max(1, std::min<int>(kPlanThreads, nfields));
+  std::vector<hipStream_t> wstreams;
+  st = plan_streams(b->device, nthreads, &wstreams);
+  if (st != HCG_OK) {
+    (void)hipEventDestroy(ready);
+    free_batch(b);
+    return st;
+  }
+  std::atomic<int32_t> next{0};
+  auto worker = [&](int t) {
+    if (hipSetDevice(b->device) != hipSuccess) return;
+    hipStream_t ws = wstreams[t];
+    if (hipStreamWaitEvent(ws, ready, 0) == hipSuccess) {
+      for (int32_t k; (k = next.fetch_add(1)) < nfields;) {
+        const int32_t f = order[k];
+        const hcg_field_desc& d = fields[f];
+        hcg_plan_t p = nullptr;
+        hcg_status s2 = hcg_plan(&p, d.lon_deg, d.lat_deg, d.n, &d.grid, d.fwhm_deg,
+                                 d.support_deg, &po, ws);
+        if (s2 == HCG_OK) {
+          const size_t nt = (size_t)p->ntx * p->nty;
+          b->ncand[f].resize(nt);
+          if (hipMemcpyAsync(b->ncand[f].data(), p->ncand, sizeof(uint32_t) * nt,
+                             hipMemcpyDeviceToHost, ws) != hipSuccess ||
+              hipStreamSynchronize(ws) != hipSuccess) {
+            s2 = fail(HCG_E_DEVICE, "reading candidate counts failed");
+          }
+        }
+        b->plans[f] = p;
+        fst[f] = s2;
+        if (s2 != HCG_OK) fmsg[f] = hcg_last_error();
+      }
+    }
+    (void)hipStreamSynchronize(ws);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; ++t) pool.emplace_back(worker, t);
+  worker(0);
+  for (std::thread& t : pool) t.join();
+  (void)hipEventDestroy(ready);
+  for (int32_t f = 0; f < nfields; ++f) {
+    if (fst[f] != HCG_OK || !b->plans[f]) {
+      const hcg_status fs = fst[f] != HCG_OK ? fst[f] : HCG_E_DEVICE;
+      const std::string msg = fst[f] != HCG_OK ? fmsg[f] : "no plan was built";
+      free_batch(b);
+      return fail(fs, "hcg_plan_batch: field %d: %s", f, msg.c_str());
+    }
+  }
   b->nblocks = 2 * cus;  // two 256-thread workgroups per CU
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||
       hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields * kClasses) != hipSuccess ||
       hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl * kClasses) != hipSuccess ||
-      hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     free_batch(b);
@@ -448,7 +618,7 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
     const hcg_field_data& d = data[f];
     fresh[f] = make_field_args(b->plans[f], d);
     vecs[f] = fresh[f].vec;
-    clss[f] = field_class(d);
+    clss[f] = field_class(d, vecs[f] != 0);
     if (!layout_changed && (b->built_C[f] != d.nchan || b->built_vec[f] != vecs[f] ||
                             b->built_cls[f] != clss[f]))
       layout_changed = true;
@@ -467,47 +637,58 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
   }
   hcg_status st;
   if (!b->tuned) {
-    if (b->opts.chan_tile) {
-      b->qw = b->opts.chan_tile / 256;
-      b->cost_order = 1;
-    } else {
-      const std::string sig = batch_signature(b, data);
-      int q = 0, o = 0;
-      if (tune_cache_lookup(sig, &q, &o)) {
-        b->qw = q;
-        b->cost_order = o;
-      } else {
-        const int cfg[4][2] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}};
-        double best = 1e300;
-        hipEvent_t e0, e1;
-        HCG_HIP(hipEventCreate(&e0));
-        HCG_HIP(hipEventCreate(&e1));
-        for (int k = 0; k < 4; ++k) {
-          st = build_items(b, data, cfg[k][0], cfg[k][1], stream);
-          if (st != HCG_OK) return st;
-          b->qw = cfg[k][0];
-          HCG_HIP(hipEventRecord(e0, stream));
-          st = launch_direct(b, stream);
-          if (st != HCG_OK) return st;
-          HCG_HIP(hipEventRecord(e1, stream));
-          HCG_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          HCG_HIP(hipEventElapsedTime(&ms, e0, e1));
-          b->tune_ms[k] = ms;
-          if (ms < best) { best = ms; q = cfg[k][0]; o = cfg[k][1]; }
+    // the configurations the options leave open: slab width x field order x
+    // launch strategy, each timed once on this batch
+    const int fixed_strategy = (b->opts.flags & HCG_BATCH_PERSISTENT) ? kLaunchPersistent
+                               : (b->opts.flags & HCG_BATCH_ITEMS)    ? kLaunchItems
+                                                                      : -1;
+    int cfg[8][3], ncfg = 0;
+    for (int l = 0; l < 2; ++l)
+      for (int o = 1; o >= 0; --o)
+        for (int q = 1; q <= 2; ++q) {
+          if (fixed_strategy >= 0 && l != fixed_strategy) continue;
+          if (b->opts.chan_tile && (q != b->opts.chan_tile / 256 || o != 1)) continue;
+          cfg[ncfg][0] = q;
+          cfg[ncfg][1] = o;
+          cfg[ncfg][2] = l;
+          ++ncfg;
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        b->qw = q;
-        b->cost_order = o;
-        tune_cache_store(sig, q, o);
+    const std::string sig = batch_signature(b, data);
+    int q = cfg[0][0], o = cfg[0][1], l = cfg[0][2];
+    if (ncfg > 1 && !tune_cache_lookup(sig, &q, &o, &l)) {
+      double best = 1e300;
+      hipEvent_t e0, e1;
+      HCG_HIP(hipEventCreate(&e0));
+      HCG_HIP(hipEventCreate(&e1));
+      for (int k = 0; k < ncfg; ++k) {
+        st = build_items(b, data, cfg[k][0], cfg[k][1], cfg[k][2], stream);
+        if (st != HCG_OK) return st;
+        b->qw = cfg[k][0];
+        b->strategy = cfg[k][2];
+        HCG_HIP(hipEventRecord(e0, stream));
+        st = launch_direct(b, stream);
+        if (st != HCG_OK) return st;
+        HCG_HIP(hipEventRecord(e1, stream));
+        HCG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HCG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        // slot: strategy * 4 + (order ? 0 : 2) + (qw - 1)
+        b->tune_ms[cfg[k][2] * 4 + (cfg[k][1] ? 0 : 2) + (cfg[k][0] - 1)] = ms;
+        if (ms < best) { best = ms; q = cfg[k][0]; o = cfg[k][1]; l = cfg[k][2]; }
       }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      tune_cache_store(sig, q, o, l);
     }
+    b->qw = q;
+    b->cost_order = o;
+    b->strategy = l;
     b->tuned = true;
   }
-  const bool rebuilt = b->built_qw != b->qw || b->built_order != b->cost_order;
+  const bool rebuilt = b->built_qw != b->qw || b->built_order != b->cost_order ||
+                       b->built_strategy != b->strategy;
   if (rebuilt) {
-    st = build_items(b, data, b->qw, b->cost_order, stream);
+    st = build_items(b, data, b->qw, b->cost_order, b->strategy, stream);
     if (st != HCG_OK) return st;
   }
   // the graph holds one launch per class with items: capture again when the
@@ -515,6 +696,7 @@ extern "C" hcg_status hcg_grid_batch(hcg_batch_t batch, const hcg_field_data* da
   if (!b->exec || b->graph_qw != b->qw || rebuilt) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (!b->cap_stream) HCG_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HCG_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     st = launch_direct(b, b->cap_stream);
     hipGraph_t g = nullptr;
@@ -558,6 +740,7 @@ extern "C" hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info
   for (int c = 0; c < kClasses; ++c) items += batch->nitems[c];
   info->items = items;
   info->persistent_blocks = batch->nblocks;
-  for (int k = 0; k < 4; ++k) info->tune_ms[k] = batch->tune_ms[k];
+  info->launch = batch->strategy;
+  for (int k = 0; k < 8; ++k) info->tune_ms[k] = batch->tune_ms[k];
   return HCG_OK;
 }

@@ -543,11 +543,29 @@ static int bit_length(uint32_t v) {
   return b;
 }
 
-// Owns device allocations until released.
+// Owns a device allocation until released.  Scratch that lives only for
+// one call is stream-ordered (alloc_async): hipFree would synchronise the
+// whole device, which serialises plans built on several streams at once.
 struct DevBuf {
   void* p = nullptr;
-  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipStream_t s = nullptr;
+  bool async = false;
+  ~DevBuf() {
+    if (!p) return;
+    if (async) (void)hipFreeAsync(p, s);
+    else (void)hipFree(p);
+  }
   void* release() { void* q = p; p = nullptr; return q; }
+  hipError_t alloc_async(size_t bytes, hipStream_t stream) {
+    const hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    s = stream;
+    async = true;
+    return e;
+  }
 };
 
 }  // namespace hcg
@@ -564,7 +582,7 @@ extern "C" hcg_status hcg_ang2pix(const double* lon_deg, const double* lat_deg, 
   if (st != HCG_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
   DevBuf stat;
-  HCG_HIP(hipMalloc(&stat.p, 16));
+  HCG_HIP(stat.alloc_async(16, stream));
   st = launch_ang2pix(lon_deg, lat_deg, n, nside, pix, (uint32_t*)stat.p, stream);
   if (st != HCG_OK) return st;
   uint32_t h[4];
@@ -586,7 +604,7 @@ extern "C" hcg_status hcg_sort_keys(const uint32_t* keys_in, int64_t n, int32_t 
   if (n == 0) return HCG_OK;
   hipStream_t stream = (hipStream_t)hip_stream;
   DevBuf temp;
-  HCG_HIP(hipMalloc(&temp.p, radix_sort_temp_bytes(n)));
+  HCG_HIP(temp.alloc_async(radix_sort_temp_bytes(n), stream));
   st = launch_radix_sort(keys_in, n, key_bits, keys_out, perm_out, temp.p, stream);
   if (st != HCG_OK) return st;
   HCG_HIP(hipStreamSynchronize(stream));
@@ -701,9 +719,9 @@ hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_
   // also the cell vectors and the tile caps, whose largest radius sizes the
   // candidate-range slots
   DevBuf pixbuf, statbuf, cellbuf, capbuf;
-  HCG_HIP(hipMalloc(&pixbuf.p, sizeof(uint32_t) * n));
-  HCG_HIP(hipMalloc(&statbuf.p, 32));
-  if (hipMalloc(&cellbuf.p, sizeof(double4) * ncell) != hipSuccess) {
+  HCG_HIP(pixbuf.alloc_async(sizeof(uint32_t) * n, stream));
+  HCG_HIP(statbuf.alloc_async(32, stream));
+  if (cellbuf.alloc_async(sizeof(double4) * ncell, stream) != hipSuccess) {
     (void)hipGetLastError();
     return fail(HCG_E_NOMEM, "%s: cannot allocate the cell vectors", who);
   }
@@ -717,7 +735,7 @@ hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_
   } else {
     k_cell_vecs_arrays<<<cell_blocks, 256, 0, stream>>>(tg.clon, tg.clat, ncell, cells);
     HCG_LAUNCH_CHECK("k_cell_vecs_arrays");
-    HCG_HIP(hipMalloc(&capbuf.p, sizeof(double4) * ntiles));
+    HCG_HIP(capbuf.alloc_async(sizeof(double4) * ntiles, stream));
     HCG_HIP(hipMemsetAsync((char*)statbuf.p + 16, 0, 8, stream));
     k_tile_caps<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
         cells, nx, ny, ntx, nty, (double4*)capbuf.p,
@@ -775,7 +793,7 @@ hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_
     return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes for the plan", who, arena_bytes);
   }
   const size_t temp_bytes = radix_sort_temp_bytes(n) + align256(sizeof(uint32_t) * n);
-  if (hipMalloc(&temp.p, temp_bytes) != hipSuccess) {
+  if (temp.alloc_async(temp_bytes, stream) != hipSuccess) {
     (void)hipGetLastError();
     return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes of scratch", who, temp_bytes);
   }

@@ -1,7 +1,8 @@
-"""GPU tests of the batched form: many maps of uneven size in one persistent,
-graph-captured launch.  Every field must match the FP64 oracle (1e-5) and the
-single-field hcg_grid of the same plan; replays of the captured graph, with
-eager work and synchronisation between them, must each match the eager
+"""GPU tests of the batched form: many maps of uneven size in one
+graph-captured launch (persistent kernels, or one workgroup per work item).
+Every field must match the FP64 oracle (1e-5) and the single-field hcg_grid
+of the same plan under either launch strategy; replays of the captured graph,
+with eager work and synchronisation between them, must each match the eager
 result; changed pointers and channel counts must be picked up; the autotuned
 and the fixed configurations must give the same cubes."""
 import ctypes
@@ -33,9 +34,9 @@ def _fields():
     ]
 
 
-def _plan(ws, chan_tile=0):
+def _plan(ws, chan_tile=0, launch="auto"):
     return hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
-                               for w in ws], chan_tile=chan_tile)
+                               for w in ws], chan_tile=chan_tile, launch=launch)
 
 
 def _outputs(ws):
@@ -54,15 +55,18 @@ def _single(w):
     return cube.cpu().numpy(), W.cpu().numpy()
 
 
-def test_batch_matches_oracle_and_single_calls():
+@pytest.mark.parametrize("launch", ["auto", "persistent", "items"])
+def test_batch_matches_oracle_and_single_calls(launch):
     ws = _fields()
-    b = _plan(ws)
+    b = _plan(ws, launch=launch)
     spectra = [w.spectra.to(DEV).contiguous() for w in ws]
     cubes, wts = _outputs(ws)
     hcg.hcg_grid_batch(b, spectra, cubes, wts)
     torch.cuda.synchronize()
     info = b.info()
     assert info["tuned"] == 1 and info["graph_captured"] == 1 and info["nfields"] == len(ws)
+    if launch != "auto":
+        assert info["launch"] == (0 if launch == "persistent" else 1)
     for w, cube, W in zip(ws, cubes, wts):
         V, Wb = cube.cpu().numpy(), W.cpu().numpy()
         Vr, Wr, _ = run_oracle(w)
@@ -114,8 +118,8 @@ def test_fixed_configurations_agree_with_autotuned(chan_tile):
     ws = _fields()[3:]
     spectra = [w.spectra.to(DEV).contiguous() for w in ws]
     outs = []
-    for ct in (0, chan_tile):
-        b = _plan(ws, chan_tile=ct)
+    for ct, launch in ((0, "auto"), (chan_tile, "persistent"), (chan_tile, "items")):
+        b = _plan(ws, chan_tile=ct, launch=launch)
         cubes, wts = _outputs(ws)
         hcg.hcg_grid_batch(b, spectra, cubes, wts)
         torch.cuda.synchronize()
@@ -123,8 +127,9 @@ def test_fixed_configurations_agree_with_autotuned(chan_tile):
         if ct:
             assert b.info()["chan_slab"] == ct
         b.destroy()
-    for a, c in zip(*outs):
-        assert np.array_equal(a, c, equal_nan=True)
+    for other in outs[1:]:
+        for a, c in zip(outs[0], other):
+            assert np.array_equal(a, c, equal_nan=True)
 
 
 def test_batch_errors():
@@ -136,6 +141,14 @@ def test_batch_errors():
         hcg.hcg_plan_batch([(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
                             for w in ws], chan_tile=300)
     assert e.value.status == hcg.HCG_E_UNSUPPORTED
+    lon0, lat0 = ws[0].lon.to(DEV), ws[0].lat.to(DEV)
+    fd = (hcg.FieldDescC * 1)()
+    fd[0] = hcg.FieldDescC(lon0.data_ptr(), lat0.data_ptr(), 10, hcg.grid_desc(ws[0].grid),
+                           ws[0].fwhm_deg, ws[0].support_deg)
+    both = hcg.OptsC(0, 0, 0, 0, 0, hcg.HCG_BATCH_PERSISTENT | hcg.HCG_BATCH_ITEMS)
+    assert lib.hcg_plan_batch(ctypes.byref(h), 1, fd, ctypes.byref(both), None) == hcg.HCG_E_UNSUPPORTED
+    other = hcg.OptsC(0, 0, 0, 0, 0, 4)
+    assert lib.hcg_plan_batch(ctypes.byref(h), 1, fd, ctypes.byref(other), None) == hcg.HCG_E_UNSUPPORTED
     bad_lat = ws[1].lat.to(DEV).clone()
     bad_lat[5] = 95.0
     with pytest.raises(hcg.HcgError, match="field 1"):
@@ -158,7 +171,8 @@ _MIXED = [(hcg.HCG_F32, 1e-5), (hcg.HCG_F16_SCALED, 1e-3), (hcg.HCG_BF16_SPLIT, 
           (hcg.HCG_F32, 1e-5), (hcg.HCG_F16_SCALED, 1e-3)]
 
 
-def test_mixed_form_batch_matches_oracle_and_single_calls():
+@pytest.mark.parametrize("launch", ["persistent", "items"])
+def test_mixed_form_batch_matches_oracle_and_single_calls(launch):
     """Fields in every storage form in one batch: each matches the oracle at
     its form's budget and the single hcg_grid call of that form; replays
     after changed data agree."""
@@ -178,7 +192,7 @@ def test_mixed_form_batch_matches_oracle_and_single_calls():
             enc, sc = hcg.hcg_quantize(s, f)
             spectra.append(enc)
             scales.append(sc)
-    b = _plan(ws)
+    b = _plan(ws, launch=launch)
     cubes, wts = _outputs(ws)
     hcg.hcg_grid_batch(b, spectra, cubes, wts, dtypes=forms, chan_scales=scales)
     torch.cuda.synchronize()
