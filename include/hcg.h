@@ -546,8 +546,9 @@ typedef struct {
  *           opts->flags may fix the launch strategy (HCG_BATCH_PERSISTENT
  *           or HCG_BATCH_ITEMS); nside and tile fields apply to every field
  *           as in hcg_plan.
- * The plans are built by up to eight host threads, each on a stream of its
- * own (kept by the library for later calls) that first waits for hip_stream.
+ * The plans are built step by step for all fields at once, on up to eight
+ * streams of the library (kept for later calls) that first wait for
+ * hip_stream, with one host synchronisation per build step.
  * Synchronous.  Errors as hcg_plan, with the failing field named in the
  * message (HCG_E_UNSUPPORTED for other flags); nothing leaks on failure.
  */

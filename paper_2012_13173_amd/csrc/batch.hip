@@ -22,9 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
-#include <atomic>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "gather_tile.h"
@@ -38,7 +36,7 @@ namespace hcg {
 // persistent kernel compiles one gather path, which keeps it in the
 // registers of two workgroups per CU.
 constexpr int kClsCells = 6;
-constexpr int kPlanThreads = 8;  // host threads building the plans of a batch
+constexpr int kPlanStreams = 8;  // streams the plans of a batch are built on
 constexpr int kClsScalarRows = 7;
 constexpr int kClasses = 13;
 
@@ -503,15 +501,18 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
     free_batch(b);
     return fail(HCG_E_DEVICE, "hcg_plan_batch: device query failed");
   }
-  // The plans are built by up to kPlanThreads host threads, each on a stream
-  // of its own that first waits for the caller's stream (where the
-  // coordinates were written): a plan is a chain of short kernels with a few
-  // host reads, so one plan at a time leaves the GPU mostly idle, and plans
-  // of different fields overlap.  Fields go to the threads largest first.
-  b->plans.assign(nfields, nullptr);
-  b->ncand.resize(nfields);
-  std::vector<hcg_status> fst(nfields, HCG_OK);
-  std::vector<std::string> fmsg(nfields);
+  // The plans are built step by step for all fields at once (plan_build_many:
+  // one host synchronisation per build step, not several per field), field
+  // f on the f % kPlanStreams-th of the library's streams, which first wait
+  // for the caller's stream (where the coordinates were written); the
+  // fields' short kernels then overlap.
+  std::vector<hipStream_t> wstreams;
+  const int nstreams = std::max(1, std::min<int>(kPlanStreams, nfields));
+  st = plan_streams(b->device, nstreams, &wstreams);
+  if (st != HCG_OK) {
+    free_batch(b);
+    return st;
+  }
   hipEvent_t ready = nullptr;
   if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(ready, stream) != hipSuccess) {
@@ -519,56 +520,32 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
     free_batch(b);
     return fail(HCG_E_DEVICE, "hcg_plan_batch: event on the caller's stream failed");
   }
-  std::vector<int32_t> order(nfields);
-  for (int32_t f = 0; f < nfields; ++f) order[f] = f;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return fields[x].n > fields[y].n; });
-  const int nthreads = std::max(1, std::min<int>(kPlanThreads, nfields));
-  std::vector<hipStream_t> wstreams;
-  st = plan_streams(b->device, nthreads, &wstreams);
-  if (st != HCG_OK) {
-    (void)hipEventDestroy(ready);
-    free_batch(b);
-    return st;
-  }
-  std::atomic<int32_t> next{0};
-  auto worker = [&](int t) {
-    if (hipSetDevice(b->device) != hipSuccess) return;
-    hipStream_t ws = wstreams[t];
-    if (hipStreamWaitEvent(ws, ready, 0) == hipSuccess) {
-      for (int32_t k; (k = next.fetch_add(1)) < nfields;) {
-        const int32_t f = order[k];
-        const hcg_field_desc& d = fields[f];
-        hcg_plan_t p = nullptr;
-        hcg_status s2 = hcg_plan(&p, d.lon_deg, d.lat_deg, d.n, &d.grid, d.fwhm_deg,
-                                 d.support_deg, &po, ws);
-        if (s2 == HCG_OK) {
-          const size_t nt = (size_t)p->ntx * p->nty;
-          b->ncand[f].resize(nt);
-          if (hipMemcpyAsync(b->ncand[f].data(), p->ncand, sizeof(uint32_t) * nt,
-                             hipMemcpyDeviceToHost, ws) != hipSuccess ||
-              hipStreamSynchronize(ws) != hipSuccess) {
-            s2 = fail(HCG_E_DEVICE, "reading candidate counts failed");
-          }
-        }
-        b->plans[f] = p;
-        fst[f] = s2;
-        if (s2 != HCG_OK) fmsg[f] = hcg_last_error();
-      }
-    }
-    (void)hipStreamSynchronize(ws);
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nthreads; ++t) pool.emplace_back(worker, t);
-  worker(0);
-  for (std::thread& t : pool) t.join();
-  (void)hipEventDestroy(ready);
-  for (int32_t f = 0; f < nfields; ++f) {
-    if (fst[f] != HCG_OK || !b->plans[f]) {
-      const hcg_status fs = fst[f] != HCG_OK ? fst[f] : HCG_E_DEVICE;
-      const std::string msg = fst[f] != HCG_OK ? fmsg[f] : "no plan was built";
+  for (hipStream_t ws : wstreams) {
+    if (hipStreamWaitEvent(ws, ready, 0) != hipSuccess) {
+      (void)hipEventDestroy(ready);
       free_batch(b);
-      return fail(fs, "hcg_plan_batch: field %d: %s", f, msg.c_str());
+      return fail(HCG_E_DEVICE, "hcg_plan_batch: stream wait failed");
+    }
+  }
+  b->plans.assign(nfields, nullptr);
+  int32_t failed = -1;
+  st = plan_build_many(nfields, fields, &po, wstreams.data(), nstreams, b->plans.data(), &failed);
+  (void)hipEventDestroy(ready);
+  if (st != HCG_OK) {
+    const std::string msg = hcg_last_error();
+    free_batch(b);
+    return fail(st, "hcg_plan_batch: field %d: %s", failed, msg.c_str());
+  }
+  // candidate counts per tile (the work-item costs)
+  b->ncand.resize(nfields);
+  for (int32_t f = 0; f < nfields; ++f) {
+    const hcg_plan_s* p = b->plans[f];
+    const size_t nt = (size_t)p->ntx * p->nty;
+    b->ncand[f].resize(nt);
+    if (hipMemcpy(b->ncand[f].data(), p->ncand, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      free_batch(b);
+      return fail(HCG_E_DEVICE, "hcg_plan_batch: reading candidate counts failed");
     }
   }
   b->nblocks = 2 * cus;  // two 256-thread workgroups per CU

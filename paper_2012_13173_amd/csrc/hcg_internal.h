@@ -260,6 +260,9 @@ struct BatchSeg {
 };
 constexpr int kBatchXcds = 8;
 constexpr int kBatchCtl = 16;
+hcg_status plan_build_many(int32_t nfields, const hcg_field_desc* fields, const hcg_opts* opts,
+                           const hipStream_t* streams, int nstreams, hcg_plan_t* plans,
+                           int32_t* failed);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
                              uint32_t* perm_out, void* temp, hipStream_t stream);
 

@@ -687,198 +687,325 @@ hcg_status kernel_params(const hcg_kernel* k, const char* who, KernelParams* kp,
   }
 }
 
+// A plan is built in three steps with a host read between them: begin (cell
+// vectors and the samples' pixels, whose range comes back to the host),
+// middle (the sizes from that range; the sorted samples, ring table and tile
+// ranges; an overflow flag comes back) and finish (the flag checked, the
+// plan registered).  hcg_plan runs the steps with a stream synchronisation
+// after each; hcg_plan_batch runs each step for every field and
+// synchronises once per step.  host: 64 bytes of host memory that the
+// device writes between the steps (page-locked for the batch).
+struct PlanBuilder {
+  const char* who = "";
+  const double* lon_deg = nullptr;
+  const double* lat_deg = nullptr;
+  int64_t n = 0;
+  PlanTarget tg{};
+  double support_deg = 0.0;
+  KernelParams kp{};
+  double sigma = 0.0, fwhm_nominal = 0.0;
+  int nside = 0;
+  hipStream_t stream = nullptr;
+  uint32_t* host = nullptr;  // [0..7] pixel stats, [8..11] flags
+  int nx = 0, ny = 0, ntx = 0, nty = 0;
+  int64_t ntiles = 0, ncell = 0;
+  double R = 0.0;
+  DevBuf pixbuf, statbuf, cellbuf, capbuf, arena, temp;
+  hcg_plan_s* p = nullptr;
+
+  ~PlanBuilder() { delete p; }
+
+  hcg_status begin(const double* lon, const double* lat, int64_t n_, const PlanTarget& tg_,
+                   const hcg_kernel* kernel, double support, const hcg_opts* opts,
+                   hipStream_t s, uint32_t* host_, const char* who_) {
+    who = who_;
+    lon_deg = lon;
+    lat_deg = lat;
+    n = n_;
+    tg = tg_;
+    support_deg = support;
+    stream = s;
+    host = host_;
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(HCG_E_ARG, "%s: n must be in 1..2^31-1", who);
+    if (!(support_deg >= 0.0) || !(support_deg < 90.0))
+      return fail(HCG_E_ARG, "%s: support must be in [0, 90) degrees", who);
+    hcg_status st = kernel_params(kernel, who, &kp, &sigma, &fwhm_nominal);
+    if (st != HCG_OK) return st;
+    hcg_opts o = {};
+    if (opts) o = *opts;
+    if ((o.tile_x && o.tile_x != kTileX) || (o.tile_y && o.tile_y != kTileY))
+      return fail(HCG_E_UNSUPPORTED, "%s: only 8 x 8 cell tiles are built", who);
+    if (o.coarsen || o.chan_tile || o.flags)
+      return fail(HCG_E_UNSUPPORTED, "%s: coarsen, chan_tile and flags must be 0", who);
+    nside = o.nside ? o.nside : auto_nside(sigma);
+    if (!is_pow2(nside) || nside > 16384)
+      return fail(HCG_E_ARG, "%s: nside %d is not a power of two in 1..16384", who, nside);
+    st = check_device_arch();
+    if (st != HCG_OK) return st;
+    nx = tg.grid ? tg.grid->nx : tg.nx;
+    ny = tg.grid ? tg.grid->ny : tg.ny;
+    ntx = (nx + kTileX - 1) / kTileX;
+    nty = (ny + kTileY - 1) / kTileY;
+    ntiles = (int64_t)ntx * nty;
+    ncell = (int64_t)nx * ny;
+    R = support_deg * kDeg2Rad;
+
+    // pixels and their range; for centre arrays also the cell vectors and
+    // the tile caps, whose largest radius sizes the candidate-range slots
+    HCG_HIP(pixbuf.alloc_async(sizeof(uint32_t) * n, stream));
+    HCG_HIP(statbuf.alloc_async(32, stream));
+    if (cellbuf.alloc_async(sizeof(double4) * ncell, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HCG_E_NOMEM, "%s: cannot allocate the cell vectors", who);
+    }
+    double4* cells = (double4*)cellbuf.p;
+    const unsigned cell_blocks = (unsigned)((ncell + 255) / 256);
+    if (tg.grid) {
+      const GridGeom gg{tg.grid->nx, tg.grid->ny, tg.grid->lon0_deg, tg.grid->lat0_deg,
+                        tg.grid->dlon_deg, tg.grid->dlat_deg};
+      k_cell_vecs_linear<<<cell_blocks, 256, 0, stream>>>(gg, cells);
+      HCG_LAUNCH_CHECK("k_cell_vecs_linear");
+    } else {
+      k_cell_vecs_arrays<<<cell_blocks, 256, 0, stream>>>(tg.clon, tg.clat, ncell, cells);
+      HCG_LAUNCH_CHECK("k_cell_vecs_arrays");
+      HCG_HIP(capbuf.alloc_async(sizeof(double4) * ntiles, stream));
+      HCG_HIP(hipMemsetAsync((char*)statbuf.p + 16, 0, 8, stream));
+      k_tile_caps<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
+          cells, nx, ny, ntx, nty, (double4*)capbuf.p,
+          (unsigned long long*)((char*)statbuf.p + 16));
+      HCG_LAUNCH_CHECK("k_tile_caps");
+    }
+    st = launch_ang2pix(lon_deg, lat_deg, n, nside, (uint32_t*)pixbuf.p, (uint32_t*)statbuf.p,
+                        stream);
+    if (st != HCG_OK) return st;
+    HCG_HIP(hipMemcpyAsync(host, statbuf.p, 32, hipMemcpyDeviceToHost, stream));
+    return HCG_OK;
+  }
+
+  // after the pixel statistics have reached host[0..7]
+  hcg_status middle() {
+    const uint32_t* hs = host;
+    if (hs[2]) return fail(HCG_E_ARG, "%s: %u sample coordinates are non-finite or |lat| > 90", who, hs[2]);
+    const uint32_t pix_base = hs[0], pix_max = hs[1];
+    const int ring_first = (int)hpx_pix2ring(nside, pix_base);
+    const int ring_last = (int)hpx_pix2ring(nside, pix_max);
+    const int nrings = ring_last - ring_first + 1;
+    const int key_bits = bit_length(pix_max - pix_base);
+
+    // candidate-range slots per tile: rings in the tile's latitude span + 2R,
+    // two ranges per ring; rings are at least 2/(3 Ns) apart in latitude
+    double tile_span = 0.0;
+    if (tg.grid) {
+      tile_span = (kTileY - 1) * std::fabs(tg.grid->dlat_deg) * kDeg2Rad;
+    } else {
+      double rmax = 0.0;
+      memcpy(&rmax, &hs[4], sizeof(double));
+      tile_span = 2.0 * std::min(rmax, kPi);
+    }
+    const double rings_d = (tile_span + 2.0 * R) / (2.0 / (3.0 * nside)) + 6.0;
+    if (rings_d > kMaxRangesLimit / 2)
+      return fail(HCG_E_UNSUPPORTED,
+                  "%s: support or tile too wide for nside %d (%.0f rings per tile; at most %d)", who,
+                  nside, rings_d, kMaxRangesLimit / 2);
+    const int maxr = 2 * (int)std::ceil(rings_d);
+
+    // plan arena
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
+    // xyz carries eight sentinel entries from n (NaN vectors) and perm one
+    // (row 0): the gather reads them for candidate lists widened to whole
+    // groups of 8 sorted positions
+    const size_t o_xyz = take(sizeof(double4) * (n + 8));
+    const size_t o_keys = take(sizeof(uint32_t) * n);
+    const size_t o_perm = take(sizeof(uint32_t) * (n + 1));
+    const size_t o_csr = take(sizeof(uint32_t) * (nrings + 1));
+    const size_t o_rng = take(sizeof(uint2) * (size_t)ntiles * maxr);
+    const size_t o_nr = take(sizeof(uint32_t) * ntiles);
+    const size_t o_nc = take(sizeof(uint32_t) * ntiles);
+    const size_t o_flags = take(16);
+    const size_t o_cells = take(sizeof(double4) * ncell);
+    const size_t arena_bytes = off;
+    if (hipMalloc(&arena.p, arena_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      arena.p = nullptr;
+      return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes for the plan", who, arena_bytes);
+    }
+    const size_t temp_bytes = radix_sort_temp_bytes(n) + align256(sizeof(uint32_t) * n);
+    if (temp.alloc_async(temp_bytes, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes of scratch", who, temp_bytes);
+    }
+    char* A = (char*)arena.p;
+    p = new hcg_plan_s{};
+    p->magic = kPlanMagic;
+    HCG_HIP(hipGetDevice(&p->device));
+    p->n = n;
+    p->nside = nside;
+    p->pix_base = pix_base;
+    p->pix_max = pix_max;
+    p->key_bits = key_bits;
+    p->passes = (key_bits + 7) / 8;
+    p->ring_first = ring_first;
+    p->ring_last = ring_last;
+    if (tg.grid)
+      p->grid = GridGeom{tg.grid->nx, tg.grid->ny, tg.grid->lon0_deg, tg.grid->lat0_deg,
+                         tg.grid->dlon_deg, tg.grid->dlat_deg};
+    else
+      p->grid = GridGeom{nx, ny, 0.0, 0.0, 0.0, 0.0};
+    p->centres = tg.grid ? 0 : 1;
+    p->fwhm_deg = fwhm_nominal;
+    p->support_deg = support_deg;
+    p->sigma_rad = sigma;
+    p->support_rad = R;
+    p->kern = kp;
+    p->ntx = ntx;
+    p->nty = nty;
+    p->maxr = maxr;
+    p->arena_bytes = arena_bytes;
+    p->xyz = (double4*)(A + o_xyz);
+    p->keys = (uint32_t*)(A + o_keys);
+    p->perm = (uint32_t*)(A + o_perm);
+    p->csr = (uint32_t*)(A + o_csr);
+    p->ranges = (uint2*)(A + o_rng);
+    p->nranges = (uint32_t*)(A + o_nr);
+    p->ncand = (uint32_t*)(A + o_nc);
+    p->flags = (uint32_t*)(A + o_flags);
+    p->cells = (double4*)(A + o_cells);
+
+    HCG_HIP(hipMemcpyAsync(p->cells, cellbuf.p, sizeof(double4) * ncell, hipMemcpyDeviceToDevice,
+                           stream));
+    // keys relative to the smallest pixel, then the stable sort
+    uint32_t* rel = (uint32_t*)((char*)temp.p + radix_sort_temp_bytes(n));
+    k_rel_keys<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>((const uint32_t*)pixbuf.p,
+                                                                 pix_base, n, rel);
+    HCG_LAUNCH_CHECK("k_rel_keys");
+    hcg_status st =
+        launch_radix_sort(rel, n, key_bits == 0 ? 1 : key_bits, p->keys, p->perm, temp.p, stream);
+    if (st != HCG_OK) return st;
+    k_permute_xyz<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(lon_deg, lat_deg, p->perm, n,
+                                                                  p->xyz);
+    HCG_LAUNCH_CHECK("k_permute_xyz");
+    HCG_HIP(hipMemsetAsync(p->xyz + n, 0xFF, 8 * sizeof(double4), stream));  // all-ones: NaN
+    HCG_HIP(hipMemsetAsync(p->perm + n, 0, sizeof(uint32_t), stream));
+    k_ring_csr<<<(unsigned)((nrings + 1 + 255) / 256), 256, 0, stream>>>(
+        p->keys, n, nside, ring_first, nrings, pix_base, p->csr);
+    HCG_LAUNCH_CHECK("k_ring_csr");
+    HCG_HIP(hipMemsetAsync(p->flags, 0, 16, stream));
+    if (tg.grid) {
+      k_tile_ranges<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
+          p->keys, p->csr, nside, ring_first, ring_last, pix_base, p->grid, ntx, nty, R, maxr,
+          p->ranges, p->nranges, p->ncand, p->flags);
+      HCG_LAUNCH_CHECK("k_tile_ranges");
+    } else {
+      k_tile_ranges_cap<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
+          p->keys, p->csr, nside, ring_first, ring_last, pix_base, (const double4*)capbuf.p,
+          (int)ntiles, R, maxr, p->ranges, p->nranges, p->ncand, p->flags);
+      HCG_LAUNCH_CHECK("k_tile_ranges_cap");
+    }
+    HCG_HIP(hipMemcpyAsync(host + 8, p->flags, 16, hipMemcpyDeviceToHost, stream));
+    return HCG_OK;
+  }
+
+  // after the flags have reached host[8..11]
+  hcg_status finish(hcg_plan_t* out) {
+    if (host[8]) return fail(HCG_E_DEVICE, "%s: candidate-range slots overflowed (internal bound)", who);
+    p->arena = arena.release();
+    plan_register(p);
+    *out = p;
+    p = nullptr;
+    return HCG_OK;
+  }
+};
+
 hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_deg, int64_t n,
                       const PlanTarget& tg, const hcg_kernel* kernel, double support_deg,
                       const hcg_opts* opts, void* hip_stream, const char* who) {
-  if (n < 1 || n >= (int64_t(1) << 31)) return fail(HCG_E_ARG, "%s: n must be in 1..2^31-1", who);
-  if (!(support_deg >= 0.0) || !(support_deg < 90.0))
-    return fail(HCG_E_ARG, "%s: support must be in [0, 90) degrees", who);
-  KernelParams kp;
-  double sigma = 0.0, fwhm_nominal = 0.0;
-  hcg_status st = kernel_params(kernel, who, &kp, &sigma, &fwhm_nominal);
-  if (st != HCG_OK) return st;
-  hcg_opts o = {};
-  if (opts) o = *opts;
-  if ((o.tile_x && o.tile_x != kTileX) || (o.tile_y && o.tile_y != kTileY))
-    return fail(HCG_E_UNSUPPORTED, "%s: only 8 x 8 cell tiles are built", who);
-  if (o.coarsen || o.chan_tile || o.flags)
-    return fail(HCG_E_UNSUPPORTED, "%s: coarsen, chan_tile and flags must be 0", who);
-  int nside = o.nside ? o.nside : auto_nside(sigma);
-  if (!is_pow2(nside) || nside > 16384)
-    return fail(HCG_E_ARG, "%s: nside %d is not a power of two in 1..16384", who, nside);
-  st = check_device_arch();
-  if (st != HCG_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
-  const int nx = tg.grid ? tg.grid->nx : tg.nx, ny = tg.grid ? tg.grid->ny : tg.ny;
-  const int ntx = (nx + kTileX - 1) / kTileX, nty = (ny + kTileY - 1) / kTileY;
-  const int64_t ntiles = (int64_t)ntx * nty;
-  const int64_t ncell = (int64_t)nx * ny;
-  const double R = support_deg * kDeg2Rad;
-
-  // pass 1: pixels and their range (one small read-back); for centre arrays
-  // also the cell vectors and the tile caps, whose largest radius sizes the
-  // candidate-range slots
-  DevBuf pixbuf, statbuf, cellbuf, capbuf;
-  HCG_HIP(pixbuf.alloc_async(sizeof(uint32_t) * n, stream));
-  HCG_HIP(statbuf.alloc_async(32, stream));
-  if (cellbuf.alloc_async(sizeof(double4) * ncell, stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HCG_E_NOMEM, "%s: cannot allocate the cell vectors", who);
-  }
-  double4* cells = (double4*)cellbuf.p;
-  const unsigned cell_blocks = (unsigned)((ncell + 255) / 256);
-  if (tg.grid) {
-    const GridGeom gg{tg.grid->nx, tg.grid->ny, tg.grid->lon0_deg, tg.grid->lat0_deg,
-                      tg.grid->dlon_deg, tg.grid->dlat_deg};
-    k_cell_vecs_linear<<<cell_blocks, 256, 0, stream>>>(gg, cells);
-    HCG_LAUNCH_CHECK("k_cell_vecs_linear");
-  } else {
-    k_cell_vecs_arrays<<<cell_blocks, 256, 0, stream>>>(tg.clon, tg.clat, ncell, cells);
-    HCG_LAUNCH_CHECK("k_cell_vecs_arrays");
-    HCG_HIP(capbuf.alloc_async(sizeof(double4) * ntiles, stream));
-    HCG_HIP(hipMemsetAsync((char*)statbuf.p + 16, 0, 8, stream));
-    k_tile_caps<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
-        cells, nx, ny, ntx, nty, (double4*)capbuf.p,
-        (unsigned long long*)((char*)statbuf.p + 16));
-    HCG_LAUNCH_CHECK("k_tile_caps");
-  }
-  st = launch_ang2pix(lon_deg, lat_deg, n, nside, (uint32_t*)pixbuf.p, (uint32_t*)statbuf.p, stream);
+  uint32_t host[16] = {0};
+  PlanBuilder b;
+  hcg_status st = b.begin(lon_deg, lat_deg, n, tg, kernel, support_deg, opts, stream, host, who);
   if (st != HCG_OK) return st;
-  uint32_t hs[8];
-  HCG_HIP(hipMemcpyAsync(hs, statbuf.p, sizeof(hs), hipMemcpyDeviceToHost, stream));
   HCG_HIP(hipStreamSynchronize(stream));
-  if (hs[2]) return fail(HCG_E_ARG, "%s: %u sample coordinates are non-finite or |lat| > 90", who, hs[2]);
-  const uint32_t pix_base = hs[0], pix_max = hs[1];
-  const int ring_first = (int)hpx_pix2ring(nside, pix_base);
-  const int ring_last = (int)hpx_pix2ring(nside, pix_max);
-  const int nrings = ring_last - ring_first + 1;
-  const int key_bits = bit_length(pix_max - pix_base);
-
-  // candidate-range slots per tile: rings in the tile's latitude span + 2R,
-  // two ranges per ring; rings are at least 2/(3 Ns) apart in latitude
-  double tile_span = 0.0;
-  if (tg.grid) {
-    tile_span = (kTileY - 1) * std::fabs(tg.grid->dlat_deg) * kDeg2Rad;
-  } else {
-    double rmax = 0.0;
-    memcpy(&rmax, &hs[4], sizeof(double));
-    tile_span = 2.0 * std::min(rmax, kPi);
-  }
-  const double rings_d = (tile_span + 2.0 * R) / (2.0 / (3.0 * nside)) + 6.0;
-  if (rings_d > kMaxRangesLimit / 2)
-    return fail(HCG_E_UNSUPPORTED,
-                "%s: support or tile too wide for nside %d (%.0f rings per tile; at most %d)", who,
-                nside, rings_d, kMaxRangesLimit / 2);
-  const int maxr = 2 * (int)std::ceil(rings_d);
-
-  // plan arena
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
-  // xyz carries eight sentinel entries from n (NaN vectors) and perm one
-  // (row 0): the gather reads them for candidate lists widened to whole
-  // groups of 8 sorted positions
-  const size_t o_xyz = take(sizeof(double4) * (n + 8));
-  const size_t o_keys = take(sizeof(uint32_t) * n);
-  const size_t o_perm = take(sizeof(uint32_t) * (n + 1));
-  const size_t o_csr = take(sizeof(uint32_t) * (nrings + 1));
-  const size_t o_rng = take(sizeof(uint2) * (size_t)ntiles * maxr);
-  const size_t o_nr = take(sizeof(uint32_t) * ntiles);
-  const size_t o_nc = take(sizeof(uint32_t) * ntiles);
-  const size_t o_flags = take(16);
-  const size_t o_cells = take(sizeof(double4) * ncell);
-  const size_t arena_bytes = off;
-  DevBuf arena, temp;
-  if (hipMalloc(&arena.p, arena_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes for the plan", who, arena_bytes);
-  }
-  const size_t temp_bytes = radix_sort_temp_bytes(n) + align256(sizeof(uint32_t) * n);
-  if (temp.alloc_async(temp_bytes, stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes of scratch", who, temp_bytes);
-  }
-  char* A = (char*)arena.p;
-  auto* p = new hcg_plan_s{};
-  p->magic = kPlanMagic;
-  HCG_HIP(hipGetDevice(&p->device));
-  p->n = n;
-  p->nside = nside;
-  p->pix_base = pix_base;
-  p->pix_max = pix_max;
-  p->key_bits = key_bits;
-  p->passes = (key_bits + 7) / 8;
-  p->ring_first = ring_first;
-  p->ring_last = ring_last;
-  if (tg.grid)
-    p->grid = GridGeom{tg.grid->nx, tg.grid->ny, tg.grid->lon0_deg, tg.grid->lat0_deg,
-                       tg.grid->dlon_deg, tg.grid->dlat_deg};
-  else
-    p->grid = GridGeom{nx, ny, 0.0, 0.0, 0.0, 0.0};
-  p->centres = tg.grid ? 0 : 1;
-  p->fwhm_deg = fwhm_nominal;
-  p->support_deg = support_deg;
-  p->sigma_rad = sigma;
-  p->support_rad = R;
-  p->kern = kp;
-  p->ntx = ntx;
-  p->nty = nty;
-  p->maxr = maxr;
-  p->arena_bytes = arena_bytes;
-  p->xyz = (double4*)(A + o_xyz);
-  p->keys = (uint32_t*)(A + o_keys);
-  p->perm = (uint32_t*)(A + o_perm);
-  p->csr = (uint32_t*)(A + o_csr);
-  p->ranges = (uint2*)(A + o_rng);
-  p->nranges = (uint32_t*)(A + o_nr);
-  p->ncand = (uint32_t*)(A + o_nc);
-  p->flags = (uint32_t*)(A + o_flags);
-  p->cells = (double4*)(A + o_cells);
-  struct PlanGuard {
-    hcg_plan_s* p;
-    ~PlanGuard() { delete p; }
-  } guard{p};
-
-  HCG_HIP(hipMemcpyAsync(p->cells, cells, sizeof(double4) * ncell, hipMemcpyDeviceToDevice,
-                         stream));
-  // keys relative to the smallest pixel, then the stable sort
-  uint32_t* rel = (uint32_t*)((char*)temp.p + radix_sort_temp_bytes(n));
-  k_rel_keys<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>((const uint32_t*)pixbuf.p,
-                                                               pix_base, n, rel);
-  HCG_LAUNCH_CHECK("k_rel_keys");
-  st = launch_radix_sort(rel, n, key_bits == 0 ? 1 : key_bits, p->keys, p->perm, temp.p, stream);
+  st = b.middle();
   if (st != HCG_OK) return st;
-  k_permute_xyz<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(lon_deg, lat_deg, p->perm, n,
-                                                                p->xyz);
-  HCG_LAUNCH_CHECK("k_permute_xyz");
-  HCG_HIP(hipMemsetAsync(p->xyz + n, 0xFF, 8 * sizeof(double4), stream));  // all-ones: NaN
-  HCG_HIP(hipMemsetAsync(p->perm + n, 0, sizeof(uint32_t), stream));
-  k_ring_csr<<<(unsigned)((nrings + 1 + 255) / 256), 256, 0, stream>>>(
-      p->keys, n, nside, ring_first, nrings, pix_base, p->csr);
-  HCG_LAUNCH_CHECK("k_ring_csr");
-  HCG_HIP(hipMemsetAsync(p->flags, 0, 16, stream));
-  if (tg.grid) {
-    k_tile_ranges<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
-        p->keys, p->csr, nside, ring_first, ring_last, pix_base, p->grid, ntx, nty, R, maxr,
-        p->ranges, p->nranges, p->ncand, p->flags);
-    HCG_LAUNCH_CHECK("k_tile_ranges");
-  } else {
-    k_tile_ranges_cap<<<(unsigned)((ntiles + 3) / 4), 256, 0, stream>>>(
-        p->keys, p->csr, nside, ring_first, ring_last, pix_base, (const double4*)capbuf.p,
-        (int)ntiles, R, maxr, p->ranges, p->nranges, p->ncand, p->flags);
-    HCG_LAUNCH_CHECK("k_tile_ranges_cap");
-  }
-  uint32_t fl[4];
-  HCG_HIP(hipMemcpyAsync(fl, p->flags, sizeof(fl), hipMemcpyDeviceToHost, stream));
   HCG_HIP(hipStreamSynchronize(stream));
-  if (fl[0]) return fail(HCG_E_DEVICE, "%s: candidate-range slots overflowed (internal bound)", who);
-  p->arena = arena.release();
-  guard.p = nullptr;
-  plan_register(p);
-  *out = p;
-  return HCG_OK;
+  return b.finish(out);
 }
 
 }  // namespace
+
+namespace hcg {
+
+// Plans of many fields on linear grids (the batch): each build step runs for
+// every field, field f on streams[f % nstreams], with one synchronisation of
+// the streams per step.  On failure *failed is the first failing field and
+// nothing is left allocated.
+hcg_status plan_build_many(int32_t nfields, const hcg_field_desc* fields, const hcg_opts* opts,
+                           const hipStream_t* streams, int nstreams, hcg_plan_t* plans,
+                           int32_t* failed) {
+  *failed = -1;
+  for (int32_t f = 0; f < nfields; ++f) plans[f] = nullptr;
+  uint32_t* host = nullptr;
+  if (hipHostMalloc((void**)&host, sizeof(uint32_t) * 16 * (size_t)nfields) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HCG_E_NOMEM, "cannot allocate page-locked host memory for %d plans", nfields);
+  }
+  struct HostFree {
+    uint32_t* h;
+    ~HostFree() { (void)hipHostFree(h); }
+  } hf{host};
+  std::vector<PlanBuilder> b(nfields);
+  auto sync_all = [&]() -> hcg_status {
+    for (int k = 0; k < std::min<int>(nstreams, nfields); ++k)
+      HCG_HIP(hipStreamSynchronize(streams[k]));
+    return HCG_OK;
+  };
+  hcg_kernel k{};
+  k.type = HCG_KERNEL_GAUSS;
+  for (int32_t f = 0; f < nfields; ++f) {
+    const hcg_field_desc& d = fields[f];
+    hcg_status st = HCG_OK;
+    if (!d.lon_deg || !d.lat_deg) st = fail(HCG_E_ARG, "hcg_plan: NULL pointer");
+    if (st == HCG_OK) st = check_grid(&d.grid, "hcg_plan");
+    if (st == HCG_OK) {
+      k.fwhm_deg = d.fwhm_deg;
+      const PlanTarget tg{&d.grid, nullptr, nullptr, d.grid.nx, d.grid.ny};
+      st = b[f].begin(d.lon_deg, d.lat_deg, d.n, tg, &k, d.support_deg, opts,
+                      streams[f % nstreams], host + 16 * (size_t)f, "hcg_plan");
+    }
+    if (st != HCG_OK) {
+      *failed = f;
+      (void)sync_all();
+      return st;
+    }
+  }
+  hcg_status st = sync_all();
+  if (st != HCG_OK) return st;
+  for (int32_t f = 0; f < nfields; ++f) {
+    st = b[f].middle();
+    if (st != HCG_OK) {
+      *failed = f;
+      (void)sync_all();
+      return st;
+    }
+  }
+  st = sync_all();
+  if (st != HCG_OK) return st;
+  for (int32_t f = 0; f < nfields; ++f) {
+    st = b[f].finish(&plans[f]);
+    if (st != HCG_OK) {
+      *failed = f;
+      for (int32_t g = 0; g < f; ++g) {
+        (void)hcg_destroy(plans[g]);
+        plans[g] = nullptr;
+      }
+      return st;
+    }
+  }
+  return HCG_OK;
+}
+
+}  // namespace hcg
 
 extern "C" hcg_status hcg_plan(hcg_plan_t* out, const double* lon_deg, const double* lat_deg,
                                int64_t n, const hcg_grid_desc* grid, double fwhm_deg,
