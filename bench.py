@@ -51,7 +51,19 @@ PAPER_CONTEXT = {"cpu_hours_per_TB": 21.0, "cpu_cores": 16,
                  "sample_channel_updates_per_s": 2.5e11 / (21.0 * 3600.0),
                  "note": "context only (the paper's multi-core CPU gridding of FAST data, "
                          "wall-clock reading; not a measurement of this build)"}
-GATHER_SRC = os.path.join(ROOT, "paper_2012_13173_amd", "csrc", "gather.hip")
+# the sources the gather kernels are compiled from: a traffic record taken on
+# other versions of them is not used
+GATHER_SRCS = [os.path.join(ROOT, "paper_2012_13173_amd", "csrc", f)
+               for f in ("gather.hip", "gather_tile.h", "sphere.h", "hcg_internal.h")]
+
+
+def gather_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for path in GATHER_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload, kernel="f32"):
@@ -60,15 +72,12 @@ def measured_traffic(workload, kernel="f32"):
     (profiles/traffic_<workload>.json: FETCH_SIZE x its copy-kernel factor +
     WRITE_SIZE), or None if it was taken on another version of the kernel
     source."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(GATHER_SRC, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("gather_source_sha256") != sha:
+    if rec.get("gather_source_sha256") != gather_source_sha256():
         return None
     k = rec.get("kernels", {}).get(kernel)
     return float(k["hbm_bytes_per_launch"]) if k else None
