@@ -36,7 +36,6 @@ namespace hcg {
 // persistent kernel compiles one gather path, which keeps it in the
 // registers of two workgroups per CU.
 constexpr int kClsCells = 6;
-constexpr int kPlanStreams = 8;  // streams the plans of a batch are built on
 constexpr int kClsScalarRows = 7;
 constexpr int kClasses = 13;
 
@@ -267,6 +266,7 @@ struct hcg_batch_s {
   int device = 0;
   int nblocks = 0;
   std::vector<hcg_plan_t> plans;
+  void* arena = nullptr;  // the plans' arrays (plan_build_fields)
   std::vector<std::vector<uint32_t>> ncand;  // per field, per tile
   hcg_opts opts{};
   GatherArgs* d_fields = nullptr;  // [nfields]
@@ -297,29 +297,6 @@ namespace {
 std::mutex g_batch_mu;
 std::vector<const hcg_batch_s*> g_batches;
 
-// Streams of the threads that build a batch's plans: made once per device
-// (creating a stream costs milliseconds) and kept until the process ends.
-constexpr int kMaxPoolDevices = 64;
-std::mutex g_pool_mu;
-std::vector<hipStream_t> g_pool[kMaxPoolDevices];
-
-// The first n worker streams of `dev` (the current device).
-hcg_status plan_streams(int dev, int n, std::vector<hipStream_t>* out) {
-  if (dev < 0 || dev >= kMaxPoolDevices)
-    return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: device %d is beyond the %d served", dev,
-                kMaxPoolDevices);
-  std::lock_guard<std::mutex> lk(g_pool_mu);
-  std::vector<hipStream_t>& pool = g_pool[dev];
-  while ((int)pool.size() < n) {
-    hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
-      return fail(HCG_E_DEVICE, "hcg_plan_batch: cannot create a stream");
-    pool.push_back(s);
-  }
-  out->assign(pool.begin(), pool.begin() + n);
-  return HCG_OK;
-}
-
 bool batch_is_live(const hcg_batch_s* b) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   return b && std::find(g_batches.begin(), g_batches.end(), b) != g_batches.end() &&
@@ -335,6 +312,7 @@ void free_batch(hcg_batch_s* b) {
   if (b->d_segs) (void)hipFree(b->d_segs);
   if (b->d_ctl) (void)hipFree(b->d_ctl);
   for (hcg_plan_t p : b->plans) (void)hcg_destroy(p);
+  if (b->arena) (void)hipFree(b->arena);
   b->magic = 0;
   delete b;
 }
@@ -501,52 +479,19 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
     free_batch(b);
     return fail(HCG_E_DEVICE, "hcg_plan_batch: device query failed");
   }
-  // The plans are built step by step for all fields at once (plan_build_many:
-  // one host synchronisation per build step, not several per field), field
-  // f on the f % kPlanStreams-th of the library's streams, which first wait
-  // for the caller's stream (where the coordinates were written); the
-  // fields' short kernels then overlap.
-  std::vector<hipStream_t> wstreams;
-  const int nstreams = std::max(1, std::min<int>(kPlanStreams, nfields));
-  st = plan_streams(b->device, nstreams, &wstreams);
-  if (st != HCG_OK) {
-    free_batch(b);
-    return st;
-  }
-  hipEvent_t ready = nullptr;
-  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(ready, stream) != hipSuccess) {
-    if (ready) (void)hipEventDestroy(ready);
-    free_batch(b);
-    return fail(HCG_E_DEVICE, "hcg_plan_batch: event on the caller's stream failed");
-  }
-  for (hipStream_t ws : wstreams) {
-    if (hipStreamWaitEvent(ws, ready, 0) != hipSuccess) {
-      (void)hipEventDestroy(ready);
-      free_batch(b);
-      return fail(HCG_E_DEVICE, "hcg_plan_batch: stream wait failed");
-    }
-  }
+  // The plans are built together (plan_build_fields): each build step runs
+  // for every field in one launch on the caller's stream, with one host read
+  // after the pixels and one at the end; the plans' arrays share one
+  // allocation that the batch owns.
   b->plans.assign(nfields, nullptr);
   int32_t failed = -1;
-  st = plan_build_many(nfields, fields, &po, wstreams.data(), nstreams, b->plans.data(), &failed);
-  (void)hipEventDestroy(ready);
+  st = plan_build_fields(nfields, fields, &po, stream, b->plans.data(), &b->arena, &b->ncand,
+                         &failed);
   if (st != HCG_OK) {
     const std::string msg = hcg_last_error();
     free_batch(b);
-    return fail(st, "hcg_plan_batch: field %d: %s", failed, msg.c_str());
-  }
-  // candidate counts per tile (the work-item costs)
-  b->ncand.resize(nfields);
-  for (int32_t f = 0; f < nfields; ++f) {
-    const hcg_plan_s* p = b->plans[f];
-    const size_t nt = (size_t)p->ntx * p->nty;
-    b->ncand[f].resize(nt);
-    if (hipMemcpy(b->ncand[f].data(), p->ncand, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost) !=
-        hipSuccess) {
-      free_batch(b);
-      return fail(HCG_E_DEVICE, "hcg_plan_batch: reading candidate counts failed");
-    }
+    if (failed >= 0) return fail(st, "hcg_plan_batch: field %d: %s", failed, msg.c_str());
+    return fail(st, "hcg_plan_batch: %s", msg.c_str());
   }
   b->nblocks = 2 * cus;  // two 256-thread workgroups per CU
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||

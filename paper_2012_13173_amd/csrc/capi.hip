@@ -73,8 +73,9 @@ extern "C" hcg_status hcg_destroy(hcg_plan_t plan) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (cur != plan->device) (void)hipSetDevice(plan->device);
-  hipError_t e1 = hipDeviceSynchronize();
-  hipError_t e2 = hipFree(plan->arena);
+  // (a plan of a batch has no arena of its own: the batch frees the shared one)
+  hipError_t e1 = plan->arena ? hipDeviceSynchronize() : hipSuccess;
+  hipError_t e2 = plan->arena ? hipFree(plan->arena) : hipSuccess;
   if (cur != plan->device && cur >= 0) (void)hipSetDevice(cur);
   plan->magic = 0;
   delete plan;

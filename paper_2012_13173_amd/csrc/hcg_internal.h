@@ -1,6 +1,8 @@
 // Internal definitions shared by the HIP sources of the gridding library.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -260,9 +262,9 @@ struct BatchSeg {
 };
 constexpr int kBatchXcds = 8;
 constexpr int kBatchCtl = 16;
-hcg_status plan_build_many(int32_t nfields, const hcg_field_desc* fields, const hcg_opts* opts,
-                           const hipStream_t* streams, int nstreams, hcg_plan_t* plans,
-                           int32_t* failed);
+hcg_status plan_build_fields(int32_t nf, const hcg_field_desc* fd, const hcg_opts* opts,
+                             hipStream_t stream, hcg_plan_t* plans, void** arena_out,
+                             std::vector<std::vector<uint32_t>>* ncand, int32_t* failed);
 hcg_status launch_radix_sort(const uint32_t* keys_in, int64_t n, int key_bits, uint32_t* keys_out,
                              uint32_t* perm_out, void* temp, hipStream_t stream);
 

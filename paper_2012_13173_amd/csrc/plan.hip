@@ -65,15 +65,15 @@ __device__ __noinline__ uint32_t ang2pix_ring(int ns_i, double lon_deg, double l
 }
 
 // stat[0] = min pixel, stat[1] = max pixel, stat[2] = count of bad inputs.
-// Grid-stride over the samples; one set of atomics per block.
-__global__ void __launch_bounds__(256) k_ang2pix(const double* __restrict__ lon,
-                                                 const double* __restrict__ lat, int64_t n,
-                                                 int ns, uint32_t* __restrict__ pix,
-                                                 uint32_t* __restrict__ stat) {
+// Block `bx` of `nb` strides over the samples; one set of atomics per block.
+__device__ inline void ang2pix_block(const double* __restrict__ lon,
+                                     const double* __restrict__ lat, int64_t n, int ns,
+                                     uint32_t* __restrict__ pix, uint32_t* __restrict__ stat,
+                                     uint32_t bx, uint32_t nb) {
   __shared__ uint32_t s_red[3][4];
   uint32_t vmin = 0xFFFFFFFFu, vmax = 0u, bad = 0u;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)bx * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)nb * blockDim.x) {
     const double lo = lon[i], la = lat[i];
     uint32_t p;
     if (!isfinite(lo) || !isfinite(la) || fabs(la) > 90.0) {
@@ -110,6 +110,13 @@ __global__ void __launch_bounds__(256) k_ang2pix(const double* __restrict__ lon,
   }
 }
 
+__global__ void __launch_bounds__(256) k_ang2pix(const double* __restrict__ lon,
+                                                 const double* __restrict__ lat, int64_t n,
+                                                 int ns, uint32_t* __restrict__ pix,
+                                                 uint32_t* __restrict__ stat) {
+  ang2pix_block(lon, lat, n, ns, pix, stat, blockIdx.x, gridDim.x);
+}
+
 hcg_status launch_ang2pix(const double* lon, const double* lat, int64_t n, int nside,
                           uint32_t* pix, uint32_t* stat, hipStream_t stream) {
   const uint32_t init[4] = {0xFFFFFFFFu, 0u, 0u, 0u};
@@ -132,22 +139,27 @@ constexpr int kRsItems = 16;
 constexpr int kRsTile = kRsThreads * kRsItems;
 constexpr int kScanChunk = 4096;
 
-__global__ void __launch_bounds__(kRsThreads) k_radix_hist(const uint32_t* __restrict__ keys,
-                                                           int64_t n, int shift,
-                                                           uint32_t* __restrict__ hist,
-                                                           int ntiles) {
+__device__ inline void radix_hist_block(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                        uint32_t* __restrict__ hist, int ntiles, uint32_t bx) {
   __shared__ uint32_t h[256];
   const int tid = threadIdx.x;
   h[tid] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const int64_t base = (int64_t)bx * kRsTile;
 #pragma unroll
   for (int r = 0; r < kRsItems; ++r) {
     const int64_t idx = base + r * kRsThreads + tid;
     if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+  hist[(int64_t)tid * ntiles + bx] = h[tid];
+}
+
+__global__ void __launch_bounds__(kRsThreads) k_radix_hist(const uint32_t* __restrict__ keys,
+                                                           int64_t n, int shift,
+                                                           uint32_t* __restrict__ hist,
+                                                           int ntiles) {
+  radix_hist_block(keys, n, shift, hist, ntiles, blockIdx.x);
 }
 
 // Exclusive scan of a 256-thread block; returns the block total in *total.
@@ -170,10 +182,10 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh_wave, u
   return wave_off + x - v;
 }
 
-__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in, int64_t m,
-                                                     uint32_t* __restrict__ partial) {
+__device__ inline void scan_reduce_block(const uint32_t* __restrict__ in, int64_t m,
+                                         uint32_t* __restrict__ partial, uint32_t bx) {
   __shared__ uint32_t sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t base = (int64_t)bx * kScanChunk;
   uint32_t s = 0;
   for (int r = 0; r < kScanChunk / 256; ++r) {
     const int64_t i = base + r * 256 + threadIdx.x;
@@ -181,10 +193,15 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict_
   }
   uint32_t tot;
   block_exclusive_scan(s, sh, &tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+  if (threadIdx.x == 0) partial[bx] = tot;
 }
 
-__global__ void __launch_bounds__(256) k_scan_top(uint32_t* __restrict__ partial, int64_t np) {
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in, int64_t m,
+                                                     uint32_t* __restrict__ partial) {
+  scan_reduce_block(in, m, partial, blockIdx.x);
+}
+
+__device__ inline void scan_top_block(uint32_t* __restrict__ partial, int64_t np) {
   __shared__ uint32_t sh[4];
   uint32_t carry = 0;
   for (int64_t base = 0; base < np; base += 256) {
@@ -197,12 +214,16 @@ __global__ void __launch_bounds__(256) k_scan_top(uint32_t* __restrict__ partial
   }
 }
 
-__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ in, int64_t m,
-                                                    const uint32_t* __restrict__ partial,
-                                                    uint32_t* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_scan_top(uint32_t* __restrict__ partial, int64_t np) {
+  scan_top_block(partial, np);
+}
+
+__device__ inline void scan_apply_block(const uint32_t* __restrict__ in, int64_t m,
+                                        const uint32_t* __restrict__ partial,
+                                        uint32_t* __restrict__ out, uint32_t bx) {
   __shared__ uint32_t sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  uint32_t carry = partial[blockIdx.x];
+  const int64_t base = (int64_t)bx * kScanChunk;
+  uint32_t carry = partial[bx];
   for (int r = 0; r < kScanChunk / 256; ++r) {
     const int64_t i = base + r * 256 + threadIdx.x;
     const uint32_t v = (i < m) ? in[i] : 0u;
@@ -213,21 +234,29 @@ __global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(kRsThreads) k_radix_scatter(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n, int shift,
-    const uint32_t* __restrict__ offs, int ntiles) {
+__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ in, int64_t m,
+                                                    const uint32_t* __restrict__ partial,
+                                                    uint32_t* __restrict__ out) {
+  scan_apply_block(in, m, partial, out, blockIdx.x);
+}
+
+__device__ inline void radix_scatter_block(const uint32_t* __restrict__ keys_in,
+                                           const uint32_t* __restrict__ vals_in,
+                                           uint32_t* __restrict__ keys_out,
+                                           uint32_t* __restrict__ vals_out, int64_t n, int shift,
+                                           const uint32_t* __restrict__ offs, int ntiles,
+                                           uint32_t bx) {
   __shared__ uint32_t base_off[256];
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[4][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  base_off[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  base_off[tid] = offs[(int64_t)tid * ntiles + bx];
   run[tid] = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t tile_base = (int64_t)blockIdx.x * kRsTile;
+  const int64_t tile_base = (int64_t)bx * kRsTile;
   for (int r = 0; r < kRsItems; ++r) {
     const int64_t idx = tile_base + r * kRsThreads + tid;
     const bool valid = idx < n;
@@ -256,6 +285,13 @@ __global__ void __launch_bounds__(kRsThreads) k_radix_scatter(
     for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(kRsThreads) k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n, int shift,
+    const uint32_t* __restrict__ offs, int ntiles) {
+  radix_scatter_block(keys_in, vals_in, keys_out, vals_out, n, shift, offs, ntiles, blockIdx.x);
 }
 
 static inline int64_t rs_ntiles(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
@@ -436,13 +472,17 @@ __device__ void tile_ranges_wave(const uint32_t* __restrict__ keys,
   }
 }
 
-// Linear lon/lat grid: the box of the tile's cell centres.
-__global__ void __launch_bounds__(256) k_tile_ranges(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ csr, int ns, int ring_first,
-    int ring_last, uint32_t pix_base, GridGeom g, int ntx, int nty, double support_rad, int maxr,
-    uint2* __restrict__ ranges, uint32_t* __restrict__ nranges, uint32_t* __restrict__ ncand,
-    uint32_t* __restrict__ flags) {
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+// Linear lon/lat grid: the box of the tile's cell centres (one wave per
+// tile; block bx holds tiles 4 bx .. 4 bx + 3).
+__device__ inline void tile_ranges_linear(const uint32_t* __restrict__ keys,
+                                          const uint32_t* __restrict__ csr, int ns,
+                                          int ring_first, int ring_last, uint32_t pix_base,
+                                          const GridGeom& g, int ntx, int nty, double support_rad,
+                                          int maxr, uint2* __restrict__ ranges,
+                                          uint32_t* __restrict__ nranges,
+                                          uint32_t* __restrict__ ncand,
+                                          uint32_t* __restrict__ flags, uint32_t bx) {
+  const int tile = (int)bx * 4 + (threadIdx.x >> 6);
   if (tile >= ntx * nty) return;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ix0 = tx * kTileX, ix1 = min(g.nx, ix0 + kTileX) - 1;
@@ -458,6 +498,15 @@ __global__ void __launch_bounds__(256) k_tile_ranges(
   const double Rs = support_rad * (1.0 + 1e-9) + 1e-12;
   tile_ranges_wave(keys, csr, ns, ring_first, ring_last, pix_base, lon_a, lon_b, lat_a, lat_b, Rs,
                    maxr, ranges + (int64_t)tile * maxr, &nranges[tile], &ncand[tile], flags);
+}
+
+__global__ void __launch_bounds__(256) k_tile_ranges(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ csr, int ns, int ring_first,
+    int ring_last, uint32_t pix_base, GridGeom g, int ntx, int nty, double support_rad, int maxr,
+    uint2* __restrict__ ranges, uint32_t* __restrict__ nranges, uint32_t* __restrict__ ncand,
+    uint32_t* __restrict__ flags) {
+  tile_ranges_linear(keys, csr, ns, ring_first, ring_last, pix_base, g, ntx, nty, support_rad,
+                     maxr, ranges, nranges, ncand, flags, blockIdx.x);
 }
 
 // Cells given by their centres: per tile (one wave), the cap around the
@@ -525,6 +574,210 @@ __global__ void __launch_bounds__(256) k_tile_ranges_cap(
   tile_ranges_wave(keys, csr, ns, ring_first, ring_last, pix_base, cap.x, cap.x, cap.y, cap.y, Rs,
                    maxr, ranges + (int64_t)tile * maxr, &nranges[tile], &ncand[tile], flags);
 }
+
+// ---------------------------------------------------------------------------
+// Many plans at once (batches of fields on linear grids): every step runs
+// for all fields in one launch.  A launch's blocks are the fields' blocks
+// laid end to end; block b finds its field by binary search in the launch
+// kind's prefix table (fields_blocks[kind][0..nf]) and runs the step's
+// block body for that field's arrays.
+// ---------------------------------------------------------------------------
+enum FieldBlockKind : int {
+  kFbSamples = 0,    // ceil(n / 256)
+  kFbSortTiles = 1,  // radix-sort tiles of 4096 keys
+  kFbScan = 2,       // scan chunks of the digit histogram
+  kFbOne = 3,        // one block per field
+  kFbCells = 4,      // ceil(cells / 256)
+  kFbRings = 5,      // ceil((rings + 1) / 256)
+  kFbTiles = 6,      // ceil(tiles / 4)
+  kFbKinds = 7
+};
+
+struct PlanField {
+  // first step
+  const double* lon;
+  const double* lat;
+  int64_t n;
+  int nside;
+  uint32_t* pix;
+  uint32_t* stat;
+  // second step
+  GridGeom grid;
+  int ntx, nty, maxr, ring_first, ring_last, nrings;
+  uint32_t pix_base;
+  double support_rad;
+  int64_t rs_ntiles, rs_m, rs_np;
+  uint32_t *rel, *k_alt, *v_alt, *hist, *offs, *partial;
+  uint32_t *keys, *perm, *csr, *nranges, *ncand, *flags;
+  uint2* ranges;
+  double4 *xyz, *cells;
+};
+
+// The field of flattened block b of launch kind `kind`, and its block there.
+__device__ inline int field_of_block(const uint32_t* __restrict__ prefix, int nf, uint32_t b,
+                                     uint32_t* local) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  *local = b - prefix[lo];
+  return lo;
+}
+
+#define HCG_FIELD_BLOCK(kind)                                                     \
+  uint32_t lb;                                                                   \
+  const int fi = field_of_block(prefix + (size_t)(kind) * (nf + 1), nf, blockIdx.x, &lb); \
+  const PlanField& F = fields[fi];
+
+__global__ void __launch_bounds__(256) k_stat_init_fields(const PlanField* __restrict__ fields,
+                                                          const uint32_t* __restrict__ prefix,
+                                                          int nf) {
+  HCG_FIELD_BLOCK(kFbOne);
+  (void)lb;
+  if (threadIdx.x < 4) F.stat[threadIdx.x] = (threadIdx.x == 0) ? 0xFFFFFFFFu : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_ang2pix_fields(const PlanField* __restrict__ fields,
+                                                        const uint32_t* __restrict__ prefix,
+                                                        int nf) {
+  HCG_FIELD_BLOCK(kFbSamples);
+  const uint32_t nb = prefix[kFbSamples * (nf + 1) + fi + 1] - prefix[kFbSamples * (nf + 1) + fi];
+  ang2pix_block(F.lon, F.lat, F.n, F.nside, F.pix, F.stat, lb, nb);
+}
+
+__global__ void __launch_bounds__(256) k_cells_rel_fields(const PlanField* __restrict__ fields,
+                                                          const uint32_t* __restrict__ prefix,
+                                                          int nf) {
+  // cell vectors into the plan, then (from block kFbCells onward) the keys
+  // relative to the smallest pixel: one launch of kFbCells + kFbSamples blocks
+  const uint32_t ncb = prefix[kFbCells * (nf + 1) + nf];
+  if (blockIdx.x < ncb) {
+    HCG_FIELD_BLOCK(kFbCells);
+    const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+    if (i < (int64_t)F.grid.nx * F.grid.ny) {
+      const CellVec c = cell_vec(F.grid, (int)(i % F.grid.nx), (int)(i / F.grid.nx));
+      F.cells[i] = make_double4(c.x, c.y, c.z, 0.0);
+    }
+    return;
+  }
+  uint32_t lb;
+  const int fi = field_of_block(prefix + (size_t)kFbSamples * (nf + 1), nf, blockIdx.x - ncb, &lb);
+  const PlanField& F = fields[fi];
+  const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+  if (i < F.n) F.rel[i] = F.pix[i] - F.pix_base;
+}
+
+// Pass p of `passes` (every field takes the same number; a digit that is
+// zero for all keys of a field leaves its order as it is): the pass reads the
+// previous pass's output (the relative keys and no values for p = 0) and
+// writes to the plan's keys and permutation on the last pass, ping-pong
+// before it.
+__device__ inline void sort_pass_arrays(const PlanField& F, int p, int passes,
+                                        const uint32_t** sk, const uint32_t** sv, uint32_t** dk,
+                                        uint32_t** dv) {
+  auto out_of = [&](int q, uint32_t** k, uint32_t** v) {
+    const bool to_out = ((passes - 1 - q) % 2) == 0;
+    *k = to_out ? F.keys : F.k_alt;
+    *v = to_out ? F.perm : F.v_alt;
+  };
+  out_of(p, dk, dv);
+  if (p == 0) {
+    *sk = F.rel;
+    *sv = nullptr;
+  } else {
+    uint32_t *k, *v;
+    out_of(p - 1, &k, &v);
+    *sk = k;
+    *sv = v;
+  }
+}
+
+__global__ void __launch_bounds__(kRsThreads) k_radix_hist_fields(
+    const PlanField* __restrict__ fields, const uint32_t* __restrict__ prefix, int nf, int p,
+    int passes) {
+  HCG_FIELD_BLOCK(kFbSortTiles);
+  const uint32_t *sk, *sv;
+  uint32_t *dk, *dv;
+  sort_pass_arrays(F, p, passes, &sk, &sv, &dk, &dv);
+  radix_hist_block(sk, F.n, 8 * p, F.hist, (int)F.rs_ntiles, lb);
+}
+
+__global__ void __launch_bounds__(256) k_scan_reduce_fields(const PlanField* __restrict__ fields,
+                                                            const uint32_t* __restrict__ prefix,
+                                                            int nf) {
+  HCG_FIELD_BLOCK(kFbScan);
+  scan_reduce_block(F.hist, F.rs_m, F.partial, lb);
+}
+
+__global__ void __launch_bounds__(256) k_scan_top_fields(const PlanField* __restrict__ fields,
+                                                         const uint32_t* __restrict__ prefix,
+                                                         int nf) {
+  HCG_FIELD_BLOCK(kFbOne);
+  (void)lb;
+  scan_top_block(F.partial, F.rs_np);
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply_fields(const PlanField* __restrict__ fields,
+                                                           const uint32_t* __restrict__ prefix,
+                                                           int nf) {
+  HCG_FIELD_BLOCK(kFbScan);
+  scan_apply_block(F.hist, F.rs_m, F.partial, F.offs, lb);
+}
+
+__global__ void __launch_bounds__(kRsThreads) k_radix_scatter_fields(
+    const PlanField* __restrict__ fields, const uint32_t* __restrict__ prefix, int nf, int p,
+    int passes) {
+  HCG_FIELD_BLOCK(kFbSortTiles);
+  const uint32_t *sk, *sv;
+  uint32_t *dk, *dv;
+  sort_pass_arrays(F, p, passes, &sk, &sv, &dk, &dv);
+  radix_scatter_block(sk, sv, dk, dv, F.n, 8 * p, F.offs, (int)F.rs_ntiles, lb);
+}
+
+__global__ void __launch_bounds__(256) k_permute_xyz_fields(const PlanField* __restrict__ fields,
+                                                            const uint32_t* __restrict__ prefix,
+                                                            int nf) {
+  HCG_FIELD_BLOCK(kFbSamples);
+  const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+  if (i < F.n) {
+    const uint32_t s = F.perm[i];
+    double sb, cb, sl, cl;
+    sincos(F.lat[s] * kDeg2Rad, &sb, &cb);
+    sincos(F.lon[s] * kDeg2Rad, &sl, &cl);
+    F.xyz[i] = make_double4(cb * cl, cb * sl, sb, 0.0);
+  }
+  // the sentinels past n: eight NaN vectors, permutation entry 0, flags 0
+  if (lb == 0 && threadIdx.x < 8) {
+    const double nan = __builtin_nan("");
+    F.xyz[F.n + threadIdx.x] = make_double4(nan, nan, nan, nan);
+    if (threadIdx.x == 0) F.perm[F.n] = 0u;
+    if (threadIdx.x < 4) F.flags[threadIdx.x] = 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ring_csr_fields(const PlanField* __restrict__ fields,
+                                                         const uint32_t* __restrict__ prefix,
+                                                         int nf) {
+  HCG_FIELD_BLOCK(kFbRings);
+  const int r = (int)lb * 256 + threadIdx.x;
+  if (r > F.nrings) return;
+  if (r == F.nrings) {
+    F.csr[r] = (uint32_t)F.n;
+    return;
+  }
+  const int64_t target = hpx_ring_start(F.nside, F.ring_first + r) - (int64_t)F.pix_base;
+  F.csr[r] = (target <= 0) ? 0u : lower_bound_u32(F.keys, 0u, (uint32_t)F.n, target);
+}
+
+__global__ void __launch_bounds__(256) k_tile_ranges_fields(const PlanField* __restrict__ fields,
+                                                            const uint32_t* __restrict__ prefix,
+                                                            int nf) {
+  HCG_FIELD_BLOCK(kFbTiles);
+  tile_ranges_linear(F.keys, F.csr, F.nside, F.ring_first, F.ring_last, F.pix_base, F.grid, F.ntx,
+                     F.nty, F.support_rad, F.maxr, F.ranges, F.nranges, F.ncand, F.flags, lb);
+}
+#undef HCG_FIELD_BLOCK
 
 // ---------------------------------------------------------------------------
 // Host side
@@ -936,72 +1189,302 @@ hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_
 
 namespace hcg {
 
-// Plans of many fields on linear grids (the batch): each build step runs for
-// every field, field f on streams[f % nstreams], with one synchronisation of
-// the streams per step.  On failure *failed is the first failing field and
-// nothing is left allocated.
-hcg_status plan_build_many(int32_t nfields, const hcg_field_desc* fields, const hcg_opts* opts,
-                           const hipStream_t* streams, int nstreams, hcg_plan_t* plans,
-                           int32_t* failed) {
+// Plans of many fields on linear grids (the batch), built together: the
+// pixels of every field in one launch, one read of their ranges, then every
+// further step for all fields in one launch each (the sort with the largest
+// number of passes any field needs), one read of the overflow flags.  The
+// plans' arrays share one allocation, *arena_out, which the caller frees
+// after destroying the plans (their own arena pointers are NULL).  On
+// failure *failed is the first failing field (or -1) and nothing is left
+// allocated.
+hcg_status plan_build_fields(int32_t nf, const hcg_field_desc* fd, const hcg_opts* opts,
+                             hipStream_t stream, hcg_plan_t* plans, void** arena_out,
+                             std::vector<std::vector<uint32_t>>* ncand, int32_t* failed) {
   *failed = -1;
-  for (int32_t f = 0; f < nfields; ++f) plans[f] = nullptr;
-  uint32_t* host = nullptr;
-  if (hipHostMalloc((void**)&host, sizeof(uint32_t) * 16 * (size_t)nfields) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HCG_E_NOMEM, "cannot allocate page-locked host memory for %d plans", nfields);
-  }
-  struct HostFree {
-    uint32_t* h;
-    ~HostFree() { (void)hipHostFree(h); }
-  } hf{host};
-  std::vector<PlanBuilder> b(nfields);
-  auto sync_all = [&]() -> hcg_status {
-    for (int k = 0; k < std::min<int>(nstreams, nfields); ++k)
-      HCG_HIP(hipStreamSynchronize(streams[k]));
-    return HCG_OK;
-  };
+  *arena_out = nullptr;
+  for (int32_t f = 0; f < nf; ++f) plans[f] = nullptr;
+  hcg_opts o = {};
+  if (opts) o = *opts;
+  if ((o.tile_x && o.tile_x != kTileX) || (o.tile_y && o.tile_y != kTileY))
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan: only 8 x 8 cell tiles are built");
+  if (o.coarsen || o.chan_tile || o.flags)
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan: coarsen, chan_tile and flags must be 0");
+  hcg_status st = check_device_arch();
+  if (st != HCG_OK) return st;
+
+  // ---- argument checks and first-step sizes
+  std::vector<PlanField> F(nf);
+  std::vector<KernelParams> kp(nf);
+  std::vector<double> sigma(nf), fwhm_nom(nf);
   hcg_kernel k{};
   k.type = HCG_KERNEL_GAUSS;
-  for (int32_t f = 0; f < nfields; ++f) {
-    const hcg_field_desc& d = fields[f];
-    hcg_status st = HCG_OK;
-    if (!d.lon_deg || !d.lat_deg) st = fail(HCG_E_ARG, "hcg_plan: NULL pointer");
-    if (st == HCG_OK) st = check_grid(&d.grid, "hcg_plan");
-    if (st == HCG_OK) {
-      k.fwhm_deg = d.fwhm_deg;
-      const PlanTarget tg{&d.grid, nullptr, nullptr, d.grid.nx, d.grid.ny};
-      st = b[f].begin(d.lon_deg, d.lat_deg, d.n, tg, &k, d.support_deg, opts,
-                      streams[f % nstreams], host + 16 * (size_t)f, "hcg_plan");
-    }
-    if (st != HCG_OK) {
-      *failed = f;
-      (void)sync_all();
-      return st;
-    }
+  for (int32_t f = 0; f < nf; ++f) {
+    const hcg_field_desc& d = fd[f];
+    *failed = f;
+    if (!d.lon_deg || !d.lat_deg) return fail(HCG_E_ARG, "hcg_plan: NULL pointer");
+    st = check_grid(&d.grid, "hcg_plan");
+    if (st != HCG_OK) return st;
+    if (d.n < 1 || d.n >= (int64_t(1) << 31)) return fail(HCG_E_ARG, "hcg_plan: n must be in 1..2^31-1");
+    if (!(d.support_deg >= 0.0) || !(d.support_deg < 90.0))
+      return fail(HCG_E_ARG, "hcg_plan: support must be in [0, 90) degrees");
+    k.fwhm_deg = d.fwhm_deg;
+    st = kernel_params(&k, "hcg_plan", &kp[f], &sigma[f], &fwhm_nom[f]);
+    if (st != HCG_OK) return st;
+    const int nside = o.nside ? o.nside : auto_nside(sigma[f]);
+    if (!is_pow2(nside) || nside > 16384)
+      return fail(HCG_E_ARG, "hcg_plan: nside %d is not a power of two in 1..16384", nside);
+    PlanField& P = F[f];
+    memset(&P, 0, sizeof(P));
+    P.lon = d.lon_deg;
+    P.lat = d.lat_deg;
+    P.n = d.n;
+    P.nside = nside;
+    P.grid = GridGeom{d.grid.nx, d.grid.ny, d.grid.lon0_deg, d.grid.lat0_deg, d.grid.dlon_deg,
+                      d.grid.dlat_deg};
+    P.ntx = (d.grid.nx + kTileX - 1) / kTileX;
+    P.nty = (d.grid.ny + kTileY - 1) / kTileY;
+    P.support_rad = d.support_deg * kDeg2Rad;
   }
-  hcg_status st = sync_all();
-  if (st != HCG_OK) return st;
-  for (int32_t f = 0; f < nfields; ++f) {
-    st = b[f].middle();
-    if (st != HCG_OK) {
-      *failed = f;
-      (void)sync_all();
-      return st;
-    }
+  *failed = -1;
+
+  // page-locked host block: the field table, the launch prefix tables, and
+  // what comes back (pixel statistics, flags)
+  const size_t tab_bytes = align256(sizeof(PlanField) * nf);
+  const size_t pre_bytes = align256(sizeof(uint32_t) * kFbKinds * (nf + 1));
+  const size_t back_bytes = align256(sizeof(uint32_t) * 4 * nf);
+  char* host = nullptr;
+  if (hipHostMalloc((void**)&host, tab_bytes + pre_bytes + back_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HCG_E_NOMEM, "cannot allocate page-locked host memory for %d plans", nf);
   }
-  st = sync_all();
-  if (st != HCG_OK) return st;
-  for (int32_t f = 0; f < nfields; ++f) {
-    st = b[f].finish(&plans[f]);
-    if (st != HCG_OK) {
-      *failed = f;
-      for (int32_t g = 0; g < f; ++g) {
-        (void)hcg_destroy(plans[g]);
-        plans[g] = nullptr;
-      }
-      return st;
+  struct HostFree {
+    char* h;
+    ~HostFree() { (void)hipHostFree(h); }
+  } hf{host};
+  PlanField* h_tab = (PlanField*)host;
+  uint32_t* h_pre = (uint32_t*)(host + tab_bytes);
+  uint32_t* h_back = (uint32_t*)(host + tab_bytes + pre_bytes);
+  auto prefix = [&](int kind, auto blocks_of) {
+    uint32_t* pr = h_pre + (size_t)kind * (nf + 1);
+    uint64_t acc = 0;
+    for (int32_t f = 0; f < nf; ++f) {
+      pr[f] = (uint32_t)acc;
+      acc += blocks_of(F[f]);
     }
+    pr[nf] = (uint32_t)acc;
+    return acc;
+  };
+
+  // ---- first step: pixels and their range
+  size_t t1 = 0;
+  std::vector<size_t> o_pix(nf);
+  for (int32_t f = 0; f < nf; ++f) {
+    o_pix[f] = t1;
+    t1 += align256(sizeof(uint32_t) * F[f].n);
   }
+  const size_t o_stat = t1;
+  t1 += align256(sizeof(uint32_t) * 4 * nf);
+  const size_t o_tab = t1;
+  t1 += tab_bytes + pre_bytes;
+  DevBuf temp1;
+  if (temp1.alloc_async(t1, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HCG_E_NOMEM, "cannot allocate %zu bytes of scratch for %d plans", t1, nf);
+  }
+  char* T1 = (char*)temp1.p;
+  for (int32_t f = 0; f < nf; ++f) {
+    F[f].pix = (uint32_t*)(T1 + o_pix[f]);
+    F[f].stat = (uint32_t*)(T1 + o_stat) + 4 * f;
+  }
+  const uint64_t nb_samples = prefix(kFbSamples, [](const PlanField& P) { return (uint64_t)((P.n + 255) / 256); });
+  prefix(kFbOne, [](const PlanField&) { return (uint64_t)1; });
+  if (nb_samples >= 0xFFFFFFF0ull) return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: too many samples");
+  memcpy(h_tab, F.data(), sizeof(PlanField) * nf);
+  PlanField* d_tab = (PlanField*)(T1 + o_tab);
+  uint32_t* d_pre = (uint32_t*)(T1 + o_tab + tab_bytes);
+  HCG_HIP(hipMemcpyAsync(d_tab, host, tab_bytes + pre_bytes, hipMemcpyHostToDevice, stream));
+  k_stat_init_fields<<<(unsigned)nf, 256, 0, stream>>>(d_tab, d_pre, nf);
+  HCG_LAUNCH_CHECK("k_stat_init_fields");
+  k_ang2pix_fields<<<(unsigned)nb_samples, 256, 0, stream>>>(d_tab, d_pre, nf);
+  HCG_LAUNCH_CHECK("k_ang2pix_fields");
+  HCG_HIP(hipMemcpyAsync(h_back, T1 + o_stat, sizeof(uint32_t) * 4 * nf, hipMemcpyDeviceToHost,
+                         stream));
+  HCG_HIP(hipStreamSynchronize(stream));
+
+  // ---- sizes, the plans' arena and the sort scratch
+  int passes = 1;
+  std::vector<size_t> o_ar(nf);
+  std::vector<int> key_bits(nf);
+  std::vector<uint32_t> pix_max_of(nf);
+  size_t arena_bytes = 0, t2 = 0;
+  std::vector<size_t> o_t2(nf);
+  struct Off { size_t xyz, keys, perm, csr, rng, nr, nc, flags, cells, bytes; };
+  std::vector<Off> off(nf);
+  for (int32_t f = 0; f < nf; ++f) {
+    PlanField& P = F[f];
+    const uint32_t* hs = h_back + 4 * f;
+    if (hs[2]) {
+      *failed = f;
+      return fail(HCG_E_ARG, "hcg_plan: %u sample coordinates are non-finite or |lat| > 90", hs[2]);
+    }
+    P.pix_base = hs[0];
+    const uint32_t pix_max = hs[1];
+    pix_max_of[f] = pix_max;
+    P.ring_first = (int)hpx_pix2ring(P.nside, P.pix_base);
+    P.ring_last = (int)hpx_pix2ring(P.nside, pix_max);
+    P.nrings = P.ring_last - P.ring_first + 1;
+    key_bits[f] = bit_length(pix_max - P.pix_base);
+    passes = std::max(passes, (key_bits[f] + 7) / 8);
+    const double tile_span = (kTileY - 1) * std::fabs(P.grid.dlat) * kDeg2Rad;
+    const double rings_d = (tile_span + 2.0 * P.support_rad) / (2.0 / (3.0 * P.nside)) + 6.0;
+    if (rings_d > kMaxRangesLimit / 2) {
+      *failed = f;
+      return fail(HCG_E_UNSUPPORTED,
+                  "hcg_plan: support or tile too wide for nside %d (%.0f rings per tile; at most %d)",
+                  P.nside, rings_d, kMaxRangesLimit / 2);
+    }
+    P.maxr = 2 * (int)std::ceil(rings_d);
+    const int64_t ntiles = (int64_t)P.ntx * P.nty, ncell = (int64_t)P.grid.nx * P.grid.ny;
+    Off& a = off[f];
+    size_t at = 0;
+    auto take = [&](size_t bytes) { size_t r = at; at += align256(bytes); return r; };
+    a.xyz = take(sizeof(double4) * (P.n + 8));
+    a.keys = take(sizeof(uint32_t) * P.n);
+    a.perm = take(sizeof(uint32_t) * (P.n + 1));
+    a.csr = take(sizeof(uint32_t) * (P.nrings + 1));
+    a.rng = take(sizeof(uint2) * (size_t)ntiles * P.maxr);
+    a.nr = take(sizeof(uint32_t) * ntiles);
+    a.nc = take(sizeof(uint32_t) * ntiles);
+    a.flags = take(16);
+    a.cells = take(sizeof(double4) * ncell);
+    a.bytes = at;
+    o_ar[f] = arena_bytes;
+    arena_bytes += at;
+    P.rs_ntiles = std::max<int64_t>(rs_ntiles(P.n), 1);
+    P.rs_m = 256 * P.rs_ntiles;
+    P.rs_np = (P.rs_m + kScanChunk - 1) / kScanChunk;
+    o_t2[f] = t2;
+    t2 += radix_sort_temp_bytes(P.n) + align256(sizeof(uint32_t) * P.n);
+  }
+  DevBuf arena, temp2;
+  if (hipMalloc(&arena.p, arena_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    arena.p = nullptr;
+    return fail(HCG_E_NOMEM, "cannot allocate %zu bytes for %d plans", arena_bytes, nf);
+  }
+  if (temp2.alloc_async(t2, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HCG_E_NOMEM, "cannot allocate %zu bytes of scratch for %d plans", t2, nf);
+  }
+  for (int32_t f = 0; f < nf; ++f) {
+    PlanField& P = F[f];
+    char* A = (char*)arena.p + o_ar[f];
+    const Off& a = off[f];
+    P.xyz = (double4*)(A + a.xyz);
+    P.keys = (uint32_t*)(A + a.keys);
+    P.perm = (uint32_t*)(A + a.perm);
+    P.csr = (uint32_t*)(A + a.csr);
+    P.ranges = (uint2*)(A + a.rng);
+    P.nranges = (uint32_t*)(A + a.nr);
+    P.ncand = (uint32_t*)(A + a.nc);
+    P.flags = (uint32_t*)(A + a.flags);
+    P.cells = (double4*)(A + a.cells);
+    char* t = (char*)temp2.p + o_t2[f];
+    P.k_alt = (uint32_t*)t;
+    t += align256(sizeof(uint32_t) * P.n);
+    P.v_alt = (uint32_t*)t;
+    t += align256(sizeof(uint32_t) * P.n);
+    P.hist = (uint32_t*)t;
+    t += align256(sizeof(uint32_t) * P.rs_m);
+    P.offs = (uint32_t*)t;
+    t += align256(sizeof(uint32_t) * P.rs_m);
+    P.partial = (uint32_t*)t;
+    P.rel = (uint32_t*)((char*)temp2.p + o_t2[f] + radix_sort_temp_bytes(P.n));
+  }
+
+  // ---- second step: every remaining build step, one launch each
+  const uint64_t nb_cells = prefix(kFbCells, [](const PlanField& P) { return (uint64_t)(((int64_t)P.grid.nx * P.grid.ny + 255) / 256); });
+  prefix(kFbSamples, [](const PlanField& P) { return (uint64_t)((P.n + 255) / 256); });
+  const uint64_t nb_sort = prefix(kFbSortTiles, [](const PlanField& P) { return (uint64_t)P.rs_ntiles; });
+  const uint64_t nb_scan = prefix(kFbScan, [](const PlanField& P) { return (uint64_t)P.rs_np; });
+  prefix(kFbOne, [](const PlanField&) { return (uint64_t)1; });
+  const uint64_t nb_rings = prefix(kFbRings, [](const PlanField& P) { return (uint64_t)((P.nrings + 1 + 255) / 256); });
+  const uint64_t nb_tiles = prefix(kFbTiles, [](const PlanField& P) { return (uint64_t)(((int64_t)P.ntx * P.nty + 3) / 4); });
+  if (nb_cells + nb_samples >= 0xFFFFFFF0ull || nb_tiles >= 0xFFFFFFF0ull)
+    return fail(HCG_E_UNSUPPORTED, "hcg_plan_batch: too many cells");
+  memcpy(h_tab, F.data(), sizeof(PlanField) * nf);
+  HCG_HIP(hipMemcpyAsync(d_tab, host, tab_bytes + pre_bytes, hipMemcpyHostToDevice, stream));
+  k_cells_rel_fields<<<(unsigned)(nb_cells + nb_samples), 256, 0, stream>>>(d_tab, d_pre, nf);
+  HCG_LAUNCH_CHECK("k_cells_rel_fields");
+  for (int p = 0; p < passes; ++p) {
+    k_radix_hist_fields<<<(unsigned)nb_sort, kRsThreads, 0, stream>>>(d_tab, d_pre, nf, p, passes);
+    k_scan_reduce_fields<<<(unsigned)nb_scan, 256, 0, stream>>>(d_tab, d_pre, nf);
+    k_scan_top_fields<<<(unsigned)nf, 256, 0, stream>>>(d_tab, d_pre, nf);
+    k_scan_apply_fields<<<(unsigned)nb_scan, 256, 0, stream>>>(d_tab, d_pre, nf);
+    k_radix_scatter_fields<<<(unsigned)nb_sort, kRsThreads, 0, stream>>>(d_tab, d_pre, nf, p,
+                                                                         passes);
+    HCG_LAUNCH_CHECK("k_radix_*_fields");
+  }
+  k_permute_xyz_fields<<<(unsigned)nb_samples, 256, 0, stream>>>(d_tab, d_pre, nf);
+  HCG_LAUNCH_CHECK("k_permute_xyz_fields");
+  k_ring_csr_fields<<<(unsigned)nb_rings, 256, 0, stream>>>(d_tab, d_pre, nf);
+  HCG_LAUNCH_CHECK("k_ring_csr_fields");
+  k_tile_ranges_fields<<<(unsigned)nb_tiles, 256, 0, stream>>>(d_tab, d_pre, nf);
+  HCG_LAUNCH_CHECK("k_tile_ranges_fields");
+  for (int32_t f = 0; f < nf; ++f)
+    HCG_HIP(hipMemcpyAsync(h_back + 4 * f, F[f].flags, 16, hipMemcpyDeviceToHost, stream));
+  ncand->assign(nf, {});
+  for (int32_t f = 0; f < nf; ++f) {
+    (*ncand)[f].resize((size_t)F[f].ntx * F[f].nty);
+    HCG_HIP(hipMemcpyAsync((*ncand)[f].data(), F[f].ncand, sizeof(uint32_t) * (*ncand)[f].size(),
+                           hipMemcpyDeviceToHost, stream));
+  }
+  HCG_HIP(hipStreamSynchronize(stream));
+  for (int32_t f = 0; f < nf; ++f)
+    if (h_back[4 * f]) {
+      *failed = f;
+      return fail(HCG_E_DEVICE, "hcg_plan: candidate-range slots overflowed (internal bound)");
+    }
+
+  // ---- the plans
+  for (int32_t f = 0; f < nf; ++f) {
+    const PlanField& P = F[f];
+    auto* p = new hcg_plan_s{};
+    p->magic = kPlanMagic;
+    (void)hipGetDevice(&p->device);
+    p->n = P.n;
+    p->nside = P.nside;
+    p->pix_base = P.pix_base;
+    p->pix_max = pix_max_of[f];
+    p->key_bits = key_bits[f];
+    p->passes = (key_bits[f] + 7) / 8;
+    p->ring_first = P.ring_first;
+    p->ring_last = P.ring_last;
+    p->grid = P.grid;
+    p->centres = 0;
+    p->fwhm_deg = fwhm_nom[f];
+    p->support_deg = fd[f].support_deg;
+    p->sigma_rad = sigma[f];
+    p->support_rad = P.support_rad;
+    p->kern = kp[f];
+    p->ntx = P.ntx;
+    p->nty = P.nty;
+    p->maxr = P.maxr;
+    p->arena_bytes = off[f].bytes;
+    p->xyz = P.xyz;
+    p->keys = P.keys;
+    p->perm = P.perm;
+    p->csr = P.csr;
+    p->ranges = P.ranges;
+    p->nranges = P.nranges;
+    p->ncand = P.ncand;
+    p->flags = P.flags;
+    p->cells = P.cells;
+    p->arena = nullptr;  // in the shared arena
+    plan_register(p);
+    plans[f] = p;
+  }
+  *arena_out = arena.release();
   return HCG_OK;
 }
 
