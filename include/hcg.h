@@ -602,6 +602,16 @@ typedef struct {
 
 hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info);
 
+/*
+ * hcg_batch_get_plan -- the plan of field `field` of a batch (built by
+ * hcg_plan_batch with every build step shared by all fields), for
+ * inspection: hcg_get_plan_info, hcg_export, hcg_get_plan_stats and hcg_grid
+ * accept it.  Borrowed: valid until hcg_destroy_batch, and hcg_destroy
+ * refuses it (HCG_E_STATE).  Errors: HCG_E_ARG (NULL pointer, field out of
+ * range), HCG_E_STATE (not a live batch).
+ */
+hcg_status hcg_batch_get_plan(hcg_batch_t batch, int32_t field, hcg_plan_t* out);
+
 #ifdef __cplusplus
 }
 #endif

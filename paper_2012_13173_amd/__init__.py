@@ -111,7 +111,7 @@ EXPORTED = ["hcg_plan", "hcg_grid", "hcg_destroy", "hcg_last_error", "hcg_get_pl
             "hcg_sort_keys", "hcg_quantize", "hcg_plan_batch", "hcg_grid_batch",
             "hcg_destroy_batch", "hcg_get_batch_info", "hcg_quantize_packed", "hcg_grid_packed",
             "hcg_packed_bytes", "hcg_grid_host", "hcg_grid_rowthreads", "hcg_plan_ex",
-            "hcg_grid_masked", "hcg_wcs_centres", "hcg_grid_noalloc"]
+            "hcg_grid_masked", "hcg_wcs_centres", "hcg_grid_noalloc", "hcg_batch_get_plan"]
 
 _lib = None
 
@@ -154,6 +154,7 @@ def load(path: str = LIB_PATH):
     lib.hcg_grid_batch.argtypes = [vp, ctypes.POINTER(FieldDataC), vp]
     lib.hcg_destroy_batch.argtypes = [vp]
     lib.hcg_get_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfoC)]
+    lib.hcg_batch_get_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
     for name in EXPORTED:
         if name != "hcg_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -530,6 +531,14 @@ def hcg_sort_keys(keys: torch.Tensor, key_bits: int, stream=None):
     return ko, po
 
 
+class BorrowedPlan(Plan):
+    """A batch's plan of one field (hcg_batch_get_plan): valid while the batch
+    lives; destroying it is left to the batch."""
+
+    def destroy(self) -> None:
+        self.handle = None
+
+
 class Batch:
     """Owns an hcg_batch_t (one plan per field)."""
 
@@ -537,6 +546,12 @@ class Batch:
         self.handle = handle
         self.grids = grids
         self.ns = [int(n) for n in ns]
+
+    def plan(self, field: int) -> BorrowedPlan:
+        h = ctypes.c_void_p()
+        _check(load().hcg_batch_get_plan(self.handle, int(field), ctypes.byref(h)),
+               "hcg_batch_get_plan")
+        return BorrowedPlan(h, self.grids[field], self.ns[field])
 
     def info(self) -> dict:
         out = BatchInfoC()

@@ -311,7 +311,11 @@ void free_batch(hcg_batch_s* b) {
   if (b->d_fields) (void)hipFree(b->d_fields);
   if (b->d_segs) (void)hipFree(b->d_segs);
   if (b->d_ctl) (void)hipFree(b->d_ctl);
-  for (hcg_plan_t p : b->plans) (void)hcg_destroy(p);
+  for (hcg_plan_t p : b->plans) {
+    if (!p) continue;
+    p->batch_owned = 0;
+    (void)hcg_destroy(p);
+  }
   if (b->arena) (void)hipFree(b->arena);
   b->magic = 0;
   delete b;
@@ -664,5 +668,15 @@ extern "C" hcg_status hcg_get_batch_info(hcg_batch_t batch, hcg_batch_info* info
   info->persistent_blocks = batch->nblocks;
   info->launch = batch->strategy;
   for (int k = 0; k < 8; ++k) info->tune_ms[k] = batch->tune_ms[k];
+  return HCG_OK;
+}
+
+extern "C" hcg_status hcg_batch_get_plan(hcg_batch_t batch, int32_t field, hcg_plan_t* out) {
+  if (!batch || !out) return fail(HCG_E_ARG, "hcg_batch_get_plan: NULL pointer");
+  *out = nullptr;
+  if (!batch_is_live(batch)) return fail(HCG_E_STATE, "hcg_batch_get_plan: not a live batch");
+  if (field < 0 || field >= (int32_t)batch->plans.size())
+    return fail(HCG_E_ARG, "hcg_batch_get_plan: field %d out of range", field);
+  *out = batch->plans[field];
   return HCG_OK;
 }

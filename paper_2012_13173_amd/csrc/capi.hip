@@ -69,6 +69,8 @@ extern "C" const char* hcg_last_error(void) { return g_last_error.c_str(); }
 extern "C" hcg_status hcg_destroy(hcg_plan_t plan) {
   if (!plan) return HCG_OK;
   if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_destroy: not a live plan");
+  if (plan->batch_owned)
+    return fail(HCG_E_STATE, "hcg_destroy: the plan belongs to a batch (hcg_destroy_batch frees it)");
   plan_unregister(plan);
   int cur = -1;
   (void)hipGetDevice(&cur);

@@ -178,6 +178,7 @@ __device__ __forceinline__ float e4m3_cvt_to_f32(uint32_t c) {
 struct hcg_plan_s {
   uint64_t magic;
   int device;
+  int batch_owned;  // a plan of a batch: freed with the batch only
   int64_t n;
   int32_t nside;
   uint32_t pix_base, pix_max;

@@ -1481,6 +1481,7 @@ hcg_status plan_build_fields(int32_t nf, const hcg_field_desc* fd, const hcg_opt
     p->flags = P.flags;
     p->cells = P.cells;
     p->arena = nullptr;  // in the shared arena
+    p->batch_owned = 1;
     plan_register(p);
     plans[f] = p;
   }

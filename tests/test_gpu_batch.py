@@ -229,3 +229,39 @@ def test_mixed_form_batch_matches_oracle_and_single_calls(launch):
     with pytest.raises(hcg.HcgError):
         hcg.hcg_grid_batch(b, spectra, cubes, wts, dtypes=forms, chan_scales=bad)
     b.destroy()
+
+
+def test_batch_plans_equal_single_plans():
+    """The batch builds every plan step for all fields in shared launches;
+    each field's plan must equal hcg_plan's bit for bit: pixel range, sorted
+    keys, permutation, ring table, tile ranges.  The fields differ in nside
+    (kernel width), sample count and key bits, so the shared sort runs more
+    passes than some fields need."""
+    ws = _fields()
+    ws.append(synth.small_cube(n=3000, nchan=5, nx=7, ny=5, seed=209, fwhm_arcmin=8.0,
+                               cell_arcmin=3.0, name="coarse"))
+    b = _plan(ws)
+    lib = hcg.load()
+    for i, w in enumerate(ws):
+        bp = b.plan(i)
+        sp = hcg.hcg_plan(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+        bi, si = bp.info(), sp.info()
+        for k in ("n", "nside", "key_bits", "pix_base", "pix_max", "ring_first", "ring_last",
+                  "ntiles_x", "ntiles_y", "max_ranges", "sort_passes"):
+            assert bi[k] == si[k], (w.name, k, bi[k], si[k])
+        for which in (hcg.HCG_ARR_KEYS, hcg.HCG_ARR_PERM, hcg.HCG_ARR_RING_CSR,
+                      hcg.HCG_ARR_TILE_NRANGES):
+            assert torch.equal(bp.export(which), sp.export(which)), (w.name, which)
+        # tile ranges: the used slots of every tile
+        nr = hcg.u32(sp.export(hcg.HCG_ARR_TILE_NRANGES))
+        rb = hcg.u32(bp.export(hcg.HCG_ARR_TILE_RANGES)).reshape(-1, si["max_ranges"], 2)
+        rs = hcg.u32(sp.export(hcg.HCG_ARR_TILE_RANGES)).reshape(-1, si["max_ranges"], 2)
+        for t in range(nr.shape[0]):
+            assert np.array_equal(rb[t, :nr[t]], rs[t, :nr[t]]), (w.name, t)
+        assert bp.stats() == sp.stats(), w.name
+        # a batch's plan is not the caller's to destroy
+        assert lib.hcg_destroy(bp.handle) == hcg.HCG_E_STATE
+        sp.destroy()
+    with pytest.raises(hcg.HcgError):
+        b.plan(len(ws))
+    b.destroy()
