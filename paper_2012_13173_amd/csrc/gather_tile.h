@@ -83,28 +83,61 @@ __device__ inline void block_centres(const GatherArgs& a, int tx, int ty, int t,
 // and increasing), so that every aligned group of 8 candidates is one group
 // of the plan-ordered spectra.  Samples added this way lie outside the
 // plan's ranges, hence beyond R of every cell of the tile: weight 0.
+//
+// With kPhase every range [lo, hi) is read from its phase point on: the
+// first multiple w of M = (hi - lo) rounded up to kPhaseQuantum at or after
+// lo, i.e. as [w, hi) followed by [lo, w).  Tiles side by side on a row of
+// the map reach each ring over ranges of about the same length, shifted
+// along the ring; unrotated, a tile meets a sample shared with its eastern
+// neighbour about one tile width of candidates after that neighbour did,
+// and the rows read by the other tiles of the XCD in that interval evict it
+// from L2.  Rotated to a common phase, both meet the shared samples at about
+// the same place in their lists.  The set of candidates is unchanged; the
+// order only decides which of them share a matrix-core step.  A tile's
+// ranges then take up to twice their number of entries, so a tile of more
+// than kMaxRangesLimit / 2 ranges (a ring split at longitude 0 gives two)
+// keeps the plan's order.
+constexpr uint32_t kPhaseQuantum = 128;
+template <bool kPhase = false>
 __device__ inline uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32_t nr, uint2* s_rng,
-                                 uint32_t* s_pre, uint32_t npad = 0) {
+                                        uint32_t* s_pre, uint32_t npad = 0) {
   const int nt = blockDim.x;
-  for (uint32_t r = threadIdx.x; r < nr; r += nt) s_rng[r] = ranges[r];
+  // rotated: the plan's ranges go to the upper half, the staged ones are
+  // written from the start (entry r is read before entries 2r, 2r + 1 are
+  // written, and 2r + 1 < kMaxRangesLimit / 2 + r + 1)
+  const bool rotate = kPhase && nr <= (uint32_t)kMaxRangesLimit / 2;
+  const uint32_t kIn = rotate ? kMaxRangesLimit / 2 : 0;
+  for (uint32_t r = threadIdx.x; r < nr; r += nt) s_rng[kIn + r] = ranges[r];
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t acc = 0, end = 0;
+    uint32_t acc = 0, end = 0, o = 0;
     for (uint32_t r = 0; r < nr; ++r) {
+      uint2 v = s_rng[kIn + r];
       if (npad) {
-        const uint2 v = s_rng[r];
         const uint32_t lo = max(v.x & ~7u, end);
         const uint32_t hi = max(lo, min((v.y + 7u) & ~7u, npad));
-        s_rng[r] = make_uint2(lo, hi);
+        v = make_uint2(lo, hi);
         end = hi;
       }
-      s_pre[r] = acc;
-      acc += s_rng[r].y - s_rng[r].x;
+      if (rotate && v.y > v.x) {
+        const uint64_t M = (uint64_t)(v.y - v.x + kPhaseQuantum - 1) / kPhaseQuantum * kPhaseQuantum;
+        const uint64_t w = ((uint64_t)v.x + M - 1) / M * M;
+        if (w > v.x && w < v.y) {
+          s_pre[o] = acc;
+          s_rng[o++] = make_uint2((uint32_t)w, v.y);
+          acc += v.y - (uint32_t)w;
+          v.y = (uint32_t)w;
+        }
+      }
+      s_pre[o] = acc;
+      s_rng[o++] = v;
+      acc += v.y - v.x;
     }
-    s_pre[nr] = acc;
+    s_pre[o] = acc;
+    s_pre[kMaxRangesLimit] = acc;
   }
   __syncthreads();
-  return s_pre[nr];
+  return s_pre[kMaxRangesLimit];
 }
 
 // Sorted position of candidate q; *cur is a monotone cursor over ranges.
@@ -258,8 +291,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   };
 
   const uint32_t total =
-      stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre,
-                   kPacked ? (a.sentinel + 7u) & ~7u : 0u);
+      stage_ranges<true>(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], s_rng, s_pre,
+                         kPacked ? (a.sentinel + 7u) & ~7u : 0u);
   if (tid < 64) block_centres(a, tx, ty, tid, sm.ctr);
 
   floatx4 acc[4][4 * kQW];
