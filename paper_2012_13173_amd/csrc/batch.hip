@@ -23,6 +23,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gather_tile.h"
@@ -54,11 +55,18 @@ __global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
   for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
 }
 
+// LDS of a class's workgroup: the few-channel class runs one wave per tile
+// on a small footprint, the matrix-core classes four waves per (tile, slab).
+template <int kCls>
+using ClassSmem = typename std::conditional<kCls == kClsCells, CellsSmem, GatherSmem>::type;
+template <int kCls>
+constexpr int class_threads() { return kCls == kClsCells ? 64 : 256; }
+
 template <int kCls, int kQW, bool kWide>
 __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
                                                          const BatchSeg* __restrict__ segs,
                                                          uint32_t* __restrict__ ctl) {
-  __shared__ GatherSmem sm;
+  __shared__ ClassSmem<kCls> sm;
   __shared__ uint32_t s_item;
   const uint32_t total = ctl[8];
   const uint32_t nseg = ctl[9];
@@ -91,7 +99,7 @@ __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __res
     const uint32_t tile = local - slab * sg.ntiles;
     const GatherArgs& a = fields[sg.field];  // read on demand (scalar loads)
     if constexpr (kCls == kClsCells) {
-      gather_cells_tile_wg(a, (int)tile, sm);
+      gather_cells_tile(a, (int)tile, sm);
     } else if constexpr (kCls >= kClsScalarRows) {  // 256-channel slabs
       gather_tile<kCls - kClsScalarRows, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
     } else if constexpr (kCls == kBF16Split) {  // 256-channel slabs only (registers)
@@ -115,7 +123,7 @@ template <int kCls, int kQW, bool kWide>
 __global__ void __launch_bounds__(256, 2) k_gather_items(const GatherArgs* __restrict__ fields,
                                                          const BatchSeg* __restrict__ segs,
                                                          uint32_t nseg) {
-  __shared__ GatherSmem sm;
+  __shared__ ClassSmem<kCls> sm;
   const uint32_t it = blockIdx.x;
   uint32_t lo = 0, hi = nseg - 1;
   while (lo < hi) {
@@ -126,7 +134,7 @@ __global__ void __launch_bounds__(256, 2) k_gather_items(const GatherArgs* __res
   const uint32_t local = it - sg.base;
   const GatherArgs& a = fields[sg.field];
   if constexpr (kCls == kClsCells) {
-    gather_cells_tile_wg(a, (int)local, sm);
+    gather_cells_tile(a, (int)local, sm);
   } else {
     const uint32_t per_slab = (uint32_t)a.tiles_per_xcd * 8u;
     const uint32_t slab = local / per_slab;
@@ -160,10 +168,14 @@ struct ClassLaunch {
 template <int kCls, int kQW, bool kWide>
 void launch_one(const ClassLaunch& l, const GatherArgs* fields, const BatchSeg* segs,
                 uint32_t* ctl, hipStream_t stream) {
+  // the few-channel class: one-wave workgroups, four times as many in the
+  // persistent grid (eight per CU, 131 KB of LDS)
+  constexpr int kThreads = class_threads<kCls>();
   if (l.strategy == kLaunchItems)
-    k_gather_items<kCls, kQW, kWide><<<l.nitems, 256, 0, stream>>>(fields, segs, l.nseg);
+    k_gather_items<kCls, kQW, kWide><<<l.nitems, kThreads, 0, stream>>>(fields, segs, l.nseg);
   else
-    k_gather_batch<kCls, kQW, kWide><<<l.nblocks, 256, 0, stream>>>(fields, segs, ctl);
+    k_gather_batch<kCls, kQW, kWide><<<l.nblocks * (256 / kThreads), kThreads, 0, stream>>>(
+        fields, segs, ctl);
 }
 
 template <int kCls>

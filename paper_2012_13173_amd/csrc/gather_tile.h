@@ -75,14 +75,35 @@ __device__ inline void block_centres(const GatherArgs& a, int tx, int ty, int t,
   if (i == 0) ctr[cb] = make_double4(c.x, c.y, c.z, thr);
 }
 
+// Inclusive scans across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_scan_add(uint32_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_scan_max(uint32_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x = max(x, y);
+  }
+  return x;
+}
+
 // Loads the tile's candidate ranges into LDS with exclusive prefix sums;
-// returns the total candidate count.  blockDim.x threads take part.
+// returns the total candidate count.  blockDim.x (>= 64) threads take part;
+// the first wave computes the prefix sums, 64 ranges at a time.
 // With npad > 0 (the sample count rounded up to a multiple of 8) every range
 // is widened to whole groups of 8 sorted positions, capped at npad, and cut
 // where it would overlap the previous one (the plan's ranges are disjoint
 // and increasing), so that every aligned group of 8 candidates is one group
 // of the plan-ordered spectra.  Samples added this way lie outside the
-// plan's ranges, hence beyond R of every cell of the tile: weight 0.
+// plan's ranges, hence beyond R of every cell of the tile: weight 0.  The
+// cut is where the previous widened range ends: the running maximum of
+// max(lo rounded down, hi rounded up and capped) over the ranges before.
 //
 // With kPhase every range [lo, hi) is read from its phase point on: the
 // first multiple w of M = (hi - lo) rounded up to kPhaseQuantum at or after
@@ -102,39 +123,63 @@ template <bool kPhase = false>
 __device__ inline uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32_t nr, uint2* s_rng,
                                         uint32_t* s_pre, uint32_t npad = 0) {
   const int nt = blockDim.x;
-  // rotated: the plan's ranges go to the upper half, the staged ones are
-  // written from the start (entry r is read before entries 2r, 2r + 1 are
-  // written, and 2r + 1 < kMaxRangesLimit / 2 + r + 1)
+  // rotated: the plan's ranges go to the upper half and the staged ones are
+  // written from the start; a chunk of 64 reads its entries before it
+  // writes, and chunk j writes below 128 j + 128 <= kMaxRangesLimit / 2 +
+  // 64 (j + 1), where the next chunk's entries begin (j <= 7)
   const bool rotate = kPhase && nr <= (uint32_t)kMaxRangesLimit / 2;
   const uint32_t kIn = rotate ? kMaxRangesLimit / 2 : 0;
   for (uint32_t r = threadIdx.x; r < nr; r += nt) s_rng[kIn + r] = ranges[r];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0, end = 0, o = 0;
-    for (uint32_t r = 0; r < nr; ++r) {
-      uint2 v = s_rng[kIn + r];
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    uint32_t end = 0, acc = 0, o = 0;  // carried from chunk to chunk
+    for (uint32_t base = 0; base < nr; base += 64) {
+      const uint32_t r = base + l;
+      const bool live = r < nr;
+      uint2 v = live ? s_rng[kIn + r] : make_uint2(0u, 0u);
       if (npad) {
-        const uint32_t lo = max(v.x & ~7u, end);
-        const uint32_t hi = max(lo, min((v.y + 7u) & ~7u, npad));
-        v = make_uint2(lo, hi);
-        end = hi;
+        const uint32_t lo8 = v.x & ~7u;
+        const uint32_t hi8 = min((v.y + 7u) & ~7u, npad);
+        const uint32_t run = wave_scan_max(live ? max(lo8, hi8) : 0u, l);
+        uint32_t prev = __shfl_up(run, 1);
+        prev = max(l == 0 ? 0u : prev, end);
+        const uint32_t lo = max(lo8, prev);
+        v = live ? make_uint2(lo, max(lo, hi8)) : make_uint2(0u, 0u);
+        end = max(end, (uint32_t)__shfl(run, 63));
       }
+      uint32_t w = 0u;
+      bool split = false;
       if (rotate && v.y > v.x) {
         const uint64_t M = (uint64_t)(v.y - v.x + kPhaseQuantum - 1) / kPhaseQuantum * kPhaseQuantum;
-        const uint64_t w = ((uint64_t)v.x + M - 1) / M * M;
-        if (w > v.x && w < v.y) {
-          s_pre[o] = acc;
-          s_rng[o++] = make_uint2((uint32_t)w, v.y);
-          acc += v.y - (uint32_t)w;
-          v.y = (uint32_t)w;
+        const uint64_t wq = ((uint64_t)v.x + M - 1) / M * M;
+        split = wq > v.x && wq < v.y;
+        w = (uint32_t)wq;
+      }
+      const uint32_t len = v.y - v.x;
+      const uint32_t cnt = live ? (split ? 2u : 1u) : 0u;
+      const uint32_t cnt_in = wave_scan_add(cnt, l);
+      const uint32_t len_in = wave_scan_add(len, l);
+      const uint32_t at = o + cnt_in - cnt;
+      const uint32_t pre = acc + len_in - len;
+      if (live) {
+        if (split) {
+          s_rng[at] = make_uint2(w, v.y);
+          s_pre[at] = pre;
+          s_rng[at + 1] = make_uint2(v.x, w);
+          s_pre[at + 1] = pre + (v.y - w);
+        } else {
+          s_rng[at] = v;
+          s_pre[at] = pre;
         }
       }
-      s_pre[o] = acc;
-      s_rng[o++] = v;
-      acc += v.y - v.x;
+      o += (uint32_t)__shfl(cnt_in, 63);
+      acc += (uint32_t)__shfl(len_in, 63);
     }
-    s_pre[o] = acc;
-    s_pre[kMaxRangesLimit] = acc;
+    if (l == 0) {
+      s_pre[o] = acc;
+      s_pre[kMaxRangesLimit] = acc;
+    }
   }
   __syncthreads();
   return s_pre[kMaxRangesLimit];
@@ -912,11 +957,23 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   }
 }
 
-// Few channels (C <= 8) for a 256-thread workgroup: one lane per cell, the
-// four waves take every fourth block of 64 candidates and their FP64 partial
-// sums are added at the end.
-__device__ inline void gather_cells_tile_wg(const GatherArgs& a, int tile, GatherSmem& sm) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// LDS of the few-channel gather in a batch (one wave per workgroup): small,
+// so that many tiles are in flight on a CU -- most tiles of a sparse field
+// hold a few candidates, and their time is the latency of the range, vector
+// and value loads.
+struct CellsSmem {
+  uint2 rng[kMaxRangesLimit];
+  uint32_t pre[kMaxRangesLimit + 1];
+  double4 xyz[kKB];
+  float spec[kKB][8];
+};
+
+// Few channels (C <= kCM <= 8) for a 64-thread workgroup: one lane per cell
+// of the 8 x 8 tile, candidates staged 64 at a time, weights and sums in
+// FP64 (the per-plan k_gather_cells without the split of the candidates).
+template <int kCM>
+__device__ inline void gather_cells_tile_wave(const GatherArgs& a, int tile, CellsSmem& sm) {
+  const int lane = threadIdx.x;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const GridGeom& g = a.g;
   const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
@@ -925,64 +982,46 @@ __device__ inline void gather_cells_tile_wg(const GatherArgs& a, int tile, Gathe
       stage_ranges(a.ranges + (int64_t)tile * a.maxr, a.nranges[tile], sm.rng, sm.pre);
   const int C = (int)a.C;
   const float* spec = (const float*)a.spec;
-  double4* wxyz = (double4*)&sm.Araw[0][0] + wave * kKB;                      // [4][64]
-  float* wspec = (float*)((double4*)&sm.Araw[0][0] + 4 * kKB) + wave * kKB * 8;  // [4][64][8]
-  double acc[8];
+  double acc[kCM];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int c = 0; c < kCM; ++c) acc[c] = 0.0;
   double wsum = 0.0;
   uint32_t cur = 0;
-  const uint32_t nblk = (total + kKB - 1) / kKB;
-  for (uint32_t b0 = 0; b0 < nblk; b0 += 4) {
-    const uint32_t blk = b0 + wave;
-    const uint32_t q = blk * kKB + lane;
-    if (blk < nblk && q < total) {
+  for (uint32_t q0 = 0; q0 < total; q0 += kKB) {
+    const uint32_t q = q0 + lane;
+    if (q < total) {
       const uint32_t pos = cand_pos(q, sm.rng, sm.pre, &cur);
-      wxyz[lane] = a.xyz[pos];
+      sm.xyz[lane] = a.xyz[pos];
       const int64_t row = a.perm[pos];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) wspec[lane * 8 + c] = (c < C) ? spec[row * C + c] : 0.f;
-    } else {
-      const double nan = __builtin_nan("");
-      wxyz[lane] = make_double4(nan, nan, nan, nan);
+      for (int c = 0; c < kCM; ++c) sm.spec[lane][c] = (c < C) ? spec[row * C + c] : 0.f;
     }
     __syncthreads();
-    if (blk < nblk) {
-      const int kmax = (int)min<uint32_t>(kKB, total - blk * kKB);
-      for (int k = 0; k < kmax; ++k) {
-        const double c2 = chord2(cell, wxyz[k]);
-        if (c2 <= a.c2R) {
-          const double w = pair_weight64(c2, a.kern.wscale);
-          wsum += w;
+    const int kmax = (int)min<uint32_t>(kKB, total - q0);
+    for (int k = 0; k < kmax; ++k) {
+      const double c2 = chord2(cell, sm.xyz[k]);
+      if (c2 <= a.c2R) {
+        const double w = pair_weight64(c2, a.kern.wscale);
+        wsum += w;
 #pragma unroll
-          for (int c = 0; c < 8; ++c) acc[c] += w * (double)wspec[k * 8 + c];
-        }
+        for (int c = 0; c < kCM; ++c) acc[c] += w * (double)sm.spec[k][c];
       }
     }
     __syncthreads();
   }
-  double* red = (double*)&sm.Araw[0][0];  // [9][64]
-  for (int w = 1; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) red[c * 64 + lane] = acc[c];
-      red[8 * 64 + lane] = wsum;
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] += red[c * 64 + lane];
-      wsum += red[8 * 64 + lane];
-    }
-    __syncthreads();
-  }
-  if (wave != 0 || ix >= g.nx || iy >= g.ny) return;
+  if (ix >= g.nx || iy >= g.ny) return;
   const int64_t G = (int64_t)g.nx * g.ny;
   const int64_t cellidx = (int64_t)iy * g.nx + ix;
   if (a.wmap) a.wmap[cellidx] = (float)wsum;
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
+  for (int c = 0; c < kCM; ++c)
     if (c < C) a.cube[c * G + cellidx] = (wsum != 0.0) ? (float)(acc[c] / wsum) : __builtin_nanf("");
+}
+
+// The few-channel gather of one tile, by channel count.
+__device__ inline void gather_cells_tile(const GatherArgs& a, int tile, CellsSmem& sm) {
+  if (a.C == 1) gather_cells_tile_wave<1>(a, tile, sm);
+  else gather_cells_tile_wave<8>(a, tile, sm);
 }
 
 }  // namespace hcg
