@@ -268,12 +268,18 @@ __device__ __forceinline__ uint32_t elem16(uint2 d, int q) {
   return (q & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// LDS slot of staged candidate k: one double4 of padding after every 8, so
+// that the four 16-lane groups of a wave reading candidates 8 apart (the
+// 16-bit and FP8 weights: lane l takes the 8 candidates of group l / 16)
+// meet different banks instead of the same ones 256 bytes apart.
+__device__ __forceinline__ int xyz_slot(int k) { return k + (k >> 3); }
+
 // LDS of one workgroup of the gather (shared by the per-plan kernel and the
 // persistent batch kernel).
 struct GatherSmem {
   uint2 rng[kMaxRangesLimit];
   uint32_t pre[kMaxRangesLimit + 1];
-  double4 xyz[3][kKB];  // staged unit vectors, three blocks in flight
+  double4 xyz[3][kKB + kKB / 8];  // staged unit vectors, three blocks in flight (xyz_slot)
   double4 ctr[4];       // cell-block centres and coarse thresholds
   uint32_t row[3][kKB];
   uint4 Araw[2][1024];  // weights in the A-operand layout, two blocks in flight
@@ -404,7 +410,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   };
   auto stage = [&](int buf) {
     if (wave == 0) {
-      sm.xyz[buf][tid] = make_double4(nx, ny, nz, 0.0);
+      sm.xyz[buf][xyz_slot(tid)] = make_double4(nx, ny, nz, 0.0);
       if (!kPacked) sm.row[buf][tid] = nrow;
       else if ((tid & 7) == 0) sm.row[buf][tid >> 3] = nrow;
     }
@@ -419,7 +425,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
     const double4* s_xyz = sm.xyz[buf];
     uint32_t nzbits = 0;
     const double4 c = sm.ctr[wave];
-    const double c2c = chord2(CellVec{c.x, c.y, c.z}, s_xyz[lane]);
+    const double c2c = chord2(CellVec{c.x, c.y, c.z}, s_xyz[xyz_slot(lane)]);
     const uint64_t bm = __ballot(c2c <= c.w);
     const uint32_t lo = (uint32_t)bm, hi = (uint32_t)(bm >> 32);
     if (kForm == kF32) {
@@ -428,7 +434,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       while (pm) {
         const int ks = __builtin_ctz(pm);
         pm &= pm - 1u;
-        const double4 sv = s_xyz[4 * ks + (lane >> 4)];
+        const double4 sv = s_xyz[xyz_slot(4 * ks + (lane >> 4))];
         const double c2 = chord2(cell, sv);
         float wf = 0.f;
         if (c2 <= a.c2R) wf = weight(c2, sv);
@@ -452,7 +458,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           const int k0 = kK * ks + 8 * grp;
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
-            const double4 sv = s_xyz[k0 + t];
+            const double4 sv = s_xyz[xyz_slot(k0 + t)];
             const double c2 = chord2(cell, sv);
             uint32_t h = 0u, l = 0u;
             if (c2 <= a.c2R) {
@@ -526,9 +532,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   using BT = typename PackedB<kForm>::T;
   constexpr int kNJ = kPacked ? 4 * kQW : 1;
   constexpr int kNSP = kPacked ? kNS : 1;
-  // plan-ordered: the k-steps loaded at the block's top (the others, where
-  // registers are short, once the previous k-step's products are issued)
-  constexpr int kEarly = (kQW == 1 || kForm == kFP8S) ? kNSP : 1;
+  // plan-ordered: the k-steps loaded at the block's top -- all of them,
+  // except in the wide-support kernels of 512-channel slabs, whose
+  // registers take only the first (the others are loaded once the previous
+  // k-step's products are issued)
+  constexpr int kEarly = (kQW == 1 || kForm == kFP8S || !kWide) ? kNSP : 1;
   BT bq[kNSP][kNJ];
   BT bql[kNSP][kNJ];
   // Plan-ordered planes hold Cp = C rounded up to 16 channels, so a
