@@ -9,7 +9,10 @@
   sample as a candidate -- cells within R + the 8 x 8 tile's diagonal + a
   HEALPix pixel (exactly the cells within R for C <= 8);
 * the binding refuses spectra whose row count is not the plan's sample count,
-  before any launch.
+  before any launch;
+* tiles with more candidate ranges than the phase-rotated staging holds (a
+  wide support at longitude 0, two ranges per ring) next to tiles that are
+  rotated, in the FP32 form and two matrix-core forms.
 """
 import math
 
@@ -182,3 +185,28 @@ def test_batch_with_a_wide_support_field():
         assert_cube_close(c.cpu().numpy(), Vr, TOL_F32, w.name)
         assert_weights_close(x.cpu().numpy(), Wr)
     b.destroy()
+
+
+def test_tiles_of_more_ranges_than_a_rotation_holds():
+    # centred on longitude 0 with a 38' support and nside 8192 (rings 0.28'
+    # apart): tiles that straddle longitude 0 reach every ring on both sides
+    # of it, two ranges per ring, more than half the staging room, and are
+    # read in the plan's order; the other tiles are read phase-rotated
+    # (40 x 16 cells of 5': the outer tile columns do not reach longitude 0)
+    w = synth.small_cube(n=50_000, nchan=16, nx=40, ny=16, cell_arcmin=5.0, fwhm_arcmin=30.0,
+                         pad_arcmin=40.0, lon_c=0.0, lat_c=10.0, nside=8192, seed=490)
+    plan = _plan(w)
+    nr = hcg.u32(plan.export(hcg.HCG_ARR_TILE_NRANGES))
+    print(f"ranges per tile: {sorted(set(nr.tolist()))}", flush=True)
+    assert nr.max() > 512 and nr.min() <= 512
+    Vr, Wr, _ = run_oracle(w)
+    cube, W = _grid(w, plan)
+    assert_cube_close(cube.cpu().numpy(), Vr, TOL_F32, "f32, > 512 ranges")
+    assert_weights_close(W.cpu().numpy(), Wr)
+    for name in ("f16_scaled", "bf16_split"):
+        form, tol = FORMS[name]
+        for packed in (False, True):
+            cube, W = _grid(w, plan, form, packed)
+            assert_cube_close(cube.cpu().numpy(), Vr, tol, f"{name} packed={packed}, > 512 ranges")
+            assert_weights_close(W.cpu().numpy(), Wr)
+    plan.destroy()
