@@ -59,6 +59,8 @@ __global__ void __launch_bounds__(256, 2) k_gather_mfma(const GatherArgs a) {
 // k_cells_finish adds them in split order.  nsplit = 1 writes the map
 // directly.  kMask: a non-finite value is a flag, left out of its channel's
 // sums (numerator and weights); the per-channel weights go to wcube.
+// kGen: a kernel shape other than the circular Gaussian (FP64 weights
+// through pair_weight_gen); the Gaussian kernels do not carry that path.
 // ---------------------------------------------------------------------------
 template <int kCM, bool kMask>
 struct CellSlots {
@@ -66,7 +68,7 @@ struct CellSlots {
   static constexpr int kN = kCM + kW;         // partial sums per cell
 };
 
-template <int kCM, bool kCount, bool kMask = false>
+template <int kCM, bool kCount, bool kMask = false, bool kGen = false>
 __global__ void __launch_bounds__(64) k_gather_cells(
     const double4* __restrict__ cells, const double4* __restrict__ xyz,
     const uint32_t* __restrict__ perm, const uint2* __restrict__ ranges,
@@ -76,18 +78,22 @@ __global__ void __launch_bounds__(64) k_gather_cells(
     unsigned long long* __restrict__ pair_count, int nsplit, double* __restrict__ part) {
   constexpr int kM = kCM > 0 ? kCM : 1;
   constexpr int kW = CellSlots<kM, kMask>::kW;
-  __shared__ uint2 s_rng[kMaxRangesLimit];
-  __shared__ uint32_t s_pre[kMaxRangesLimit + 1];
-  __shared__ double4 s_xyz[kKB];
-  __shared__ float s_spec[kKB][kM];
+  // LDS of cells_lds_bytes(kM, maxr): staged vectors and values, then the
+  // tile's ranges sized to the plan's largest range count (not to
+  // kMaxRangesLimit), so that many one-wave workgroups fit on a CU
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  double4* s_xyz = (double4*)s_dyn;                   // [kKB]
+  float (*s_spec)[kM] = (float (*)[kM])(s_xyz + kKB);  // [kKB][kM]
+  uint2* s_rng = (uint2*)(s_spec + kKB);              // [maxr]
+  uint32_t* s_pre = (uint32_t*)(s_rng + maxr);        // [maxr + 1]
 
   const int tile = blockIdx.x;
   const int lane = threadIdx.x;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ix = tx * kTileX + (lane & 7), iy = ty * kTileY + (lane >> 3);
   const CellVec cell = cell_at(cells, g, ix, iy);
-  const CellFrame frame = (kp.type == kElliptic) ? cell_frame(cell)
-                                                 : CellFrame{0.0, 0.0, 0.0, 0.0, 0.0};
+  const CellFrame frame = (kGen && kp.type == kElliptic) ? cell_frame(cell)
+                                                         : CellFrame{0.0, 0.0, 0.0, 0.0, 0.0};
   const uint32_t total = stage_ranges(ranges + (int64_t)tile * maxr, nranges[tile], s_rng, s_pre);
 
   double accv[kM];
@@ -122,8 +128,8 @@ __global__ void __launch_bounds__(64) k_gather_cells(
         if (kCount) {
           ++npair;
         } else {
-          const double w = (kp.type == kGauss) ? pair_weight64(c2, kp.wscale)
-                                               : pair_weight_gen(kp, c2, v, cell, frame);
+          const double w = kGen ? pair_weight_gen(kp, c2, v, cell, frame)
+                                : pair_weight64(c2, kp.wscale);
           if constexpr (kMask) {
 #pragma unroll
             for (int c = 0; c < kM; ++c) {
@@ -223,6 +229,12 @@ static int cells_split(unsigned ntiles) {
              ? 1
              : (int)std::min<int64_t>(kCellsMaxSplit, (kCellsTargetGroups + ntiles - 1) / ntiles);
 }
+// Dynamic LDS of k_gather_cells for km staged values per candidate.
+static size_t cells_lds_bytes(int km, int maxr) {
+  return sizeof(double4) * kKB + sizeof(float) * kKB * km + sizeof(uint2) * maxr +
+         sizeof(uint32_t) * (maxr + 1);
+}
+
 static size_t cells_part_bytes(int nsplit, int cm, bool mask, unsigned ntiles) {
   if (nsplit <= 1) return 0;
   const int slots = cm + (mask ? cm : 1);
@@ -251,9 +263,12 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
   }
   const dim3 grid(ntiles, (unsigned)nsplit);
   const unsigned fin_blocks = (unsigned)((ntiles * (int64_t)kTileCells + 255) / 256);
-#define HCG_CELLS(CM, MASK)                                                                    \
+  // the circular Gaussian and the other kernel shapes are separate kernels,
+  // so the common case carries no general weight path in its registers
+  const bool gen = p->kern.type != kGauss;
+#define HCG_CELLS(CM, MASK, GEN)                                                               \
   do {                                                                                         \
-    k_gather_cells<CM, false, MASK><<<grid, 64, 0, stream>>>(                                  \
+    k_gather_cells<CM, false, MASK, GEN><<<grid, 64, cells_lds_bytes(CM, p->maxr), stream>>>(  \
         p->cells, p->xyz, p->perm, p->ranges, p->nranges, p->maxr, spec, C, p->grid, p->ntx,   \
         c2R, p->kern, cube, wmap, wcube, nullptr, nsplit, part);                               \
     if (nsplit > 1)                                                                            \
@@ -261,17 +276,21 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
                                                                p->grid, p->ntx, cube, wmap,    \
                                                                wcube);                         \
   } while (0)
+#define HCG_CELLS_CM(MASK, GEN)               \
+  do {                                        \
+    if (cm == 1) HCG_CELLS(1, MASK, GEN);      \
+    else if (cm == 2) HCG_CELLS(2, MASK, GEN); \
+    else if (cm == 4) HCG_CELLS(4, MASK, GEN); \
+    else HCG_CELLS(8, MASK, GEN);              \
+  } while (0)
   if (mask) {
-    if (cm == 1) HCG_CELLS(1, true);
-    else if (cm == 2) HCG_CELLS(2, true);
-    else if (cm == 4) HCG_CELLS(4, true);
-    else HCG_CELLS(8, true);
+    if (gen) HCG_CELLS_CM(true, true);
+    else HCG_CELLS_CM(true, false);
   } else {
-    if (cm == 1) HCG_CELLS(1, false);
-    else if (cm == 2) HCG_CELLS(2, false);
-    else if (cm == 4) HCG_CELLS(4, false);
-    else HCG_CELLS(8, false);
+    if (gen) HCG_CELLS_CM(false, true);
+    else HCG_CELLS_CM(false, false);
   }
+#undef HCG_CELLS_CM
 #undef HCG_CELLS
   const hipError_t le = hipGetLastError();
   if (owned) (void)hipFreeAsync(part, stream);
@@ -576,7 +595,7 @@ extern "C" hcg_status hcg_get_plan_stats(hcg_plan_t plan, hcg_plan_stats* stats,
     ~Free() { (void)hipFree(q); }
   } fr{dcount};
   HCG_HIP(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), stream));
-  k_gather_cells<0, true><<<ntiles, 64, 0, stream>>>(
+  k_gather_cells<0, true><<<ntiles, 64, cells_lds_bytes(1, p->maxr), stream>>>(
       p->cells, p->xyz, p->perm, p->ranges, p->nranges, p->maxr, nullptr, 0, p->grid, p->ntx,
       support_chord2(p), p->kern, nullptr, nullptr, nullptr, dcount, 1, nullptr);
   HCG_LAUNCH_CHECK("k_gather_cells<count>");

@@ -95,7 +95,9 @@ __device__ __forceinline__ uint32_t wave_scan_max(uint32_t x, int lane) {
 
 // Loads the tile's candidate ranges into LDS with exclusive prefix sums;
 // returns the total candidate count.  blockDim.x (>= 64) threads take part;
-// the first wave computes the prefix sums, 64 ranges at a time.
+// with widening or rotation the first wave computes the prefix sums, 64
+// ranges at a time (and s_pre needs kMaxRangesLimit + 1 entries); plain
+// ranges need s_rng[nr] and s_pre[nr + 1] only.
 // With npad > 0 (the sample count rounded up to a multiple of 8) every range
 // is widened to whole groups of 8 sorted positions, capped at npad, and cut
 // where it would overlap the previous one (the plan's ranges are disjoint
@@ -131,7 +133,20 @@ __device__ inline uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32
   const uint32_t kIn = rotate ? kMaxRangesLimit / 2 : 0;
   for (uint32_t r = threadIdx.x; r < nr; r += nt) s_rng[kIn + r] = ranges[r];
   __syncthreads();
-  if (threadIdx.x < 64) {
+  if (!kPhase && npad == 0) {
+    // plain ranges: one thread's loop, whose loads do not wait on the
+    // running sum (faster than the wave scans, whose shuffles each wait
+    // on LDS, for the few-channel gathers that stage ranges per workgroup
+    // of a split tile)
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      for (uint32_t r = 0; r < nr; ++r) {
+        s_pre[r] = acc;
+        acc += s_rng[r].y - s_rng[r].x;
+      }
+      s_pre[nr] = acc;
+    }
+  } else if (threadIdx.x < 64) {
     const int l = threadIdx.x;
     uint32_t end = 0, acc = 0, o = 0;  // carried from chunk to chunk
     for (uint32_t base = 0; base < nr; base += 64) {
@@ -182,7 +197,7 @@ __device__ inline uint32_t stage_ranges(const uint2* __restrict__ ranges, uint32
     }
   }
   __syncthreads();
-  return s_pre[kMaxRangesLimit];
+  return (!kPhase && npad == 0) ? s_pre[nr] : s_pre[kMaxRangesLimit];
 }
 
 // Sorted position of candidate q; *cur is a monotone cursor over ranges.
