@@ -592,7 +592,7 @@ typedef struct {
   int32_t tuned;             /* 1 once the configuration is fixed */
   int32_t graph_captured;    /* 1 once the launch is captured */
   int32_t persistent_blocks; /* 256-thread workgroups of the persistent kernels (the
-                                C <= 8 class runs four 64-thread ones for each) */
+                                C <= 8 class runs eight 64-thread ones for each) */
   int64_t items;             /* work items of the last build */
   double tune_ms[8];         /* autotuner timings, persistent then work-item
                                 launch, each (256, cost), (512, cost),

@@ -23,7 +23,6 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <type_traits>
 #include <vector>
 
 #include "gather_tile.h"
@@ -55,52 +54,93 @@ __global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
   for (int x = 0; x < kBatchXcds; ++x) ctl[x] = batch_seg_begin(total, x);
 }
 
-// LDS of a class's workgroup: the few-channel class runs one wave per tile
-// on a small footprint, the matrix-core classes four waves per (tile, slab).
-template <int kCls>
-using ClassSmem = typename std::conditional<kCls == kClsCells, CellsSmem, GatherSmem>::type;
-template <int kCls>
-constexpr int class_threads() { return kCls == kClsCells ? 64 : 256; }
+// The next item of a persistent workgroup: thread 0 pops one from its
+// XCD's segment, then from the others once it is empty (*k counts the
+// segments it has left); 0xFFFFFFFF when every segment is empty.  Called by
+// every thread of the workgroup.
+__device__ inline uint32_t batch_next_item(uint32_t* __restrict__ ctl, uint32_t total, int home,
+                                           int* k, uint32_t* s_item) {
+  if (threadIdx.x == 0) {
+    uint32_t it = 0xFFFFFFFFu;
+    while (*k < kBatchXcds) {
+      const int x = (home + *k) % kBatchXcds;
+      const uint32_t i = atomicAdd(&ctl[x], 1u);
+      if (i < batch_seg_begin(total, x + 1)) { it = i; break; }
+      ++*k;
+    }
+    *s_item = it;
+  }
+  __syncthreads();
+  const uint32_t it = __builtin_amdgcn_readfirstlane(*s_item);
+  __syncthreads();
+  return it;
+}
+
+// The segment of item it: the last one whose base is <= it.
+__device__ inline BatchSeg batch_seg_of(const BatchSeg* __restrict__ segs, uint32_t nseg,
+                                        uint32_t it) {
+  uint32_t lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
+  }
+  return segs[lo];
+}
+
+// The few-channel class (FP32, C <= 8): one wave per tile, on dynamic LDS of
+// cells_batch_lds_bytes(maxr) with maxr the largest range count of the
+// batch's plans, in kernels of their own (64 threads, so that the registers
+// of the matrix-core classes' bounds do not apply): many tiles in flight on
+// a CU.  Items are tiles; one workgroup per item ...
+__global__ void __launch_bounds__(64) k_cells_items(const GatherArgs* __restrict__ fields,
+                                                    const BatchSeg* __restrict__ segs,
+                                                    uint32_t nseg, int maxr) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  const uint32_t it = blockIdx.x;
+  const BatchSeg sg = batch_seg_of(segs, nseg, it);
+  gather_cells_tile(fields[sg.field], (int)(it - sg.base), cells_lds(s_dyn, maxr));
+}
+
+// ... or persistent workgroups popping items (sixteen per CU).
+__global__ void __launch_bounds__(64) k_cells_batch(const GatherArgs* __restrict__ fields,
+                                                    const BatchSeg* __restrict__ segs,
+                                                    uint32_t* __restrict__ ctl, int maxr) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  __shared__ uint32_t s_item;
+  const CellsLds L = cells_lds(s_dyn, maxr);
+  const uint32_t total = ctl[8];
+  const uint32_t nseg = ctl[9];
+  const int home = (int)(blockIdx.x % kBatchXcds);
+  int k = 0;
+  for (;;) {
+    const uint32_t it = batch_next_item(ctl, total, home, &k, &s_item);
+    if (it == 0xFFFFFFFFu) break;
+    const BatchSeg sg = batch_seg_of(segs, nseg, it);
+    gather_cells_tile(fields[sg.field], (int)(it - sg.base), L);
+    __syncthreads();
+  }
+}
 
 template <int kCls, int kQW, bool kWide>
 __global__ void __launch_bounds__(256, 2) k_gather_batch(const GatherArgs* __restrict__ fields,
                                                          const BatchSeg* __restrict__ segs,
                                                          uint32_t* __restrict__ ctl) {
-  __shared__ ClassSmem<kCls> sm;
+  static_assert(kCls != kClsCells, "the few-channel class has kernels of its own");
+  __shared__ GatherSmem sm;
   __shared__ uint32_t s_item;
   const uint32_t total = ctl[8];
   const uint32_t nseg = ctl[9];
   const int home = (int)(blockIdx.x % kBatchXcds);
   int k = 0;  // segments visited so far (thread 0 only)
   for (;;) {
-    if (threadIdx.x == 0) {
-      uint32_t it = 0xFFFFFFFFu;
-      while (k < kBatchXcds) {
-        const int x = (home + k) % kBatchXcds;
-        const uint32_t i = atomicAdd(&ctl[x], 1u);
-        if (i < batch_seg_begin(total, x + 1)) { it = i; break; }
-        ++k;
-      }
-      s_item = it;
-    }
-    __syncthreads();
-    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
+    const uint32_t it = batch_next_item(ctl, total, home, &k, &s_item);
     if (it == 0xFFFFFFFFu) break;
-    // the last segment whose base is <= it
-    uint32_t lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
-    }
-    const BatchSeg sg = segs[lo];
+    const BatchSeg sg = batch_seg_of(segs, nseg, it);
     const uint32_t local = it - sg.base;
     const uint32_t slab = local / sg.ntiles;
     const uint32_t tile = local - slab * sg.ntiles;
     const GatherArgs& a = fields[sg.field];  // read on demand (scalar loads)
-    if constexpr (kCls == kClsCells) {
-      gather_cells_tile(a, (int)tile, sm);
-    } else if constexpr (kCls >= kClsScalarRows) {  // 256-channel slabs
+    if constexpr (kCls >= kClsScalarRows) {  // 256-channel slabs
       gather_tile<kCls - kClsScalarRows, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
     } else if constexpr (kCls == kBF16Split) {  // 256-channel slabs only (registers)
       gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
@@ -123,31 +163,23 @@ template <int kCls, int kQW, bool kWide>
 __global__ void __launch_bounds__(256, 2) k_gather_items(const GatherArgs* __restrict__ fields,
                                                          const BatchSeg* __restrict__ segs,
                                                          uint32_t nseg) {
-  __shared__ ClassSmem<kCls> sm;
+  static_assert(kCls != kClsCells, "the few-channel class has kernels of its own");
+  __shared__ GatherSmem sm;
   const uint32_t it = blockIdx.x;
-  uint32_t lo = 0, hi = nseg - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (segs[mid].base <= it) lo = mid; else hi = mid - 1;
-  }
-  const BatchSeg sg = segs[lo];
+  const BatchSeg sg = batch_seg_of(segs, nseg, it);
   const uint32_t local = it - sg.base;
   const GatherArgs& a = fields[sg.field];
-  if constexpr (kCls == kClsCells) {
-    gather_cells_tile(a, (int)local, sm);
+  const uint32_t per_slab = (uint32_t)a.tiles_per_xcd * 8u;
+  const uint32_t slab = local / per_slab;
+  const uint32_t loc = local - slab * per_slab;
+  const uint32_t tile = (loc & 7u) * (uint32_t)a.tiles_per_xcd + (loc >> 3);
+  if (tile >= (uint32_t)a.ntiles) return;
+  if constexpr (kCls >= kClsScalarRows) {
+    gather_tile<kCls - kClsScalarRows, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
+  } else if constexpr (kCls == kBF16Split) {
+    gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
   } else {
-    const uint32_t per_slab = (uint32_t)a.tiles_per_xcd * 8u;
-    const uint32_t slab = local / per_slab;
-    const uint32_t loc = local - slab * per_slab;
-    const uint32_t tile = (loc & 7u) * (uint32_t)a.tiles_per_xcd + (loc >> 3);
-    if (tile >= (uint32_t)a.ntiles) return;
-    if constexpr (kCls >= kClsScalarRows) {
-      gather_tile<kCls - kClsScalarRows, 1, false, false, kWide, false>(a, (int)tile, (int)slab, sm);
-    } else if constexpr (kCls == kBF16Split) {
-      gather_tile<kBF16Split, 1, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
-    } else {
-      gather_tile<kCls, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
-    }
+    gather_tile<kCls, kQW, true, false, kWide, true>(a, (int)tile, (int)slab, sm);
   }
 }
 
@@ -163,19 +195,16 @@ struct ClassLaunch {
   int strategy;
   int nblocks;
   uint32_t nitems, nseg;
+  int cells_maxr;  // largest range count of the batch's plans (few-channel LDS)
 };
 
 template <int kCls, int kQW, bool kWide>
 void launch_one(const ClassLaunch& l, const GatherArgs* fields, const BatchSeg* segs,
                 uint32_t* ctl, hipStream_t stream) {
-  // the few-channel class: one-wave workgroups, four times as many in the
-  // persistent grid (eight per CU, 131 KB of LDS)
-  constexpr int kThreads = class_threads<kCls>();
   if (l.strategy == kLaunchItems)
-    k_gather_items<kCls, kQW, kWide><<<l.nitems, kThreads, 0, stream>>>(fields, segs, l.nseg);
+    k_gather_items<kCls, kQW, kWide><<<l.nitems, 256, 0, stream>>>(fields, segs, l.nseg);
   else
-    k_gather_batch<kCls, kQW, kWide><<<l.nblocks * (256 / kThreads), kThreads, 0, stream>>>(
-        fields, segs, ctl);
+    k_gather_batch<kCls, kQW, kWide><<<l.nblocks, 256, 0, stream>>>(fields, segs, ctl);
 }
 
 template <int kCls>
@@ -202,7 +231,15 @@ hcg_status launch_class(int cls, int qw, bool wide, const GatherArgs* fields,
     HCG_LAUNCH_CHECK("k_batch_reset");
   }
   switch (cls) {
-    case kClsCells: launch_cls<kClsCells>(1, wide, fields, segs, ctl, l, stream); break;
+    case kClsCells: {
+      // one-wave workgroups; the persistent grid eight per 256-thread one
+      const size_t lds = cells_batch_lds_bytes(l.cells_maxr);
+      if (l.strategy == kLaunchItems)
+        k_cells_items<<<l.nitems, 64, lds, stream>>>(fields, segs, l.nseg, l.cells_maxr);
+      else
+        k_cells_batch<<<l.nblocks * 8, 64, lds, stream>>>(fields, segs, ctl, l.cells_maxr);
+      break;
+    }
     case kBF16Split: launch_cls<kBF16Split>(1, wide, fields, segs, ctl, l, stream); break;
     case kF32: launch_cls<kF32>(qw, wide, fields, segs, ctl, l, stream); break;
     case kBF16: launch_cls<kBF16>(qw, wide, fields, segs, ctl, l, stream); break;
@@ -292,6 +329,7 @@ struct hcg_batch_s {
   uint32_t nseg[kClasses] = {};
   bool wide[kClasses] = {};
   int qw = 0, cost_order = 1, strategy = kLaunchPersistent;
+  int cells_maxr = 0;  // largest range count of the plans
   bool tuned = false;
   double tune_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipStream_t cap_stream = nullptr;
@@ -402,7 +440,7 @@ hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
   const size_t nf = b->plans.size();
   for (int c = 0; c < kClasses; ++c) {
     if (!b->nitems[c]) continue;
-    const ClassLaunch l{b->strategy, b->nblocks, b->nitems[c], b->nseg[c]};
+    const ClassLaunch l{b->strategy, b->nblocks, b->nitems[c], b->nseg[c], b->cells_maxr};
     const hcg_status st = launch_class(c, b->qw, b->wide[c], b->d_fields,
                                        b->d_segs + (size_t)c * nf,
                                        b->d_ctl + (size_t)c * kBatchCtl, l, stream);
@@ -510,6 +548,7 @@ extern "C" hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields,
     return fail(st, "hcg_plan_batch: %s", msg.c_str());
   }
   b->nblocks = 2 * cus;  // two 256-thread workgroups per CU
+  for (hcg_plan_t pl : b->plans) b->cells_maxr = std::max(b->cells_maxr, pl->maxr);
   if (hipMalloc(&b->d_fields, sizeof(GatherArgs) * nfields) != hipSuccess ||
       hipMalloc(&b->d_segs, sizeof(BatchSeg) * nfields * kClasses) != hipSuccess ||
       hipMalloc(&b->d_ctl, sizeof(uint32_t) * kBatchCtl * kClasses) != hipSuccess ||

@@ -980,22 +980,35 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   }
 }
 
-// LDS of the few-channel gather in a batch (one wave per workgroup): small,
-// so that many tiles are in flight on a CU -- most tiles of a sparse field
-// hold a few candidates, and their time is the latency of the range, vector
-// and value loads.
-struct CellsSmem {
-  uint2 rng[kMaxRangesLimit];
-  uint32_t pre[kMaxRangesLimit + 1];
-  double4 xyz[kKB];
-  float spec[kKB][8];
+// LDS of the few-channel gather in a batch (one wave per workgroup), carved
+// from dynamic LDS of cells_batch_lds_bytes(maxr) bytes with maxr the largest
+// range count of the batch's plans: small, so that many tiles are in flight
+// on a CU -- most tiles of a sparse field hold a few candidates, and their
+// time is the latency of the range, vector and value loads.
+struct CellsLds {
+  double4* xyz;       // [kKB]
+  float (*spec)[8];   // [kKB][8]
+  uint2* rng;         // [maxr]
+  uint32_t* pre;      // [maxr + 1]
 };
+__host__ __device__ constexpr size_t cells_batch_lds_bytes(int maxr) {
+  return sizeof(double4) * kKB + sizeof(float) * kKB * 8 + sizeof(uint2) * (size_t)maxr +
+         sizeof(uint32_t) * ((size_t)maxr + 1);
+}
+__device__ inline CellsLds cells_lds(unsigned char* base, int maxr) {
+  CellsLds L;
+  L.xyz = (double4*)base;
+  L.spec = (float (*)[8])(L.xyz + kKB);
+  L.rng = (uint2*)(L.spec + kKB);
+  L.pre = (uint32_t*)(L.rng + maxr);
+  return L;
+}
 
 // Few channels (C <= kCM <= 8) for a 64-thread workgroup: one lane per cell
 // of the 8 x 8 tile, candidates staged 64 at a time, weights and sums in
 // FP64 (the per-plan k_gather_cells without the split of the candidates).
 template <int kCM>
-__device__ inline void gather_cells_tile_wave(const GatherArgs& a, int tile, CellsSmem& sm) {
+__device__ inline void gather_cells_tile_wave(const GatherArgs& a, int tile, const CellsLds& sm) {
   const int lane = threadIdx.x;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const GridGeom& g = a.g;
@@ -1042,7 +1055,7 @@ __device__ inline void gather_cells_tile_wave(const GatherArgs& a, int tile, Cel
 }
 
 // The few-channel gather of one tile, by channel count.
-__device__ inline void gather_cells_tile(const GatherArgs& a, int tile, CellsSmem& sm) {
+__device__ inline void gather_cells_tile(const GatherArgs& a, int tile, const CellsLds& sm) {
   if (a.C == 1) gather_cells_tile_wave<1>(a, tile, sm);
   else gather_cells_tile_wave<8>(a, tile, sm);
 }
