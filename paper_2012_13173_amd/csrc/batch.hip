@@ -56,8 +56,8 @@ __global__ void k_batch_reset(uint32_t* __restrict__ ctl) {
 
 // The next item of a persistent workgroup: thread 0 pops one from its
 // XCD's segment, then from the others once it is empty (*k counts the
-// segments it has left); 0xFFFFFFFF when every segment is empty.  Called by
-// every thread of the workgroup.
+// segments it has found empty); 0xFFFFFFFF when every segment is empty.
+// Called by every thread of the workgroup.
 __device__ inline uint32_t batch_next_item(uint32_t* __restrict__ ctl, uint32_t total, int home,
                                            int* k, uint32_t* s_item) {
   if (threadIdx.x == 0) {
@@ -89,9 +89,11 @@ __device__ inline BatchSeg batch_seg_of(const BatchSeg* __restrict__ segs, uint3
 
 // The few-channel class (FP32, C <= 8): one wave per tile, on dynamic LDS of
 // cells_batch_lds_bytes(maxr) with maxr the largest range count of the
-// batch's plans, in kernels of their own (64 threads, so that the registers
-// of the matrix-core classes' bounds do not apply): many tiles in flight on
-// a CU.  Items are tiles; one workgroup per item ...
+// batch's plans, in kernels of their own (bounded at 64 threads, not by the
+// matrix-core classes' 256-thread, two-per-CU bounds, so that they keep few
+// registers): many tiles in flight on a CU.  Items are tiles.
+//
+// One workgroup per item:
 __global__ void __launch_bounds__(64) k_cells_items(const GatherArgs* __restrict__ fields,
                                                     const BatchSeg* __restrict__ segs,
                                                     uint32_t nseg, int maxr) {
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(64) k_cells_items(const GatherArgs* __restrict
   gather_cells_tile(fields[sg.field], (int)(it - sg.base), cells_lds(s_dyn, maxr));
 }
 
-// ... or persistent workgroups popping items (sixteen per CU).
+// Persistent workgroups (sixteen per CU) popping items:
 __global__ void __launch_bounds__(64) k_cells_batch(const GatherArgs* __restrict__ fields,
                                                     const BatchSeg* __restrict__ segs,
                                                     uint32_t* __restrict__ ctl, int maxr) {
