@@ -421,7 +421,11 @@ hcg_status hcg_grid_rowthreads(hcg_plan_t plan, const float* spectra, int gamma,
                                float* map, float* weights, void* hip_stream);
 
 /* hcg_destroy -- wait for the device, then free the plan.  NULL is a no-op
- * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE. */
+ * (HCG_OK); a handle that is not a live plan gives HCG_E_STATE.  A plan's
+ * arrays, and the scratch of hcg_plan and hcg_grid, come from a stream-ordered
+ * memory pool of the library's own (one per device, alive until the process
+ * ends); freed memory up to 2 GiB per device stays in it for the next plan
+ * instead of going back to the driver. */
 hcg_status hcg_destroy(hcg_plan_t plan);
 
 /* Message for the last non-OK status returned to the calling thread. */

@@ -77,7 +77,10 @@ extern "C" hcg_status hcg_destroy(hcg_plan_t plan) {
   if (cur != plan->device) (void)hipSetDevice(plan->device);
   // (a plan of a batch has no arena of its own: the batch frees the shared one)
   hipError_t e1 = plan->arena ? hipDeviceSynchronize() : hipSuccess;
-  hipError_t e2 = plan->arena ? hipFree(plan->arena) : hipSuccess;
+  // (a pooled arena goes back to the library's pool, kept there for the next plan)
+  hipError_t e2 = !plan->arena        ? hipSuccess
+                  : plan->arena_pooled ? hipFreeAsync(plan->arena, nullptr)
+                                       : hipFree(plan->arena);
   if (cur != plan->device && cur >= 0) (void)hipSetDevice(cur);
   plan->magic = 0;
   delete plan;

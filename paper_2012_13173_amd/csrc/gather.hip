@@ -253,7 +253,9 @@ static hcg_status launch_cells(const hcg_plan_s* p, const float* spec, int C, fl
   bool owned = false;
   if (nsplit > 1 && !part) {
     const size_t bytes = cells_part_bytes(nsplit, cm, mask, ntiles);
-    if (hipMallocAsync((void**)&part, bytes, stream) != hipSuccess) {
+    hipMemPool_t pool = plan_pool();
+    if ((pool ? hipMallocFromPoolAsync((void**)&part, bytes, pool, stream)
+              : hipMallocAsync((void**)&part, bytes, stream)) != hipSuccess) {
       (void)hipGetLastError();  // no room for the partial sums: one workgroup per tile
       part = nullptr;
       nsplit = 1;

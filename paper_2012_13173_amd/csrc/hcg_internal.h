@@ -179,6 +179,7 @@ struct hcg_plan_s {
   uint64_t magic;
   int device;
   int batch_owned;  // a plan of a batch: freed with the batch only
+  int arena_pooled;  // the arena came from the library's pool (freed stream-ordered)
   int64_t n;
   int32_t nside;
   uint32_t pix_base, pix_max;
@@ -257,6 +258,12 @@ static_assert(offsetof(GatherArgs, kern) == 8 && offsetof(GatherArgs, wcube) == 
 // (one per field) and BatchSeg, and a control block of kBatchCtl words.
 // Largest squared support chord of the narrow-support gather kernels.
 constexpr double kNarrowChord2 = 1e-4;
+
+// The library's stream-ordered memory pool on the current device (NULL if
+// it cannot be created): plan arenas and per-call scratch, kept for reuse
+// up to a release threshold instead of being handed back to the driver
+// at every synchronisation.  Lives until the process ends.
+hipMemPool_t plan_pool();
 
 struct BatchSeg {
   uint32_t base, ntiles, slabs, field;

@@ -796,6 +796,40 @@ static int bit_length(uint32_t v) {
   return b;
 }
 
+// Freed memory the pool keeps for reuse (a plan of the 20M-sample cube
+// takes about 1.2 GB of arena and scratch).
+constexpr uint64_t kPoolKeepBytes = 2ull << 30;
+constexpr int kMaxDevices = 64;
+
+hipMemPool_t plan_pool() {
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  static bool tried[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!tried[dev]) {
+    tried[dev] = true;
+    hipMemPoolProps props = {};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+      uint64_t keep = kPoolKeepBytes;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      pools[dev] = pool;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  return pools[dev];
+}
+
 // Owns a device allocation until released.  Scratch that lives only for
 // one call is stream-ordered (alloc_async): hipFree would synchronise the
 // whole device, which serialises plans built on several streams at once.
@@ -810,7 +844,9 @@ struct DevBuf {
   }
   void* release() { void* q = p; p = nullptr; return q; }
   hipError_t alloc_async(size_t bytes, hipStream_t stream) {
-    const hipError_t e = hipMallocAsync(&p, bytes, stream);
+    hipMemPool_t pool = plan_pool();
+    const hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, stream)
+                              : hipMallocAsync(&p, bytes, stream);
     if (e != hipSuccess) {
       p = nullptr;
       return e;
@@ -1078,9 +1114,8 @@ struct PlanBuilder {
     const size_t o_flags = take(16);
     const size_t o_cells = take(sizeof(double4) * ncell);
     const size_t arena_bytes = off;
-    if (hipMalloc(&arena.p, arena_bytes) != hipSuccess) {
+    if (arena.alloc_async(arena_bytes, stream) != hipSuccess) {
       (void)hipGetLastError();
-      arena.p = nullptr;
       return fail(HCG_E_NOMEM, "%s: cannot allocate %zu bytes for the plan", who, arena_bytes);
     }
     const size_t temp_bytes = radix_sort_temp_bytes(n) + align256(sizeof(uint32_t) * n);
@@ -1162,6 +1197,7 @@ struct PlanBuilder {
   // after the flags have reached host[8..11]
   hcg_status finish(hcg_plan_t* out) {
     if (host[8]) return fail(HCG_E_DEVICE, "%s: candidate-range slots overflowed (internal bound)", who);
+    p->arena_pooled = arena.async ? 1 : 0;
     p->arena = arena.release();
     plan_register(p);
     *out = p;
@@ -1174,7 +1210,20 @@ hcg_status plan_build(hcg_plan_t* out, const double* lon_deg, const double* lat_
                       const PlanTarget& tg, const hcg_kernel* kernel, double support_deg,
                       const hcg_opts* opts, void* hip_stream, const char* who) {
   hipStream_t stream = (hipStream_t)hip_stream;
-  uint32_t host[16] = {0};
+  // the two reads between the steps land in page-locked memory (a copy to
+  // pageable memory is staged by the runtime: about 0.1-0.2 ms each)
+  thread_local uint32_t* pinned = nullptr;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (hipHostMalloc((void**)&pinned, sizeof(uint32_t) * 16, hipHostMallocPortable) != hipSuccess) {
+      (void)hipGetLastError();
+      pinned = nullptr;
+    }
+  }
+  uint32_t stack_words[16] = {0};
+  uint32_t* host = pinned ? pinned : stack_words;
+  memset(host, 0, sizeof(uint32_t) * 16);
   PlanBuilder b;
   hcg_status st = b.begin(lon_deg, lat_deg, n, tg, kernel, support_deg, opts, stream, host, who);
   if (st != HCG_OK) return st;
