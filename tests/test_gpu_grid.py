@@ -112,6 +112,39 @@ def test_plan_reuse_and_stream():
     plan.destroy()
 
 
+def test_repeated_plans_reuse_memory_and_agree():
+    # plans and their scratch come from the library's pool: forty plan +
+    # grid + destroy cycles (the second half on another stream, the
+    # few-channel gather's partial sums included) leave the device's free
+    # memory where the first cycle left it, up to the pool's retained bytes,
+    # and every cycle gives the same map bit for bit
+    dev = torch.device("cuda:0")
+    w = synth.small_cube(n=400_000, nchan=3, nx=60, ny=50, seed=77)
+    lon, lat, spec = w.lon.to(dev), w.lat.to(dev), w.spectra.to(dev).contiguous()
+    s2 = torch.cuda.Stream()
+    first, free_after_first = None, None
+    for i in range(40):
+        st = None if i < 20 else s2
+        with torch.cuda.stream(st if st is not None else torch.cuda.current_stream()):
+            plan = hcg.hcg_plan(lon, lat, w.grid, w.fwhm_deg, w.support_deg, nside=w.nside,
+                                stream=st)
+            cube = torch.empty((3, 50, 60), dtype=torch.float32, device=dev)
+            hcg.hcg_grid(plan, spec, cube, None, stream=st)
+            torch.cuda.synchronize()
+            plan.destroy()
+        if first is None:
+            first = cube.cpu().numpy()
+            free_after_first = torch.cuda.mem_get_info()[0]
+        else:
+            assert np.array_equal(cube.cpu().numpy(), first, equal_nan=True), i
+        del cube
+    torch.cuda.synchronize()
+    drop = free_after_first - torch.cuda.mem_get_info()[0]
+    print(f"free device memory after 40 cycles: {drop / 2**20:.1f} MiB less than after the first",
+          flush=True)
+    assert drop <= (2 << 30) + (64 << 20)
+
+
 def test_grid_argument_errors():
     w = synth.small_cube(n=2000, nchan=4, nx=8, ny=8)
     dev = torch.device("cuda:0")
