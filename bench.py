@@ -320,7 +320,8 @@ def run_host_stream(w, slabs, samp, pageable_slab=256):
     copy (the bound of the stream).  Page-locked: the first channels that fit
     20 GB of spectra (torch rounds page-locked blocks up to a power of two, and
     the page-locked total is limited), once per slab width; pageable: the
-    whole cube, once."""
+    whole cube, once; spectra stored as FP16 x per-channel scale (half the
+    host bytes), page-locked, the same channels, once per slab width."""
     g = w.grid
     dev = w.spectra.device
     nch = int(min(w.nchan, max(16, 20e9 // (4 * w.n) // 16 * 16)))
@@ -347,16 +348,16 @@ def run_host_stream(w, slabs, samp, pageable_slab=256):
         samp_h = dict(samp, V=samp["V"][:, :nch])
     plan = hcg.hcg_plan(w.lon, w.lat, g, w.fwhm_deg, w.support_deg, nside=w.nside)
 
-    def timed(spec, cube, W, cs, reps):
-        hcg.hcg_grid_host(plan, spec, cube, W, slab=cs)
+    def timed(spec, cube, W, cs, reps, dtype=hcg.HCG_F32, scale=None):
+        hcg.hcg_grid_host(plan, spec, cube, W, slab=cs, dtype=dtype, chan_scale=scale)
         ts = []
         for _ in range(reps):
             t0 = time.perf_counter()
-            hcg.hcg_grid_host(plan, spec, cube, W, slab=cs)
+            hcg.hcg_grid_host(plan, spec, cube, W, slab=cs, dtype=dtype, chan_scale=scale)
             ts.append(time.perf_counter() - t0)
         ms = 1e3 * float(np.mean(ts))
-        C = spec.shape[1]
-        h2d = 4.0 * w.n * C
+        C = spec.shape[-1]
+        h2d = float(spec.element_size() * spec.numel())
         return {"nchan": C, "slab": cs, "ms": ms, "updates_per_s": w.n * C / (ms * 1e-3),
                 "h2d_bytes": h2d, "d2h_bytes": 4.0 * C * g.ncells,
                 "h2d_GBps": h2d / (ms * 1e-3) / 1e9,
@@ -370,7 +371,24 @@ def run_host_stream(w, slabs, samp, pageable_slab=256):
         out["page_locked"].append(rec)
         log(f"host stream, page-locked, slabs of {cs}: {rec['ms']:.1f} ms per {nch}-channel "
             f"cube, host-to-device {rec['h2d_GBps']:.1f} GB/s (plain copy {copy_gbs:.1f} GB/s)")
-    del spec_h, cube_h
+    del spec_h
+    # the same channels stored as FP16 x scale (encoded on the device, copied
+    # to page-locked memory outside the timed calls)
+    enc, scale = hcg.hcg_quantize(w.spectra[:, :nch].contiguous(), hcg.HCG_F16_SCALED)
+    enc_h = torch.empty(tuple(enc.shape), dtype=enc.dtype, pin_memory=True)
+    enc_h.copy_(enc)
+    scale_h = scale.cpu()
+    del enc, scale
+    torch.cuda.empty_cache()
+    out["page_locked_f16_scaled"] = []
+    for cs in slabs:
+        rec = timed(enc_h, cube_h, W_h, cs, 2, hcg.HCG_F16_SCALED, scale_h)
+        if samp_h is not None:
+            rec["rel_l2_max_over_channels"] = float(sampled_errors(cube_h, samp_h).max())
+        out["page_locked_f16_scaled"].append(rec)
+        log(f"host stream, page-locked FP16 x scale, slabs of {cs}: {rec['ms']:.1f} ms per "
+            f"{nch}-channel cube, host-to-device {rec['h2d_GBps']:.1f} GB/s")
+    del enc_h, cube_h
     if pageable_slab:
         t0 = time.perf_counter()
         spec_p = w.spectra.cpu()

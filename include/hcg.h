@@ -366,36 +366,48 @@ hcg_status hcg_grid_packed(hcg_plan_t plan, const void* packed, int64_t nchan, h
                            void* hip_stream);
 
 /*
- * hcg_grid_host -- hcg_grid (FP32 form) for spectra and a cube held in host
- * memory, streamed through the device in channel slabs: the overlap of
- * host-device copies with the gridding on separate streams that Section 5
- * names as future work, so that a cube larger than device memory can be
- * made with one plan.
+ * hcg_grid_host -- hcg_grid for spectra and a cube held in host memory,
+ * streamed through the device in channel slabs: the overlap of host-device
+ * copies with the gridding on separate streams that Section 5 names as
+ * future work, so that a cube larger than device memory can be made with one
+ * plan.  Every storage form of hcg_grid can be streamed; the 16- and 8-bit
+ * forms move half or a quarter of the FP32 bytes over the host link.
  *
- *   spectra_host  host float [n][nchan] in the sample order given to
- *                 hcg_plan, channel-fastest.
+ *   spectra_host  host memory in the sample order given to hcg_plan,
+ *                 channel-fastest, in the storage of dtype as hcg_grid takes
+ *                 it: [n][nchan] elements of the form, or [2][n][nchan] (the
+ *                 high plane, then the low plane) for the split forms.
  *   nchan         >= 1.
+ *   dtype         any hcg_dtype.
+ *   chan_scale    host float [nchan] for the scaled forms (the scales the
+ *                 encoding used, as hcg_quantize writes them); NULL for the
+ *                 others.
  *   slab_chan     channels per slab; 0 picks 512 (fewer if one slab of
- *                 spectra or of the cube would exceed 4 GiB).  The last slab
- *                 may be shorter.
+ *                 spectra, all planes, or of the cube would exceed 4 GiB).
+ *                 The last slab may be shorter.
  *   cube_host     host float [nchan][ny][nx]: V as hcg_grid writes it.
  *   weights_host  host float [ny][nx] or NULL: W as hcg_grid writes it.
  *
  * Slab s + 1 is copied in on a stream of the library's while slab s is
  * gridded on hip_stream and slab s - 1 is copied out on a third stream, each
- * through two device buffers of slab_chan channels (2 slab_chan (n + nx ny)
- * floats of device memory, plus nx ny for W, allocated per call and freed on
- * return).  The copies overlap the gridding only for page-locked host memory
- * (hipHostMalloc); pageable memory gives the same result, slower.
- * Synchronous: returns after the last slab has reached cube_host (the work
- * queued earlier on hip_stream runs first).  Errors: HCG_E_ARG (NULL pointer,
- * nchan < 1, slab_chan < 0), HCG_E_STATE (not a live plan), HCG_E_NOMEM (the
- * slab buffers do not fit), HCG_E_DEVICE (a copy or launch failed; the
- * streams are drained before the call returns).
+ * through two device buffers of slab_chan channels (2 slab_chan (b n + 4 nx
+ * ny) bytes of device memory, b the bytes per sample and channel of the
+ * form, all planes, plus 4 nx ny for W and 4 nchan for the scales, allocated
+ * per call and freed on return).  Each slab is gridded by hcg_grid on the
+ * slab's channels (and their scales), so the cube equals, bit for bit, what
+ * hcg_grid gives for those channels on the device.  The copies overlap the
+ * gridding only for page-locked host memory (hipHostMalloc); pageable memory
+ * gives the same result, slower.  Synchronous: returns after the last slab
+ * has reached cube_host (the work queued earlier on hip_stream runs first).
+ * Errors: HCG_E_ARG (NULL pointer, nchan < 1, slab_chan < 0, a device
+ * pointer given for host memory, chan_scale missing for a scaled dtype or
+ * given for another), HCG_E_UNSUPPORTED (unknown dtype), HCG_E_STATE (not a
+ * live plan), HCG_E_NOMEM (the slab buffers do not fit), HCG_E_DEVICE (a
+ * copy or launch failed; the streams are drained before the call returns).
  */
-hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
-                         int64_t slab_chan, float* cube_host, float* weights_host,
-                         void* hip_stream);
+hcg_status hcg_grid_host(hcg_plan_t plan, const void* spectra_host, int64_t nchan,
+                         hcg_dtype dtype, const float* chan_scale, int64_t slab_chan,
+                         float* cube_host, float* weights_host, void* hip_stream);
 
 /*
  * hcg_grid_rowthreads -- the paper's GPU gather scheme on one channel, the

@@ -147,7 +147,7 @@ def load(path: str = LIB_PATH):
     lib.hcg_quantize_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp]
     lib.hcg_grid_packed.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp, vp]
     lib.hcg_packed_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(i64)]
-    lib.hcg_grid_host.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    lib.hcg_grid_host.argtypes = [vp, vp, i64, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.hcg_grid_rowthreads.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.hcg_plan_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(FieldDescC),
                                    ctypes.POINTER(OptsC), vp]
@@ -385,25 +385,27 @@ def _grid_call(name, plan, spectra, cube, weights, dtype, chan_scale, stream):
     _check(st, name)
 
 
-def _hptr(t, name):
+def _hptr(t, name, dtype=torch.float32):
     if t is None:
         return None
     if not isinstance(t, torch.Tensor) or t.device.type != "cpu":
         raise TypeError(f"{name} must be a CPU tensor")
-    if t.dtype != torch.float32 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous float32 tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
 def hcg_grid_host(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights=None,
-                  slab: int = 0, stream=None) -> None:
-    """Grids host spectra [n, C] into the host cube [C, ny, nx] (and weights
-    [ny, nx]) in channel slabs streamed through the device (FP32 form).
-    Synchronous.  Page-locked tensors (``pin_memory()``) let the copies
-    overlap the gridding."""
-    if spectra.dim() != 2:
-        raise ValueError("spectra must be [n, nchan]")
-    n, C = (int(x) for x in spectra.shape)
+                  slab: int = 0, dtype: int = HCG_F32, chan_scale=None, stream=None) -> None:
+    """Grids host spectra ([n, C], or [2, n, C] for the split forms, in the
+    storage of ``dtype``) into the host cube [C, ny, nx] (and weights
+    [ny, nx]) in channel slabs streamed through the device; ``chan_scale`` is
+    a host float32 [C] for the scaled forms.  Synchronous.  Page-locked
+    tensors (``pin_memory()``) let the copies overlap the gridding."""
+    sdt, prefix = _FORM_STORAGE[dtype]
+    if spectra.dim() != 2 + len(prefix) or tuple(spectra.shape[:len(prefix)]) != prefix:
+        raise ValueError(f"spectra must be [{', '.join(map(str, prefix + ('n', 'nchan')))}]")
+    n, C = int(spectra.shape[-2]), int(spectra.shape[-1])
     if n != plan.n:
         raise ValueError(f"spectra has {n} rows, the plan {plan.n} samples")
     g = plan.grid
@@ -411,8 +413,11 @@ def hcg_grid_host(plan: Plan, spectra: torch.Tensor, cube: torch.Tensor, weights
         raise ValueError(f"cube must be [{C}, {g.ny}, {g.nx}]")
     if weights is not None and tuple(weights.shape) != (g.ny, g.nx):
         raise ValueError(f"weights must be [{g.ny}, {g.nx}]")
-    st = load().hcg_grid_host(plan.handle, _hptr(spectra, "spectra"), C, int(slab),
-                              _hptr(cube, "cube"), _hptr(weights, "weights"), _stream(stream))
+    if chan_scale is not None and tuple(chan_scale.shape) != (C,):
+        raise ValueError(f"chan_scale must be [{C}]")
+    st = load().hcg_grid_host(plan.handle, _hptr(spectra, "spectra", sdt), C, int(dtype),
+                              _hptr(chan_scale, "chan_scale"), int(slab), _hptr(cube, "cube"),
+                              _hptr(weights, "weights"), _stream(stream))
     _check(st, "hcg_grid_host")
 
 

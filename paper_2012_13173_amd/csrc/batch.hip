@@ -25,6 +25,7 @@
 #include <string>
 #include <vector>
 
+#include "forms.h"
 #include "gather_tile.h"
 
 namespace hcg {
@@ -258,15 +259,6 @@ hcg_status launch_class(int cls, int qw, bool wide, const GatherArgs* fields,
   HCG_LAUNCH_CHECK("k_gather_batch");
   return HCG_OK;
 }
-
-// Element size and planes of each storage form (input sample order).
-size_t form_elem(int dtype) {
-  return dtype == HCG_F32 ? 4 : (dtype == HCG_FP8E4M3_SCALED || dtype == HCG_FP8E4M3_SPLIT) ? 1 : 2;
-}
-bool form_scaled(int dtype) {
-  return dtype == HCG_F16_SCALED || dtype == HCG_FP8E4M3_SCALED || dtype == HCG_FP8E4M3_SPLIT;
-}
-bool form_split(int dtype) { return dtype == HCG_BF16_SPLIT || dtype == HCG_FP8E4M3_SPLIT; }
 
 // Kernel class of a field's data (vec: rows read four elements at a time).
 int field_class(const hcg_field_data& d, bool vec) {

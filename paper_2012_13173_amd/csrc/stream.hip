@@ -9,9 +9,11 @@
 //   in[s]   waits until the gather of slab s - 2 has read its buffer;
 //   grid[s] waits for in[s] and for the copy-out of slab s - 2;
 //   out[s]  waits for grid[s].
-// A slab of spectra is a strided host region (n rows of slab channels, row
-// pitch nchan floats) that becomes a dense [n][slab] device buffer, which is
-// what hcg_grid takes.
+// A slab of spectra is a strided host region per storage plane (n rows of
+// slab channels, row pitch nchan elements) that becomes a dense
+// [planes][n][slab] device buffer, which is what hcg_grid takes; every form
+// of hcg_grid streams this way, so spectra stored in a 16- or 8-bit form
+// cross the host link in half or a quarter of the FP32 bytes.
 //
 // Page-locked host memory is copied by the DMA engines directly (one 2-D copy
 // per slab in, one copy per slab out).  Pageable memory goes through rings
@@ -31,6 +33,7 @@
 #include <thread>
 #include <vector>
 
+#include "forms.h"
 #include "hcg_internal.h"
 
 using namespace hcg;
@@ -141,6 +144,7 @@ struct StreamRes {
   void* dspec[2] = {};
   void* dcube[2] = {};
   float* dw = nullptr;
+  float* dscale = nullptr;
   Ring rin, rout;
   ~StreamRes() {
     // no copy or gather may still use the buffers when they go (an error
@@ -161,6 +165,7 @@ struct StreamRes {
       if (dcube[b]) (void)hipFree(dcube[b]);
     }
     if (dw) (void)hipFree(dw);
+    if (dscale) (void)hipFree(dscale);
     if (s_in) (void)hipStreamDestroy(s_in);
     if (s_out) (void)hipStreamDestroy(s_out);
   }
@@ -230,24 +235,34 @@ constexpr size_t kChunkBytes = size_t(64) << 20;
 
 }  // namespace
 
-static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
-                            int64_t slab_chan, float* cube_host, float* weights_host,
-                            void* hip_stream) {
+static hcg_status grid_host(hcg_plan_t plan, const void* spectra_host, int64_t nchan,
+                            hcg_dtype dtype, const float* chan_scale, int64_t slab_chan,
+                            float* cube_host, float* weights_host, void* hip_stream) {
   if (!plan) return fail(HCG_E_ARG, "hcg_grid_host: plan is NULL");
   if (!plan_is_live(plan)) return fail(HCG_E_STATE, "hcg_grid_host: not a live plan");
   if (!spectra_host || !cube_host) return fail(HCG_E_ARG, "hcg_grid_host: NULL pointer");
   if (nchan < 1) return fail(HCG_E_ARG, "hcg_grid_host: nchan must be >= 1");
   if (slab_chan < 0) return fail(HCG_E_ARG, "hcg_grid_host: slab_chan must be >= 0");
+  if ((int)dtype < HCG_F32 || (int)dtype > HCG_FP8E4M3_SPLIT)
+    return fail(HCG_E_UNSUPPORTED, "hcg_grid_host: unknown dtype %d", (int)dtype);
+  const bool scaled = form_scaled(dtype);
+  if (scaled && !chan_scale)
+    return fail(HCG_E_ARG, "hcg_grid_host: chan_scale is required for this dtype");
+  if (!scaled && chan_scale)
+    return fail(HCG_E_ARG, "hcg_grid_host: chan_scale must be NULL for this dtype");
   if (device_memory(spectra_host) || device_memory(cube_host) ||
-      (weights_host && device_memory(weights_host)))
+      (weights_host && device_memory(weights_host)) || (chan_scale && device_memory(chan_scale)))
     return fail(HCG_E_ARG, "hcg_grid_host: a device pointer was given for host memory");
   const hcg_plan_s* p = plan;
   const int64_t n = p->n;
   const int64_t G = (int64_t)p->grid.nx * p->grid.ny;
-  // default slab: 512 channels, or fewer so that one spectra buffer stays
-  // within 4 GiB
+  const size_t esz = form_elem(dtype);
+  const int planes = form_split(dtype) ? 2 : 1;
+  // default slab: 512 channels, or fewer so that one spectra buffer (all its
+  // planes) or one cube slab stays within 4 GiB
   int64_t cs = slab_chan ? slab_chan : 512;
-  const int64_t cap = std::max<int64_t>(1, ((int64_t)4 << 30) / (4 * std::max<int64_t>(n, G)));
+  const int64_t cap = std::max<int64_t>(
+      1, ((int64_t)4 << 30) / std::max<int64_t>((int64_t)esz * planes * n, 4 * G));
   if (!slab_chan) cs = std::min(cs, cap);
   cs = std::min(cs, nchan);
   const int64_t nslab = (nchan + cs - 1) / cs;
@@ -264,7 +279,7 @@ static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t 
     HCG_HIP(hipEventCreateWithFlags(&r.ev_in[b], hipEventDisableTiming));
     HCG_HIP(hipEventCreateWithFlags(&r.ev_grid[b], hipEventDisableTiming));
     HCG_HIP(hipEventCreateWithFlags(&r.ev_out[b], hipEventDisableTiming));
-    if (hipMalloc(&r.dspec[b], sizeof(float) * n * cs) != hipSuccess ||
+    if (hipMalloc(&r.dspec[b], esz * planes * n * cs) != hipSuccess ||
         hipMalloc(&r.dcube[b], sizeof(float) * G * cs) != hipSuccess) {
       (void)hipGetLastError();
       return fail(HCG_E_NOMEM, "hcg_grid_host: cannot allocate two slabs of %lld channels",
@@ -275,8 +290,12 @@ static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t 
     (void)hipGetLastError();
     return fail(HCG_E_NOMEM, "hcg_grid_host: cannot allocate the weight map");
   }
-  // rows per copy-in chunk (at least one row of a slab)
-  const size_t row_bytes = sizeof(float) * (size_t)cs;
+  if (scaled && hipMalloc((void**)&r.dscale, sizeof(float) * nchan) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HCG_E_NOMEM, "hcg_grid_host: cannot allocate the channel scales");
+  }
+  // rows per copy-in chunk (at least one row of a slab, of one plane)
+  const size_t row_bytes = esz * (size_t)cs;
   const int64_t chunk_rows = (int64_t)std::max<size_t>(1, kChunkBytes / row_bytes);
   hcg_status st = HCG_OK;
   if (!in_direct) st = ring_init(r.rin, 4, (size_t)chunk_rows * row_bytes);
@@ -287,37 +306,48 @@ static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t 
   // the caller's earlier work on its stream comes first
   HCG_HIP(hipEventRecord(r.ev_grid[1], s_grid));
   HCG_HIP(hipStreamWaitEvent(r.s_in, r.ev_grid[1], 0));
+  // all the scales go in once, ahead of the first slab (its event orders
+  // them before every gather)
+  if (scaled)
+    HCG_HIP(hipMemcpyAsync(r.dscale, chan_scale, sizeof(float) * nchan, hipMemcpyHostToDevice,
+                           r.s_in));
 
   auto copy_in = [&](int64_t s) -> hcg_status {
     const int b = (int)(s & 1);
     const int64_t c0 = s * cs, cn = std::min(cs, nchan - c0);
     // the buffer was last read by the gather of slab s - 2
     if (s >= 2) HCG_HIP(hipStreamWaitEvent(r.s_in, r.ev_grid[b], 0));
-    if (in_direct) {
-      HCG_HIP(hipMemcpy2DAsync(r.dspec[b], sizeof(float) * cn, spectra_host + c0,
-                               sizeof(float) * nchan, sizeof(float) * cn, n,
-                               hipMemcpyHostToDevice, r.s_in));
-    } else {
-      const int64_t rows = std::max<int64_t>(1, (int64_t)(r.rin.bytes / (sizeof(float) * cn)));
+    // plane pl of the slab: n rows of cn elements at row pitch nchan, into
+    // the dense [n][cn] plane pl of the device buffer
+    const size_t pitch = esz * (size_t)nchan, width = esz * (size_t)cn;
+    for (int pl = 0; pl < planes; ++pl) {
+      const char* src = (const char*)spectra_host + esz * ((size_t)pl * n * nchan + c0);
+      char* dst = (char*)r.dspec[b] + (size_t)pl * n * width;
+      if (in_direct) {
+        HCG_HIP(hipMemcpy2DAsync(dst, width, src, pitch, width, n, hipMemcpyHostToDevice,
+                                 r.s_in));
+        continue;
+      }
+      const int64_t rows = std::max<int64_t>(1, (int64_t)(r.rin.bytes / width));
       for (int64_t r0 = 0; r0 < n; r0 += rows) {
         const int64_t nr = std::min(rows, n - r0);
         int i;
         hcg_status e = ring_acquire(r.rin, pool, &i);
         if (e != HCG_OK) return e;
-        float* stage = (float*)r.rin.buf[i];
+        char* stage = (char*)r.rin.buf[i];
         if (cn == nchan) {
-          const char* src = (const char*)(spectra_host + r0 * nchan);
-          pool.run(nr * cn * (int64_t)sizeof(float), [&](int64_t lo, int64_t hi) {
-            memcpy((char*)stage + lo, src + lo, hi - lo);
+          const char* from = src + r0 * pitch;
+          pool.run(nr * (int64_t)width, [&](int64_t lo, int64_t hi) {
+            memcpy(stage + lo, from + lo, hi - lo);
           });
         } else {
           pool.run(nr, [&](int64_t lo, int64_t hi) {
             for (int64_t q = lo; q < hi; ++q)
-              memcpy(stage + q * cn, spectra_host + (r0 + q) * nchan + c0, sizeof(float) * cn);
+              memcpy(stage + q * width, src + (r0 + q) * pitch, width);
           });
         }
-        HCG_HIP(hipMemcpyAsync((float*)r.dspec[b] + r0 * cn, stage, sizeof(float) * nr * cn,
-                               hipMemcpyHostToDevice, r.s_in));
+        HCG_HIP(hipMemcpyAsync(dst + r0 * width, stage, nr * width, hipMemcpyHostToDevice,
+                               r.s_in));
         HCG_HIP(hipEventRecord(r.rin.ev[i], r.s_in));
         r.rin.busy[i] = true;
       }
@@ -369,8 +399,8 @@ static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t 
       if (st != HCG_OK) break;
       HCG_HIP(hipStreamWaitEvent(s_grid, r.ev_in[b], 0));
       if (s >= 2) HCG_HIP(hipStreamWaitEvent(s_grid, r.ev_out[b], 0));
-      st = hcg_grid(plan, r.dspec[b], cn, HCG_F32, nullptr, (float*)r.dcube[b],
-                    s == 0 ? r.dw : nullptr, s_grid);
+      st = hcg_grid(plan, r.dspec[b], cn, dtype, scaled ? r.dscale + s * cs : nullptr,
+                    (float*)r.dcube[b], s == 0 ? r.dw : nullptr, s_grid);
       if (st != HCG_OK) break;
       HCG_HIP(hipEventRecord(r.ev_grid[b], s_grid));
     }
@@ -391,11 +421,12 @@ static hcg_status grid_host(hcg_plan_t plan, const float* spectra_host, int64_t 
 // No C++ exception crosses the C ABI: thread creation and the pool's job
 // objects can throw; the streams are drained by the resources' destructors
 // before the status is returned.
-extern "C" hcg_status hcg_grid_host(hcg_plan_t plan, const float* spectra_host, int64_t nchan,
-                                    int64_t slab_chan, float* cube_host, float* weights_host,
-                                    void* hip_stream) {
+extern "C" hcg_status hcg_grid_host(hcg_plan_t plan, const void* spectra_host, int64_t nchan,
+                                    hcg_dtype dtype, const float* chan_scale, int64_t slab_chan,
+                                    float* cube_host, float* weights_host, void* hip_stream) {
   try {
-    return grid_host(plan, spectra_host, nchan, slab_chan, cube_host, weights_host, hip_stream);
+    return grid_host(plan, spectra_host, nchan, dtype, chan_scale, slab_chan, cube_host,
+                     weights_host, hip_stream);
   } catch (const std::bad_alloc&) {
     return fail(HCG_E_NOMEM, "hcg_grid_host: out of host memory");
   } catch (const std::exception& e) {

@@ -79,8 +79,9 @@ def test_argument_errors_before_device_work():
     assert lib.hcg_grid_rowthreads(None, vp(1), 1, 64, vp(1), None, None) == hcg.HCG_E_ARG
     assert lib.hcg_grid_rowthreads(vp(12345), vp(1), 1, 64, vp(1), None, None) == hcg.HCG_E_STATE
     # host streaming
-    assert lib.hcg_grid_host(None, vp(1), 4, 0, vp(1), None, None) == hcg.HCG_E_ARG
-    assert lib.hcg_grid_host(vp(12345), vp(1), 4, 0, vp(1), None, None) == hcg.HCG_E_STATE
+    assert lib.hcg_grid_host(None, vp(1), 4, hcg.HCG_F32, None, 0, vp(1), None, None) == hcg.HCG_E_ARG
+    assert lib.hcg_grid_host(vp(12345), vp(1), 4, hcg.HCG_F32, None, 0, vp(1), None,
+                             None) == hcg.HCG_E_STATE
     nbytes = ctypes.c_int64()
     assert lib.hcg_packed_bytes(None, 4, hcg.HCG_BF16, ctypes.byref(nbytes)) == hcg.HCG_E_ARG
     assert lib.hcg_packed_bytes(vp(12345), 4, hcg.HCG_BF16, ctypes.byref(nbytes)) == hcg.HCG_E_STATE

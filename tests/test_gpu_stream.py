@@ -6,7 +6,14 @@ Each streamed slab must equal, bit for bit, hcg_grid run on the device over
 the same channels (the same kernels on the same inputs), and the whole cube
 must agree with the FP64 oracle to the FP32 bound of 1e-5.  Cases: ragged last
 slab, one-channel slabs, a slab wider than the cube, pageable and page-locked
-host memory, W omitted, and a full-size sample count with sampled cells."""
+host memory, W omitted, and a full-size sample count with sampled cells.
+
+The low-precision storage forms stream the same way (one or two planes of
+16- or 8-bit elements, per-channel scales in host memory): each slab equals
+hcg_grid on the device over the same encoded channels and scales, and the cube
+meets the form's error budget against the oracle on the FP32 master spectra
+(the budgets of the precision tests: FP16 x scale 1e-3, BF16 hi+lo 5e-5, FP8
+hi+lo 1e-2, plain BF16 1e-2, FP8 x scale 1e-1)."""
 import numpy as np
 import pytest
 import torch
@@ -18,6 +25,9 @@ from tests.gridcheck import (assert_cube_close, assert_weights_close, gather_cel
 
 pytestmark = pytest.mark.gpu
 TOL_F32 = 1e-5
+DEV = torch.device("cuda:0")
+LP_FORMS = [(hcg.HCG_BF16, 1e-2), (hcg.HCG_BF16_SPLIT, 5e-5), (hcg.HCG_F16_SCALED, 1e-3),
+            (hcg.HCG_FP8E4M3_SCALED, 1e-1), (hcg.HCG_FP8E4M3_SPLIT, 1e-2)]
 
 
 def _plan(w):
@@ -44,6 +54,34 @@ def _device_slabs(plan, w, slab):
         spec = w.spectra[:, c0:c0 + cn].contiguous().to(dev)
         cube = torch.empty((cn, g.ny, g.nx), dtype=torch.float32, device=dev)
         hcg.hcg_grid(plan, spec, cube, W if c0 == 0 else None)
+        V[c0:c0 + cn] = cube.cpu().numpy()
+    torch.cuda.synchronize()
+    return V, W.cpu().numpy()
+
+
+def _encoded(w, form, pinned):
+    """The form's encoding of the spectra (hcg_quantize on the device), on the
+    device and as a host copy, with its scales."""
+    enc, scale = hcg.hcg_quantize(w.spectra.to(DEV).contiguous(), form)
+    torch.cuda.synchronize()
+    enc_h = enc.cpu()
+    if pinned:
+        enc_h = enc_h.pin_memory()
+    return enc, scale, enc_h, (scale.cpu() if scale is not None else None)
+
+
+def _device_slabs_form(plan, w, enc, scale, form, slab):
+    """hcg_grid on the device over each slab of encoded channels."""
+    C, g = w.nchan, w.grid
+    cs = slab if slab else C
+    V = np.empty((C, g.ny, g.nx), dtype=np.float32)
+    W = torch.empty((g.ny, g.nx), dtype=torch.float32, device=DEV)
+    for c0 in range(0, C, cs):
+        cn = min(cs, C - c0)
+        spec = enc[..., c0:c0 + cn].contiguous()
+        sc = scale[c0:c0 + cn].contiguous() if scale is not None else None
+        cube = torch.empty((cn, g.ny, g.nx), dtype=torch.float32, device=DEV)
+        hcg.hcg_grid(plan, spec, cube, W if c0 == 0 else None, dtype=form, chan_scale=sc)
         V[c0:c0 + cn] = cube.cpu().numpy()
     torch.cuda.synchronize()
     return V, W.cpu().numpy()
@@ -86,6 +124,28 @@ def test_streamed_equals_device_slabs(nchan, slab, pinned, pinned_out):
     assert_weights_close(W, Wr)
 
 
+@pytest.mark.parametrize("form,tol", LP_FORMS)
+@pytest.mark.parametrize("pinned,slab", [(True, 32), (False, 32), (False, 0)])
+def test_streamed_forms_equal_device_slabs(form, tol, pinned, slab):
+    # 70 channels in slabs of 32: two full slabs and a ragged one of 6 (rows
+    # read one element at a time); slab 0: one slab of whole rows
+    w = synth.small_cube(n=12_000, nchan=70, nx=29, ny=19)
+    plan = _plan(w)
+    g = w.grid
+    enc, scale, enc_h, scale_h = _encoded(w, form, pinned)
+    cube = _host((w.nchan, g.ny, g.nx), pinned)
+    W = _host((g.ny, g.nx), pinned)
+    hcg.hcg_grid_host(plan, enc_h, cube, W, slab=slab, dtype=form, chan_scale=scale_h)
+    Vd, Wd = _device_slabs_form(plan, w, enc, scale, form, slab if slab else 512)
+    plan.destroy()
+    V = cube.numpy()
+    assert np.array_equal(V, Vd, equal_nan=True), f"form {form}: streamed cube differs from hcg_grid"
+    assert np.array_equal(W.numpy(), Wd)
+    Vr, Wr, _ = run_oracle(w)
+    assert_cube_close(V, Vr, tol, f"form {form} slab={slab} pinned={pinned}")
+    assert_weights_close(W.numpy(), Wr)
+
+
 def test_streamed_without_weights_and_repeated():
     w = synth.small_cube(n=9000, nchan=50, nx=23, ny=31, lat_c=-60.0)
     plan = _plan(w)
@@ -126,6 +186,17 @@ def test_argument_errors():
         hcg.hcg_grid_host(plan, w.spectra, cube[:3].contiguous())
     with pytest.raises(hcg.HcgError):
         hcg.hcg_grid_host(plan, w.spectra, cube, slab=-1)
+    enc, scale, enc_h, scale_h = _encoded(w, hcg.HCG_F16_SCALED, False)
+    with pytest.raises(hcg.HcgError, match="chan_scale is required"):
+        hcg.hcg_grid_host(plan, enc_h, cube, dtype=hcg.HCG_F16_SCALED)
+    with pytest.raises(hcg.HcgError, match="chan_scale must be NULL"):
+        hcg.hcg_grid_host(plan, w.spectra, cube, chan_scale=scale_h)
+    with pytest.raises(TypeError):  # scales in device memory
+        hcg.hcg_grid_host(plan, enc_h, cube, dtype=hcg.HCG_F16_SCALED, chan_scale=scale)
+    with pytest.raises(TypeError):  # FP32 spectra given for a 16-bit form
+        hcg.hcg_grid_host(plan, w.spectra, cube, dtype=hcg.HCG_F16_SCALED, chan_scale=scale_h)
+    with pytest.raises(ValueError):  # one plane given for a split form
+        hcg.hcg_grid_host(plan, enc_h, cube, dtype=hcg.HCG_BF16_SPLIT)
     plan.destroy()
 
 
@@ -137,9 +208,20 @@ def test_device_pointer_refused():
     spec_d = w.spectra.cuda()
     cube = torch.empty((4, 8, 8), dtype=torch.float32)
     lib = hcg.load()
-    st = lib.hcg_grid_host(plan.handle, ctypes.c_void_p(spec_d.data_ptr()), 4, 0,
+    st = lib.hcg_grid_host(plan.handle, ctypes.c_void_p(spec_d.data_ptr()), 4, hcg.HCG_F32,
+                           None, 0, ctypes.c_void_p(cube.data_ptr()), None, None)
+    assert st == hcg.HCG_E_ARG and b"device pointer" in lib.hcg_last_error()
+    # the scales of a scaled form, given in device memory
+    enc_h = torch.zeros((2000, 4), dtype=torch.float16)
+    scale_d = torch.ones(4, dtype=torch.float32, device=DEV)
+    st = lib.hcg_grid_host(plan.handle, ctypes.c_void_p(enc_h.data_ptr()), 4,
+                           hcg.HCG_F16_SCALED, ctypes.c_void_p(scale_d.data_ptr()), 0,
                            ctypes.c_void_p(cube.data_ptr()), None, None)
     assert st == hcg.HCG_E_ARG and b"device pointer" in lib.hcg_last_error()
+    # an unknown form
+    st = lib.hcg_grid_host(plan.handle, ctypes.c_void_p(enc_h.data_ptr()), 4, 99, None, 0,
+                           ctypes.c_void_p(cube.data_ptr()), None, None)
+    assert st == hcg.HCG_E_UNSUPPORTED
     plan.destroy()
 
 
@@ -180,3 +262,38 @@ def test_full_size_sample_count_sampled():
     Vg, Wg = gather_cells(cube, W, cells)
     assert_cube_close(Vg.T, Vr.T, TOL_F32, "drift scan, sampled")
     assert_weights_close(Wg, Wr)
+
+
+def test_full_size_sample_count_forms_sampled():
+    """The 9.12M-sample drift scan (64 channels) streamed in two stored
+    forms: FP16 x scale from page-locked memory in slabs of 16, BF16 hi+lo
+    (two planes) from pageable memory in slabs of 48 (each plane packed
+    through the library's chunks).  Slabs equal hcg_grid on the device;
+    sampled cells meet the form's budget against the oracle."""
+    w = synth.drift_scan_cube(40, 12_000, 64, 600, 0.5, 3.0, synth.SEED0 + 1, device=DEV,
+                              name="drift_scan_600x600_c64")
+    print(f"{w.name}: {w.n} samples x {w.nchan} channels", flush=True)
+    plan = _plan(w)
+    g = w.grid
+    groups = sample_cells(g, seed=5, patches=3, patch=8)
+    cells = np.concatenate(groups)
+    ref = [sampled_oracle(w, c) for c in groups]
+    Vr = np.concatenate([v for v, _ in ref])
+    Wr = np.concatenate([x for _, x in ref])
+    for form, tol, pinned, slab in [(hcg.HCG_F16_SCALED, 1e-3, True, 16),
+                                    (hcg.HCG_BF16_SPLIT, 5e-5, False, 48)]:
+        print(f"form {form}, pinned {pinned}, slab {slab}", flush=True)
+        enc, scale, enc_h, scale_h = _encoded(w, form, pinned)
+        cube = _host((w.nchan, g.ny, g.nx), pinned)
+        W = _host((g.ny, g.nx), pinned)
+        hcg.hcg_grid_host(plan, enc_h, cube, W, slab=slab, dtype=form, chan_scale=scale_h)
+        del enc_h
+        Vd, Wd = _device_slabs_form(plan, w, enc, scale, form, slab)
+        del enc
+        assert np.array_equal(cube.numpy(), Vd, equal_nan=True), f"form {form}"
+        assert np.array_equal(W.numpy(), Wd)
+        del Vd
+        Vg, Wg = gather_cells(cube, W, cells)
+        assert_cube_close(Vg.T, Vr.T, tol, f"drift scan, form {form}, sampled")
+        assert_weights_close(Wg, Wr)
+    plan.destroy()
