@@ -236,7 +236,11 @@ hcg_status hcg_plan_ex(hcg_plan_t* out, const double* lon_deg, const double* lat
  *
  *   spectra     device [n][nchan] in the sample order given to hcg_plan,
  *               channel-fastest, in the storage type of dtype (two planes
- *               for the split dtypes).  Values should be finite: with
+ *               for the split dtypes).  Any element alignment is accepted;
+ *               rows read several elements at a time (nchan a multiple of
+ *               4, spectra aligned to 4 elements; for BF16 and FP16 x scale
+ *               a multiple of 8 and 16 bytes as well) are gridded faster.
+ *               Values should be finite: with
  *               nchan <= 8 (FP32) a non-finite value reaches exactly the
  *               cells within R of its sample, but the matrix-core forms
  *               multiply zero weights too (0 x NaN = NaN), so it can reach
@@ -577,7 +581,10 @@ hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_des
  *         may use different storage forms.
  * Every (field, tile, channel slab) is a work item.  Items are grouped by
  * kernel class (the few-channel FP32 gather, and the matrix-core gather of
- * each storage form, for rows read four elements or one at a time); per
+ * each storage form, for rows read four elements or one at a time; a
+ * BF16 or FP16 x scale class takes 512-channel slabs at narrow support only
+ * if every field's rows can be read eight at a time: nchan a multiple of 8,
+ * spectra 16-byte aligned); per
  * class, either a persistent kernel of two workgroups per CU pops the items
  * from per-XCD counters, or one launch runs one workgroup per item (the
  * fields' items in turn, each field's tiles dealt to the XCDs in contiguous

@@ -289,8 +289,13 @@ GatherArgs make_field_args(const hcg_plan_s* p, const hcg_field_data& d) {
   a.ntx = p->ntx;
   a.ntiles = p->ntx * p->nty;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
-  a.vec = (d.nchan % 4 == 0 && (uintptr_t)d.spectra % (4 * esz) == 0 &&
-           (!a.spec_lo || (uintptr_t)a.spec_lo % (4 * esz) == 0)) ? 1 : 0;
+  // 1: rows read four elements at a time; 2: eight too (16-byte aligned
+  // rows), which the narrow-support 512-channel BF16 and FP16 x scale
+  // kernels need
+  const bool rows4 = d.nchan % 4 == 0 && (uintptr_t)d.spectra % (4 * esz) == 0 &&
+                     (!a.spec_lo || (uintptr_t)a.spec_lo % (4 * esz) == 0);
+  const bool rows8 = rows4 && !a.spec_lo && d.nchan % 8 == 0 && (uintptr_t)d.spectra % 16 == 0;
+  a.vec = rows8 ? 2 : rows4 ? 1 : 0;
   a.c2R = support_chord2(p);
   a.cube = d.cube;
   a.wmap = d.weights;
@@ -322,6 +327,7 @@ struct hcg_batch_s {
   uint32_t nitems[kClasses] = {};
   uint32_t nseg[kClasses] = {};
   bool wide[kClasses] = {};
+  int cls_qw[kClasses] = {};  // slab width / 256 of each class
   int qw = 0, cost_order = 1, strategy = kLaunchPersistent;
   int cells_maxr = 0;  // largest range count of the plans
   bool tuned = false;
@@ -366,19 +372,32 @@ void free_batch(hcg_batch_s* b) {
 }
 
 // Item segments of every class for slab width 256 * qw (256 for the BF16
-// hi+lo form and for fields whose rows cannot be read four elements at a
-// time; one item per tile for the few-channel class).  The work-item launch
+// hi+lo form, for fields whose rows cannot be read four elements at a time,
+// and for a narrow-support BF16 or FP16 x scale class with a field whose rows
+// cannot be read eight at a time; one item per tile for the few-channel
+// class).  The work-item launch
 // gives a field slabs x (tiles rounded up to whole eighths) items.
 hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int cost_order,
                        int strategy, hipStream_t stream) {
   const size_t nf = b->plans.size();
+  bool cwide[kClasses] = {}, all8[kClasses];
+  for (int c = 0; c < kClasses; ++c) all8[c] = true;
+  for (size_t f = 0; f < nf; ++f) {
+    const int c = b->built_cls[f];
+    cwide[c] = cwide[c] || !(b->h_fields[f].c2R < kNarrowChord2);
+    all8[c] = all8[c] && b->built_vec[f] == 2;
+  }
+  for (int c = 0; c < kClasses; ++c)
+    b->cls_qw[c] = (c >= kClsCells || c == kBF16Split) ? 1
+                   : ((c == kBF16 || c == kF16S) && !cwide[c] && !all8[c]) ? 1
+                                                                            : qw;
   std::vector<double> cost(nf);
   std::vector<BatchSeg> seg(nf);
   for (size_t f = 0; f < nf; ++f) {
     const int64_t C = data[f].nchan;
     const int cls = b->built_cls[f];
     const bool cells = cls == kClsCells;
-    const int64_t width = cells ? C : ((cls < kClsCells && cls != kBF16Split) ? 256 * qw : 256);
+    const int64_t width = cells ? C : 256 * b->cls_qw[cls];
     const int64_t slabs = cells ? 1 : (C + width - 1) / width;
     const std::vector<uint32_t>& nc = b->ncand[f];
     double cand = 0.0;
@@ -435,7 +454,7 @@ hcg_status launch_direct(hcg_batch_s* b, hipStream_t stream) {
   for (int c = 0; c < kClasses; ++c) {
     if (!b->nitems[c]) continue;
     const ClassLaunch l{b->strategy, b->nblocks, b->nitems[c], b->nseg[c], b->cells_maxr};
-    const hcg_status st = launch_class(c, b->qw, b->wide[c], b->d_fields,
+    const hcg_status st = launch_class(c, b->cls_qw[c], b->wide[c], b->d_fields,
                                        b->d_segs + (size_t)c * nf,
                                        b->d_ctl + (size_t)c * kBatchCtl, l, stream);
     if (st != HCG_OK) return st;

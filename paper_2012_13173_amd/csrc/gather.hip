@@ -346,16 +346,20 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   // the other kernel shapes and the flagged form keep to 256-channel slabs
   // (registers for the cell frame, or for the weight-sum accumulators)
   const bool gen = p->kern.type != kGauss;
-  const int qw = (C > 256 && vec && kForm != kBF16Split && !gen && !kMask &&
+  // supports below 0.57 deg (squared chord < 1e-4) take the kernels with the
+  // short distance series
+  const bool wide = !(a.c2R < kNarrowChord2);
+  // the narrow-support 512-channel kernels of BF16 and FP16 x scale in input
+  // order read a row's channels eight at a time (16-byte loads)
+  const bool rows8 = kPacked || wide || !(kForm == kBF16 || kForm == kF16S) ||
+                     (C % 8 == 0 && (uintptr_t)spec % 16 == 0);
+  const int qw = (C > 256 && vec && rows8 && kForm != kBF16Split && !gen && !kMask &&
                   groups512 >= kFewGroups) ? 2 : 1;
   const int64_t slab_ch = 256 * qw;
   const int64_t slabs = (C + slab_ch - 1) / slab_ch;
   const int64_t blocks = slabs * a.tiles_per_xcd * 8;
   if (blocks > INT32_MAX) return fail(HCG_E_UNSUPPORTED, "hcg_grid: too many channels");
   const dim3 grid((unsigned)blocks), block(256);
-  // supports below 0.57 deg (squared chord < 1e-4) take the kernels with the
-  // short distance series
-  const bool wide = !(a.c2R < kNarrowChord2);
 #define HCG_MFMA(QW, VEC)                                                                \
   do {                                                                                   \
     if (wide) k_gather_mfma<kForm, QW, VEC, kPacked, true><<<grid, block, 0, stream>>>(a); \

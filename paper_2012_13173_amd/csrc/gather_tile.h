@@ -601,6 +601,21 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   // the later k-steps' pieces too, one k-step ahead -- except in the
   // wide-support kernels of 512-channel slabs, whose registers would spill
   constexpr bool kRawAhead = kEarlyRaw && (!kWide || kQW == 1);
+  // BF16 and FP16 x scale in 512-channel slabs (narrow support): a lane's
+  // eight consecutive channels of a row in one 16-byte load, so that a
+  // k-step takes eight loads per lane instead of sixteen.  The launchers
+  // take these kernels only for rows that can be read eight elements at a
+  // time (C a multiple of 8, spectra 16-byte aligned); with C % 8 == 0 a
+  // lane's eight channels are all in the row or all past it.
+  constexpr bool kW16 = kRawAhead && kQW == 2 && !is_fp8(kForm);
+  const int64_t my_ch8 = c_w + 8 * (lane & 15);
+  uint4 w16[kW16 ? 8 : 1];
+  auto load_w = [&](const uint32_t* rows, int ks, int t) {
+    const bool ok = my_ch8 < C;
+    const int64_t row = rows[kK * ks + 8 * (lane >> 4) + t];
+    const uint4 v = *(const uint4*)((const uint16_t*)a.spec + row * C + (ok ? my_ch8 : 0));
+    w16[t] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+  };
   // FP32: a ring of kDepth k-steps' rows in flight.  The row loads are
   // issued unconditionally (an index past the last channel is clamped into
   // the row and the value replaced after the load): a load under a divergent
@@ -639,7 +654,12 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
       for (int ks = 0; ks < kEarly; ++ks) load_b(s_row, ks);
     }
-    if constexpr (kEarlyRaw) load_raw(s_row);
+    if constexpr (kW16) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) load_w(s_row, 0, t);
+    } else if constexpr (kEarlyRaw) {
+      load_raw(s_row);
+    }
     if constexpr (kForm == kF32) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) load(s_row, d, bb[d]);
@@ -771,6 +791,52 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           }
         }
       }
+    } else if constexpr (kW16) {
+      // the eight rows' pieces are transposed into the B operands of the
+      // eight channels two rows at a time, and those two rows' pieces of the
+      // next k-step loaded into the freed registers (all unconditional); the
+      // products of the k-step follow.  (Drift scan, 9.12M x 1024: FP16 x
+      // scale 29.6 -> 22.9 ms, BF16 30.0 -> 23.5 ms, same results bit for
+      // bit; loading all eight rows after the transposition spilled
+      // registers, and loading them at the k-step was slower.)
+      const uint4* A16 = sA16(ab);
+      const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
+#pragma unroll
+      for (int ks = 0; ks < kNS; ++ks) {
+        const bool act = (any >> ks) & 1u;
+        uint32_t fb[8][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const uint4 d0 = w16[2 * m], d1 = w16[2 * m + 1];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const uint2 h0 = q < 4 ? make_uint2(d0.x, d0.y) : make_uint2(d0.z, d0.w);
+            const uint2 h1 = q < 4 ? make_uint2(d1.x, d1.y) : make_uint2(d1.z, d1.w);
+            fb[q][m] = elem16(h0, q & 3) | (elem16(h1, q & 3) << 16);
+          }
+          if (ks + 1 < kNS) {
+            load_w(s_row, ks + 1, 2 * m);
+            load_w(s_row, ks + 1, 2 * m + 1);
+          }
+        }
+        if (!act) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if (!((nzc[cb] >> ks) & 1u)) continue;
+          const uint4 av = A16[(cb * kNS + ks) * 64 + lane];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            floatx4& c = acc[cb][q];
+            const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
+            if constexpr (kForm == kF16S)
+              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, av),
+                                                        __builtin_bit_cast(halfx8, bv), c, 0, 0, 0);
+            else
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                         __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
+          }
+        }
+      }
     } else if constexpr (kRawAhead) {
       // input-order BF16, FP16 x scale and FP8 x scale rows read four
       // channels at a time: the raw row pieces of k-step ks + 1 are loaded
@@ -779,9 +845,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       // while the previous k-step's products are issued (k-step 0's are
       // loaded at the block's top).  The loads are unconditional: a load
       // under a branch makes the compiler wait for all outstanding loads.
-      // (Drift scan, 9.12M x 1024: FP8 x scale 22.2 -> 20.4 ms, BF16 and
-      // FP16 x scale 30.7 -> 30.1 and 30.2 -> 29.6 ms, same results bit for
-      // bit.)
+      // (Drift scan, 9.12M x 1024: FP8 x scale 22.2 -> 20.4 ms, same results
+      // bit for bit; eight FP8 channels per lane measured slower, 21.8 ms.)
       const uint4* A16 = sA16(ab);
       const uint2* A8 = sA8(ab);
       const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
@@ -1016,8 +1081,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         // accumulator 4 h + q: channel 4 (lane % 16) + 64 h + q, or for the
-        // plan-ordered spectra lane % 16 + 16 (4 h + q)
-        const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15) : my_ch + 64 * h + q;
+        // plan-ordered spectra lane % 16 + 16 (4 h + q), or for eight
+        // channels per lane 8 (lane % 16) + 4 h + q
+        const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15)
+                           : kW16  ? my_ch8 + 4 * h + q
+                                   : my_ch + 64 * h + q;
         if (ch >= C) continue;
         const float sc = (kForm == kF16S || is_fp8(kForm)) ? a.scale[ch] : 1.f;
         float v[4], wc[4];

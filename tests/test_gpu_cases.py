@@ -12,7 +12,11 @@
   before any launch;
 * tiles with more candidate ranges than the phase-rotated staging holds (a
   wide support at longitude 0, two ranges per ring) next to tiles that are
-  rotated, in the FP32 form and two matrix-core forms.
+  rotated, in the FP32 form and two matrix-core forms;
+* input-order BF16 and FP16 x scale spectra whose rows are read eight
+  elements at a time (512-channel slabs, C a multiple of 8, 16-byte aligned)
+  against the same spectra read four at a time (256-channel slabs), bit for
+  bit, and against the oracle.
 """
 import math
 
@@ -209,4 +213,48 @@ def test_tiles_of_more_ranges_than_a_rotation_holds():
             cube, W = _grid(w, plan, form, packed)
             assert_cube_close(cube.cpu().numpy(), Vr, tol, f"{name} packed={packed}, > 512 ranges")
             assert_weights_close(W.cpu().numpy(), Wr)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("nchan", [520, 516])
+def test_rows_read_eight_channels_at_a_time(nchan):
+    """A map of 576 8 x 8 tiles takes 512-channel slabs above 256 channels.
+    C = 520: the input-order BF16 and FP16 x scale gathers read a lane's eight
+    channels of a row in one load (the second slab holds 8 channels); the same
+    encoding placed 8 bytes off a 16-byte boundary is read four channels at a
+    time in 256-channel slabs, and both give the same cube bit for bit (the
+    same weights and the same products in the same order per channel).
+    C = 516 (not a multiple of 8) takes the four-channel reads for both.  Each
+    cube matches the oracle on sampled cells at the form's budget."""
+    w = synth.small_cube(n=120_000, nchan=nchan, nx=192, ny=192, cell_arcmin=0.5,
+                         seed=470 + nchan)
+    plan = _plan(w)
+    info = plan.info()
+    assert info["ntiles_x"] * info["ntiles_y"] >= 512
+    groups = sample_cells(w.grid, seed=9, patches=3, patch=10)
+    cells = np.concatenate(groups)
+    ref = [sampled_oracle(w, c) for c in groups]
+    Vr = np.concatenate([v for v, _ in ref])
+    Wr = np.concatenate([x for _, x in ref])
+    spec = w.spectra.to(DEV).contiguous()
+    g = w.grid
+    for form, tol in [(hcg.HCG_BF16, 1e-2), (hcg.HCG_F16_SCALED, 1e-3)]:
+        print(f"C={nchan} form {form}", flush=True)
+        enc, scale = hcg.hcg_quantize(spec, form)
+        cube = torch.empty((nchan, g.ny, g.nx), dtype=torch.float32, device=DEV)
+        W = torch.empty((g.ny, g.nx), dtype=torch.float32, device=DEV)
+        hcg.hcg_grid(plan, enc, cube, W, dtype=form, chan_scale=scale)
+        flat = torch.empty(enc.numel() + 4, dtype=enc.dtype, device=DEV)
+        off = flat[4:].view(enc.shape)
+        off.copy_(enc)
+        assert off.data_ptr() % 16 == 8
+        cube_off = torch.empty_like(cube)
+        hcg.hcg_grid(plan, off, cube_off, None, dtype=form, chan_scale=scale)
+        torch.cuda.synchronize()
+        assert torch.equal(cube.view(torch.int32), cube_off.view(torch.int32)), (
+            f"C={nchan} form {form}: eight- and four-channel reads differ")
+        V, Wg = gather_cells(cube, W, cells)
+        assert_cube_close(V.T, Vr.T, tol, f"C={nchan} form {form}, 576 tiles")
+        assert_weights_close(Wg, Wr)
+        del enc, flat, off, cube, cube_off
     plan.destroy()
