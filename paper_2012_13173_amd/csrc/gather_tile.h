@@ -575,7 +575,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   constexpr bool kEarlyRaw = !kPacked && kVec && (kForm == kBF16 || kForm == kF16S ||
                                                   kForm == kFP8S);
   uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
-  uint32_t e8[(kEarlyRaw && is_fp8(kForm)) ? kQW : 1][8];
+  // input-order FP8 hi+lo: both planes' pieces one k-step ahead (not in the
+  // general-shape kernels, whose registers would spill)
+  constexpr bool kSplitAhead = !kPacked && kVec && kForm == kFP8Split && !kGen && (!kWide || kQW == 1);
+  uint32_t e8[((kEarlyRaw && is_fp8(kForm)) || kSplitAhead) ? kQW : 1][8];
+  uint32_t e8l[kSplitAhead ? kQW : 1][8];
   auto load_raw_h = [&](const uint32_t* rows, int ks, int h) {
     {
       const int64_t ch = my_ch + 64 * h;
@@ -587,6 +591,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           const bool ok = ch + 3 < C;
           const uint32_t v = *(const uint32_t*)((const uint8_t*)a.spec + row * C + (ok ? ch : 0));
           e8[h][t] = ok ? v : 0u;
+          if constexpr (kSplitAhead) {
+            const uint32_t vl =
+                *(const uint32_t*)((const uint8_t*)a.spec_lo + row * C + (ok ? ch : 0));
+            e8l[h][t] = ok ? vl : 0u;
+          }
         } else {
           const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
           e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
@@ -600,7 +609,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   };
   // the later k-steps' pieces too, one k-step ahead -- except in the
   // wide-support kernels of 512-channel slabs, whose registers would spill
-  constexpr bool kRawAhead = kEarlyRaw && (!kWide || kQW == 1);
+  constexpr bool kRawAhead = (kEarlyRaw && (!kWide || kQW == 1)) || kSplitAhead;
   // BF16 and FP16 x scale in 512-channel slabs (narrow support): a lane's
   // eight consecutive channels of a row in one 16-byte load, so that a
   // k-step takes eight loads per lane instead of sixteen.  The launchers
@@ -657,7 +666,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
     if constexpr (kW16) {
 #pragma unroll
       for (int t = 0; t < 8; ++t) load_w(s_row, 0, t);
-    } else if constexpr (kEarlyRaw) {
+    } else if constexpr (kEarlyRaw || kSplitAhead) {
       load_raw(s_row);
     }
     if constexpr (kForm == kF32) {
@@ -838,15 +847,16 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         }
       }
     } else if constexpr (kRawAhead) {
-      // input-order BF16, FP16 x scale and FP8 x scale rows read four
-      // channels at a time: the raw row pieces of k-step ks + 1 are loaded
+      // input-order BF16, FP16 x scale, FP8 x scale and FP8 hi+lo rows read
+      // four channels at a time: the raw row pieces of k-step ks + 1 are loaded
       // into the registers that held those of k-step ks once these are
       // repacked into B operands, so that a k-step's loads are in flight
       // while the previous k-step's products are issued (k-step 0's are
       // loaded at the block's top).  The loads are unconditional: a load
       // under a branch makes the compiler wait for all outstanding loads.
-      // (Drift scan, 9.12M x 1024: FP8 x scale 22.2 -> 20.4 ms, same results
-      // bit for bit; eight FP8 channels per lane measured slower, 21.8 ms.)
+      // (Drift scan, 9.12M x 1024: FP8 x scale 22.2 -> 20.4 ms, FP8 hi+lo
+      // 33.7 -> 32.4 ms, same results bit for bit; eight FP8 channels per
+      // lane measured slower, 21.8 ms.)
       const uint4* A16 = sA16(ab);
       const uint2* A8 = sA8(ab);
       const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
@@ -856,14 +866,25 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
         for (int h = 0; h < kQW; ++h) {
           uint32_t fb[4][4];
+          uint32_t fbl[kSplitAhead ? 4 : 1][2];
           if constexpr (is_fp8(kForm)) {
-            const uint32_t* d = e8[kEarlyRaw ? h : 0];
+            const uint32_t* d = e8[h];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               fb[q][0] = ((d[0] >> (8 * q)) & 0xFFu) | (((d[1] >> (8 * q)) & 0xFFu) << 8) |
                          (((d[2] >> (8 * q)) & 0xFFu) << 16) | (((d[3] >> (8 * q)) & 0xFFu) << 24);
               fb[q][1] = ((d[4] >> (8 * q)) & 0xFFu) | (((d[5] >> (8 * q)) & 0xFFu) << 8) |
                          (((d[6] >> (8 * q)) & 0xFFu) << 16) | (((d[7] >> (8 * q)) & 0xFFu) << 24);
+            }
+            if constexpr (kSplitAhead) {
+              const uint32_t* dl = e8l[h];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                fbl[q][0] = ((dl[0] >> (8 * q)) & 0xFFu) | (((dl[1] >> (8 * q)) & 0xFFu) << 8) |
+                            (((dl[2] >> (8 * q)) & 0xFFu) << 16) | (((dl[3] >> (8 * q)) & 0xFFu) << 24);
+                fbl[q][1] = ((dl[4] >> (8 * q)) & 0xFFu) | (((dl[5] >> (8 * q)) & 0xFFu) << 8) |
+                            (((dl[6] >> (8 * q)) & 0xFFu) << 16) | (((dl[7] >> (8 * q)) & 0xFFu) << 24);
+              }
             }
           } else {
             const uint2* d = e16[kEarlyRaw ? h : 0];
@@ -886,6 +907,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                 const long Aop = (long)(((uint64_t)av.y << 32) | av.x);
                 const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, B, c, 0, 0, 0);
+                if constexpr (kSplitAhead) {
+                  // W_hi S_lo + W_lo S_hi (the W_lo S_lo term is below the budget)
+                  const uint2 al = A8[(4 * kNS + cb * kNS + ks) * 64 + lane];
+                  const long Al = (long)(((uint64_t)al.y << 32) | al.x);
+                  const long Bl = (long)(((uint64_t)fbl[q][1] << 32) | fbl[q][0]);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, Bl, c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Al, B, c, 0, 0, 0);
+                }
               } else {
                 const uint4 av = A16[(cb * kNS + ks) * 64 + lane];
                 const uint4 bv = make_uint4(fb[q][0], fb[q][1], fb[q][2], fb[q][3]);
