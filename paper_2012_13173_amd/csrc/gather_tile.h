@@ -574,10 +574,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   // are loaded at the block's top as well (repacked where they are used)
   constexpr bool kEarlyRaw = !kPacked && kVec && (kForm == kBF16 || kForm == kF16S ||
                                                   kForm == kFP8S);
-  uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
   // input-order FP8 hi+lo: both planes' pieces one k-step ahead (not in the
   // general-shape kernels, whose registers would spill)
   constexpr bool kSplitAhead = !kPacked && kVec && kForm == kFP8Split && !kGen && (!kWide || kQW == 1);
+  // the later k-steps' pieces too, one k-step ahead -- except in the
+  // wide-support kernels of 512-channel slabs, whose registers would spill
+  constexpr bool kRawAhead = (kEarlyRaw && (!kWide || kQW == 1)) || kSplitAhead;
+  uint2 e16[(kEarlyRaw && !is_fp8(kForm)) ? kQW : 1][8];
   uint32_t e8[((kEarlyRaw && is_fp8(kForm)) || kSplitAhead) ? kQW : 1][8];
   uint32_t e8l[kSplitAhead ? kQW : 1][8];
   auto load_raw_h = [&](const uint32_t* rows, int ks, int h) {
@@ -589,16 +592,16 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         if constexpr (is_fp8(kForm)) {
           // 4-byte pieces: unconditional (clamped) loads measured faster
           const bool ok = ch + 3 < C;
-          const uint32_t v = *(const uint32_t*)((const uint8_t*)a.spec + row * C + (ok ? ch : 0));
-          e8[h][t] = ok ? v : 0u;
-          if constexpr (kSplitAhead) {
-            const uint32_t vl =
-                *(const uint32_t*)((const uint8_t*)a.spec_lo + row * C + (ok ? ch : 0));
-            e8l[h][t] = ok ? vl : 0u;
-          }
+          e8[h][t] = *(const uint32_t*)((const uint8_t*)a.spec + row * C + (ok ? ch : 0));
+          if constexpr (kSplitAhead)
+            e8l[h][t] = *(const uint32_t*)((const uint8_t*)a.spec_lo + row * C + (ok ? ch : 0));
         } else {
-          const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
-          e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+          if constexpr (kRawAhead) {
+            e16[h][t] = *(const uint2*)((const uint16_t*)a.spec + row * C + ((ch + 3 < C) ? ch : 0));
+          } else {
+            const uint16_t* src = (const uint16_t*)a.spec + row * C + ch;
+            e16[h][t] = (ch + 3 < C) ? *(const uint2*)src : make_uint2(0u, 0u);
+          }
         }
       }
     }
@@ -607,9 +610,6 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
 #pragma unroll
     for (int h = 0; h < kQW; ++h) load_raw_h(rows, 0, h);
   };
-  // the later k-steps' pieces too, one k-step ahead -- except in the
-  // wide-support kernels of 512-channel slabs, whose registers would spill
-  constexpr bool kRawAhead = (kEarlyRaw && (!kWide || kQW == 1)) || kSplitAhead;
   // BF16 and FP16 x scale in 512-channel slabs (narrow support): a lane's
   // eight consecutive channels of a row in one 16-byte load, so that a
   // k-step takes eight loads per lane instead of sixteen.  The launchers
@@ -619,11 +619,17 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   constexpr bool kW16 = kRawAhead && kQW == 2 && !is_fp8(kForm);
   const int64_t my_ch8 = c_w + 8 * (lane & 15);
   uint4 w16[kW16 ? 8 : 1];
+  // The loads of the kernels that load a k-step ahead are unconditional and
+  // keep what they read: a select of zero for the lanes past the last
+  // channel made the compiler branch around the load, and after such a
+  // branch it waits for every outstanding load, the next k-step's included
+  // (BF16 and FP16 x scale 23.8 -> 21.2 ms on the drift scan).  Such a lane
+  // reads its row's first channels instead; their products only reach
+  // accumulators of channels >= C, which are never stored.
   auto load_w = [&](const uint32_t* rows, int ks, int t) {
     const bool ok = my_ch8 < C;
     const int64_t row = rows[kK * ks + 8 * (lane >> 4) + t];
-    const uint4 v = *(const uint4*)((const uint16_t*)a.spec + row * C + (ok ? my_ch8 : 0));
-    w16[t] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+    w16[t] = *(const uint4*)((const uint16_t*)a.spec + row * C + (ok ? my_ch8 : 0));
   };
   // FP32: a ring of kDepth k-steps' rows in flight.  The row loads are
   // issued unconditionally (an index past the last channel is clamped into
