@@ -16,7 +16,11 @@
 * input-order BF16 and FP16 x scale spectra whose rows are read eight
   elements at a time (512-channel slabs, C a multiple of 8, 16-byte aligned)
   against the same spectra read four at a time (256-channel slabs), bit for
-  bit, and against the oracle.
+  bit, and against the oracle;
+* channels stay apart: with channel 0 non-finite in every sample, no other
+  channel of any form holds a NaN where the map has samples (lanes whose
+  channels lie past the last one read their row's first channels, whose
+  products go to accumulators that are never stored).
 """
 import math
 
@@ -257,4 +261,30 @@ def test_rows_read_eight_channels_at_a_time(nchan):
         assert_cube_close(V.T, Vr.T, tol, f"C={nchan} form {form}, 576 tiles")
         assert_weights_close(Wg, Wr)
         del enc, flat, off, cube, cube_off
+    plan.destroy()
+
+
+@pytest.mark.parametrize("nchan", [40, 300, 520])
+def test_a_non_finite_channel_stays_in_its_channel(nchan):
+    # C = 40: one 64-channel group per wave, partly past the last channel;
+    # C = 300: 256-channel slabs, the second holding 44; C = 520 on 576
+    # tiles: eight channels per lane, the second 512-channel slab holding 8
+    w = synth.small_cube(n=120_000, nchan=nchan, nx=192, ny=192, cell_arcmin=0.5,
+                         seed=480 + nchan)
+    spec = w.spectra.clone()
+    spec[:, 0] = float("nan")
+    plan = _plan(w)
+    empty = np.isnan(_grid(w, plan)[0].cpu().numpy()[1])  # cells without samples
+    assert (~empty).sum() > 0.9 * empty.size
+    forms = [("f32", hcg.HCG_F32)] + [(k, v[0]) for k, v in FORMS.items()]
+    for name, form in forms:
+        print(f"C={nchan} {name}", flush=True)
+        cube, _ = _grid(w, plan, form, spectra=spec)
+        V = cube.cpu().numpy()
+        leaked = np.isnan(V[1:]) & ~empty[None]
+        assert not leaked.any(), (
+            f"C={nchan} {name}: NaN in {int(leaked.sum())} values of channels 1..{nchan - 1}")
+        if form == hcg.HCG_F32:
+            assert np.isnan(V[0]).all(), f"C={nchan}: channel 0 should be NaN everywhere"
+        del cube
     plan.destroy()
