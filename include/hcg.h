@@ -386,9 +386,10 @@ hcg_status hcg_grid_packed(hcg_plan_t plan, const void* packed, int64_t nchan, h
  *   chan_scale    host float [nchan] for the scaled forms (the scales the
  *                 encoding used, as hcg_quantize writes them); NULL for the
  *                 others.
- *   slab_chan     channels per slab; 0 picks 512 (fewer if one slab of
- *                 spectra, all planes, or of the cube would exceed 4 GiB).
- *                 The last slab may be shorter.
+ *   slab_chan     channels per slab; 0 picks 512, or fewer (a multiple of
+ *                 8) where the slab buffers below would take more than a
+ *                 quarter of the free device memory.  The last slab may be
+ *                 shorter.
  *   cube_host     host float [nchan][ny][nx]: V as hcg_grid writes it.
  *   weights_host  host float [ny][nx] or NULL: W as hcg_grid writes it.
  *

@@ -258,12 +258,19 @@ static hcg_status grid_host(hcg_plan_t plan, const void* spectra_host, int64_t n
   const int64_t G = (int64_t)p->grid.nx * p->grid.ny;
   const size_t esz = form_elem(dtype);
   const int planes = form_split(dtype) ? 2 : 1;
-  // default slab: 512 channels, or fewer so that one spectra buffer (all its
-  // planes) or one cube slab stays within 4 GiB
+  // default slab: 512 channels, or fewer so that the double buffers of
+  // spectra (all planes) and cube take at most a quarter of the free device
+  // memory, rounded down to a multiple of 8 channels (wide rows copy at the
+  // link's rate; rows of a few dozen bytes copy at a fraction of it)
   int64_t cs = slab_chan ? slab_chan : 512;
-  const int64_t cap = std::max<int64_t>(
-      1, ((int64_t)4 << 30) / std::max<int64_t>((int64_t)esz * planes * n, 4 * G));
-  if (!slab_chan) cs = std::min(cs, cap);
+  if (!slab_chan) {
+    size_t free_b = 0, total_b = 0;
+    HCG_HIP(hipMemGetInfo(&free_b, &total_b));
+    const int64_t per_chan = 2 * ((int64_t)esz * planes * n + 4 * G);
+    int64_t cap = std::max<int64_t>(1, (int64_t)(free_b / 4) / std::max<int64_t>(per_chan, 1));
+    if (cap >= 8) cap -= cap % 8;
+    cs = std::min(cs, cap);
+  }
   cs = std::min(cs, nchan);
   const int64_t nslab = (nchan + cs - 1) / cs;
   hipStream_t s_grid = (hipStream_t)hip_stream;
