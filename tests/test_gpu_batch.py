@@ -265,3 +265,40 @@ def test_batch_plans_equal_single_plans():
     with pytest.raises(hcg.HcgError):
         b.plan(len(ws))
     b.destroy()
+
+
+@pytest.mark.parametrize("form", [hcg.HCG_BF16, hcg.HCG_F16_SCALED])
+@pytest.mark.parametrize("chan_tile", [256, 512])
+def test_eight_channel_rows_in_a_batch_class(form, chan_tile):
+    """Input-order BF16 and FP16 x scale fields of one kernel class whose rows
+    can (C = 520, 16-byte aligned) and cannot (C = 516; C = 520 placed 8
+    bytes off a 16-byte boundary) be read eight elements at a time.  The
+    narrow-support 512-channel kernels read eight, so with such a field in the
+    class the class takes 256-channel slabs; a class of eight-channel rows
+    alone keeps 512.  Every field equals its single hcg_grid call bit for bit
+    (the same weights and products per channel in every slab width)."""
+    w520 = synth.small_cube(n=12000, nchan=520, nx=24, ny=20, seed=221, name="c520")
+    w516 = synth.small_cube(n=12000, nchan=516, nx=20, ny=24, seed=222, name="c516")
+    enc520, sc520 = hcg.hcg_quantize(w520.spectra.to(DEV).contiguous(), form)
+    enc516, sc516 = hcg.hcg_quantize(w516.spectra.to(DEV).contiguous(), form)
+    flat = torch.empty(enc520.numel() + 4, dtype=enc520.dtype, device=DEV)
+    off520 = flat[4:].view(enc520.shape)
+    off520.copy_(enc520)
+    assert off520.data_ptr() % 16 == 8
+    cases = [([w520, w516, w520], [enc520, enc516, off520], [sc520, sc516, sc520]),
+             ([w520], [enc520], [sc520])]
+    for ws, spectra, scales in cases:
+        print(f"form {form} chan_tile {chan_tile}: fields {[w.name for w in ws]}", flush=True)
+        b = _plan(ws, chan_tile=chan_tile, launch="items")
+        cubes, wts = _outputs(ws)
+        hcg.hcg_grid_batch(b, spectra, cubes, wts, dtypes=[form] * len(ws), chan_scales=scales)
+        torch.cuda.synchronize()
+        assert b.info()["chan_slab"] == chan_tile
+        b.destroy()
+        for w, sp, sc, cube in zip(ws, spectra, scales, cubes):
+            plan = hcg.hcg_plan(w.lon.to(DEV), w.lat.to(DEV), w.grid, w.fwhm_deg, w.support_deg)
+            single = torch.empty_like(cube)
+            hcg.hcg_grid(plan, sp, single, dtype=form, chan_scale=sc)
+            torch.cuda.synchronize()
+            plan.destroy()
+            assert np.array_equal(cube.cpu().numpy(), single.cpu().numpy(), equal_nan=True), w.name
