@@ -238,8 +238,9 @@ hcg_status hcg_plan_ex(hcg_plan_t* out, const double* lon_deg, const double* lat
  *               channel-fastest, in the storage type of dtype (two planes
  *               for the split dtypes).  Any element alignment is accepted;
  *               rows read several elements at a time (nchan a multiple of
- *               4, spectra aligned to 4 elements; for BF16 and FP16 x scale
- *               a multiple of 8 and 16 bytes as well) are gridded faster.
+ *               4, spectra aligned to 4 elements; for BF16, FP16 x scale
+ *               and FP8 x scale a multiple of 8 and 8 elements as well) are
+ *               gridded faster.
  *               Values should be finite: with
  *               nchan <= 8 (FP32) a non-finite value reaches exactly the
  *               cells within R of its sample, but the matrix-core forms
@@ -583,9 +584,9 @@ hcg_status hcg_plan_batch(hcg_batch_t* out, int32_t nfields, const hcg_field_des
  * Every (field, tile, channel slab) is a work item.  Items are grouped by
  * kernel class (the few-channel FP32 gather, and the matrix-core gather of
  * each storage form, for rows read four elements or one at a time; a
- * BF16 or FP16 x scale class takes 512-channel slabs at narrow support only
- * if every field's rows can be read eight at a time: nchan a multiple of 8,
- * spectra 16-byte aligned); per
+ * BF16, FP16 x scale or FP8 x scale class takes 512-channel slabs at narrow
+ * support only if every field's rows can be read eight at a time: nchan a
+ * multiple of 8, spectra aligned to 8 elements); per
  * class, either a persistent kernel of two workgroups per CU pops the items
  * from per-XCD counters, or one launch runs one workgroup per item (the
  * fields' items in turn, each field's tiles dealt to the XCDs in contiguous

@@ -289,12 +289,13 @@ GatherArgs make_field_args(const hcg_plan_s* p, const hcg_field_data& d) {
   a.ntx = p->ntx;
   a.ntiles = p->ntx * p->nty;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
-  // 1: rows read four elements at a time; 2: eight too (16-byte aligned
-  // rows), which the narrow-support 512-channel BF16 and FP16 x scale
-  // kernels need
+  // 1: rows read four elements at a time; 2: eight too (rows aligned to 8
+  // elements), which the narrow-support 512-channel BF16, FP16 x scale and
+  // FP8 x scale kernels need
   const bool rows4 = d.nchan % 4 == 0 && (uintptr_t)d.spectra % (4 * esz) == 0 &&
                      (!a.spec_lo || (uintptr_t)a.spec_lo % (4 * esz) == 0);
-  const bool rows8 = rows4 && !a.spec_lo && d.nchan % 8 == 0 && (uintptr_t)d.spectra % 16 == 0;
+  const bool rows8 = rows4 && !a.spec_lo && d.nchan % 8 == 0 &&
+                     (uintptr_t)d.spectra % (8 * esz) == 0;
   a.vec = rows8 ? 2 : rows4 ? 1 : 0;
   a.c2R = support_chord2(p);
   a.cube = d.cube;
@@ -373,9 +374,9 @@ void free_batch(hcg_batch_s* b) {
 
 // Item segments of every class for slab width 256 * qw (256 for the BF16
 // hi+lo form, for fields whose rows cannot be read four elements at a time,
-// and for a narrow-support BF16 or FP16 x scale class with a field whose rows
-// cannot be read eight at a time; one item per tile for the few-channel
-// class).  The work-item launch
+// and for a narrow-support BF16, FP16 x scale or FP8 x scale class with a
+// field whose rows cannot be read eight at a time; one item per tile for the
+// few-channel class).  The work-item launch
 // gives a field slabs x (tiles rounded up to whole eighths) items.
 hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int cost_order,
                        int strategy, hipStream_t stream) {
@@ -389,7 +390,7 @@ hcg_status build_items(hcg_batch_s* b, const hcg_field_data* data, int qw, int c
   }
   for (int c = 0; c < kClasses; ++c)
     b->cls_qw[c] = (c >= kClsCells || c == kBF16Split) ? 1
-                   : ((c == kBF16 || c == kF16S) && !cwide[c] && !all8[c]) ? 1
+                   : ((c == kBF16 || c == kF16S || c == kFP8S) && !cwide[c] && !all8[c]) ? 1
                                                                             : qw;
   std::vector<double> cost(nf);
   std::vector<BatchSeg> seg(nf);

@@ -349,10 +349,10 @@ static hcg_status launch_mfma(const hcg_plan_s* p, const void* spec, const void*
   // supports below 0.57 deg (squared chord < 1e-4) take the kernels with the
   // short distance series
   const bool wide = !(a.c2R < kNarrowChord2);
-  // the narrow-support 512-channel kernels of BF16 and FP16 x scale in input
-  // order read a row's channels eight at a time (16-byte loads)
-  const bool rows8 = kPacked || wide || !(kForm == kBF16 || kForm == kF16S) ||
-                     (C % 8 == 0 && (uintptr_t)spec % 16 == 0);
+  // the narrow-support 512-channel kernels of BF16, FP16 x scale and FP8 x
+  // scale in input order read a row's channels eight at a time
+  const bool rows8 = kPacked || wide || !(kForm == kBF16 || kForm == kF16S || kForm == kFP8S) ||
+                     (C % 8 == 0 && (uintptr_t)spec % (8 * esz) == 0);
   const int qw = (C > 256 && vec && rows8 && kForm != kBF16Split && !gen && !kMask &&
                   groups512 >= kFewGroups) ? 2 : 1;
   const int64_t slab_ch = 256 * qw;

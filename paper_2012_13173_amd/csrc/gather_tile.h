@@ -614,11 +614,20 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   // eight consecutive channels of a row in one 16-byte load, so that a
   // k-step takes eight loads per lane instead of sixteen.  The launchers
   // take these kernels only for rows that can be read eight elements at a
-  // time (C a multiple of 8, spectra 16-byte aligned); with C % 8 == 0 a
-  // lane's eight channels are all in the row or all past it.
+  // time (C a multiple of 8, spectra aligned to 8 elements); with C % 8 == 0
+  // a lane's eight channels are all in the row or all past it.
   constexpr bool kW16 = kRawAhead && kQW == 2 && !is_fp8(kForm);
+  // FP8 x scale the same way, eight channels in one 8-byte load (FP8 x scale
+  // 20.3 -> 18.4 ms on the drift scan, same results bit for bit)
+  constexpr bool kW8 = kRawAhead && kQW == 2 && kForm == kFP8S;
   const int64_t my_ch8 = c_w + 8 * (lane & 15);
   uint4 w16[kW16 ? 8 : 1];
+  uint2 w8[kW8 ? 8 : 1];
+  auto load_w8 = [&](const uint32_t* rows, int ks, int t) {
+    const bool ok = my_ch8 < C;
+    const int64_t row = rows[kK * ks + 8 * (lane >> 4) + t];
+    w8[t] = *(const uint2*)((const uint8_t*)a.spec + row * C + (ok ? my_ch8 : 0));
+  };
   // The loads of the kernels that load a k-step ahead are unconditional and
   // keep what they read: a select of zero for the lanes past the last
   // channel made the compiler branch around the load, and after such a
@@ -672,6 +681,9 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
     if constexpr (kW16) {
 #pragma unroll
       for (int t = 0; t < 8; ++t) load_w(s_row, 0, t);
+    } else if constexpr (kW8) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) load_w8(s_row, 0, t);
     } else if constexpr (kEarlyRaw || kSplitAhead) {
       load_raw(s_row);
     }
@@ -852,6 +864,42 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
           }
         }
       }
+    } else if constexpr (kW8) {
+      const uint2* A8 = sA8(ab);
+      const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
+#pragma unroll
+      for (int ks = 0; ks < kNS; ++ks) {
+        const bool act = (any >> ks) & 1u;
+        uint32_t fb[8][2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int sh = 8 * (q & 3);
+          uint32_t v0 = 0u, v1 = 0u;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            v0 |= (((q < 4 ? w8[t].x : w8[t].y) >> sh) & 0xFFu) << (8 * t);
+            v1 |= (((q < 4 ? w8[4 + t].x : w8[4 + t].y) >> sh) & 0xFFu) << (8 * t);
+          }
+          fb[q][0] = v0;
+          fb[q][1] = v1;
+        }
+        if (ks + 1 < kNS) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) load_w8(s_row, ks + 1, t);
+        }
+        if (!act) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if (!((nzc[cb] >> ks) & 1u)) continue;
+          const uint2 av = A8[(cb * kNS + ks) * 64 + lane];
+          const long Aop = (long)(((uint64_t)av.y << 32) | av.x);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const long B = (long)(((uint64_t)fb[q][1] << 32) | fb[q][0]);
+            acc[cb][q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(Aop, B, acc[cb][q], 0, 0, 0);
+          }
+        }
+      }
     } else if constexpr (kRawAhead) {
       // input-order BF16, FP16 x scale, FP8 x scale and FP8 hi+lo rows read
       // four channels at a time: the raw row pieces of k-step ks + 1 are loaded
@@ -861,8 +909,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       // loaded at the block's top).  The loads are unconditional: a load
       // under a branch makes the compiler wait for all outstanding loads.
       // (Drift scan, 9.12M x 1024: FP8 x scale 22.2 -> 20.4 ms, FP8 hi+lo
-      // 33.7 -> 32.4 ms, same results bit for bit; eight FP8 channels per
-      // lane measured slower, 21.8 ms.)
+      // 33.7 -> 32.4 ms, same results bit for bit.)
       const uint4* A16 = sA16(ab);
       const uint2* A8 = sA8(ab);
       const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
@@ -1119,7 +1166,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         // plan-ordered spectra lane % 16 + 16 (4 h + q), or for eight
         // channels per lane 8 (lane % 16) + 4 h + q
         const int64_t ch = kPacked ? c_w + 16 * (4 * h + q) + (lane & 15)
-                           : kW16  ? my_ch8 + 4 * h + q
+                           : (kW16 || kW8) ? my_ch8 + 4 * h + q
                                    : my_ch + 64 * h + q;
         if (ch >= C) continue;
         const float sc = (kForm == kF16S || is_fp8(kForm)) ? a.scale[ch] : 1.f;

@@ -267,12 +267,13 @@ def test_batch_plans_equal_single_plans():
     b.destroy()
 
 
-@pytest.mark.parametrize("form", [hcg.HCG_BF16, hcg.HCG_F16_SCALED])
+@pytest.mark.parametrize("form", [hcg.HCG_BF16, hcg.HCG_F16_SCALED, hcg.HCG_FP8E4M3_SCALED])
 @pytest.mark.parametrize("chan_tile", [256, 512])
 def test_eight_channel_rows_in_a_batch_class(form, chan_tile):
-    """Input-order BF16 and FP16 x scale fields of one kernel class whose rows
-    can (C = 520, 16-byte aligned) and cannot (C = 516; C = 520 placed 8
-    bytes off a 16-byte boundary) be read eight elements at a time.  The
+    """Input-order BF16, FP16 x scale and FP8 x scale fields of one kernel
+    class whose rows can (C = 520, aligned) and cannot (C = 516; C = 520
+    placed four elements off an eight-element boundary) be read eight
+    elements at a time.  The
     narrow-support 512-channel kernels read eight, so with such a field in the
     class the class takes 256-channel slabs; a class of eight-channel rows
     alone keeps 512.  Every field equals its single hcg_grid call bit for bit
@@ -284,7 +285,8 @@ def test_eight_channel_rows_in_a_batch_class(form, chan_tile):
     flat = torch.empty(enc520.numel() + 4, dtype=enc520.dtype, device=DEV)
     off520 = flat[4:].view(enc520.shape)
     off520.copy_(enc520)
-    assert off520.data_ptr() % 16 == 8
+    esz = enc520.element_size()
+    assert off520.data_ptr() % (8 * esz) == 4 * esz
     cases = [([w520, w516, w520], [enc520, enc516, off520], [sc520, sc516, sc520]),
              ([w520], [enc520], [sc520])]
     for ws, spectra, scales in cases:

@@ -13,8 +13,8 @@
 * tiles with more candidate ranges than the phase-rotated staging holds (a
   wide support at longitude 0, two ranges per ring) next to tiles that are
   rotated, in the FP32 form and two matrix-core forms;
-* input-order BF16 and FP16 x scale spectra whose rows are read eight
-  elements at a time (512-channel slabs, C a multiple of 8, 16-byte aligned)
+* input-order BF16, FP16 x scale and FP8 x scale spectra whose rows are read
+  eight elements at a time (512-channel slabs, C a multiple of 8, aligned)
   against the same spectra read four at a time (256-channel slabs), bit for
   bit, and against the oracle;
 * channels stay apart: with channel 0 non-finite in every sample, no other
@@ -223,10 +223,11 @@ def test_tiles_of_more_ranges_than_a_rotation_holds():
 @pytest.mark.parametrize("nchan", [520, 516])
 def test_rows_read_eight_channels_at_a_time(nchan):
     """A map of 576 8 x 8 tiles takes 512-channel slabs above 256 channels.
-    C = 520: the input-order BF16 and FP16 x scale gathers read a lane's eight
-    channels of a row in one load (the second slab holds 8 channels); the same
-    encoding placed 8 bytes off a 16-byte boundary is read four channels at a
-    time in 256-channel slabs, and both give the same cube bit for bit (the
+    C = 520: the input-order BF16, FP16 x scale and FP8 x scale gathers read a
+    lane's eight channels of a row in one load (the second slab holds 8
+    channels); the same encoding placed four elements off an eight-element
+    boundary is read four channels at a time in 256-channel slabs, and both
+    give the same cube bit for bit (the
     same weights and the same products in the same order per channel).
     C = 516 (not a multiple of 8) takes the four-channel reads for both.  Each
     cube matches the oracle on sampled cells at the form's budget."""
@@ -242,7 +243,8 @@ def test_rows_read_eight_channels_at_a_time(nchan):
     Wr = np.concatenate([x for _, x in ref])
     spec = w.spectra.to(DEV).contiguous()
     g = w.grid
-    for form, tol in [(hcg.HCG_BF16, 1e-2), (hcg.HCG_F16_SCALED, 1e-3)]:
+    for form, tol in [(hcg.HCG_BF16, 1e-2), (hcg.HCG_F16_SCALED, 1e-3),
+                      (hcg.HCG_FP8E4M3_SCALED, 1e-1)]:
         print(f"C={nchan} form {form}", flush=True)
         enc, scale = hcg.hcg_quantize(spec, form)
         cube = torch.empty((nchan, g.ny, g.nx), dtype=torch.float32, device=DEV)
@@ -251,7 +253,8 @@ def test_rows_read_eight_channels_at_a_time(nchan):
         flat = torch.empty(enc.numel() + 4, dtype=enc.dtype, device=DEV)
         off = flat[4:].view(enc.shape)
         off.copy_(enc)
-        assert off.data_ptr() % 16 == 8
+        esz = enc.element_size()
+        assert off.data_ptr() % (8 * esz) == 4 * esz  # four elements off
         cube_off = torch.empty_like(cube)
         hcg.hcg_grid(plan, off, cube_off, None, dtype=form, chan_scale=scale)
         torch.cuda.synchronize()
