@@ -1049,6 +1049,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
                 const uint16_t* rp = spec + row * C;
                 if (kEarlyRaw && ks == 0 && plane == 0) {
                   d[t] = e16[kEarlyRaw ? h : 0][t];
+                } else if (kVec && kQW == 1) {
+                  // unconditional, keeping what a lane past the last channel
+                  // reads (those products are never stored): without the
+                  // branch around each load the BF16 hi+lo gather took 43.2
+                  // instead of 48.1 ms on the drift scan; the wide-support
+                  // 512-channel kernels that come here would spill
+                  d[t] = *(const uint2*)(rp + ((ch + 3 < C) ? ch : 0));
                 } else if (kVec) {
                   d[t] = (ch + 3 < C) ? *(const uint2*)(rp + ch) : make_uint2(0u, 0u);
                 } else {
