@@ -642,7 +642,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
   };
   // FP32: a ring of kDepth k-steps' rows in flight.  The row loads are
   // issued unconditionally (an index past the last channel is clamped into
-  // the row and the value replaced after the load): a load under a divergent
+  // the row; rows read one element at a time replace the value after the
+  // load, rows read four at a time keep it): a load under a divergent
   // branch makes the compiler wait for every outstanding load before its
   // value is used, which serialised the ring (66.3 -> 60.5 ms on the
   // 9.12M x 1024 drift scan with this and the A operands read a k-step ahead).
@@ -657,8 +658,11 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
       const float* rp = spec + row * C;
       if (kVec) {
         const bool ok = ch + 3 < C;
-        const floatx4 v = *(const floatx4*)(rp + (ok ? ch : 0));
-        dst[h] = ok ? v : floatx4{0.f, 0.f, 0.f, 0.f};
+        // a lane past the last channel keeps what it reads (the row's first
+        // channels): those products only reach accumulators that are never
+        // stored, and the select that zeroed them cost 60.3 -> 58.9 ms on
+        // the drift scan
+        dst[h] = *(const floatx4*)(rp + (ok ? ch : 0));
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
