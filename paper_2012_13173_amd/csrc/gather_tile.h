@@ -905,15 +905,16 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int s
         }
       }
     } else if constexpr (kRawAhead) {
-      // input-order BF16, FP16 x scale, FP8 x scale and FP8 hi+lo rows read
-      // four channels at a time: the raw row pieces of k-step ks + 1 are loaded
-      // into the registers that held those of k-step ks once these are
-      // repacked into B operands, so that a k-step's loads are in flight
-      // while the previous k-step's products are issued (k-step 0's are
-      // loaded at the block's top).  The loads are unconditional: a load
-      // under a branch makes the compiler wait for all outstanding loads.
-      // (Drift scan, 9.12M x 1024: FP8 x scale 22.2 -> 20.4 ms, FP8 hi+lo
-      // 33.7 -> 32.4 ms, same results bit for bit.)
+      // input-order rows read four channels at a time (the 256-channel
+      // BF16, FP16 x scale and FP8 x scale kernels, and FP8 hi+lo): the raw
+      // row pieces of k-step ks + 1 are loaded into the registers that held
+      // those of k-step ks once these are repacked into B operands, so that
+      // a k-step's loads are in flight while the previous k-step's products
+      // are issued (k-step 0's are loaded at the block's top).  The loads are
+      // unconditional: a load under a branch makes the compiler wait for all
+      // outstanding loads.  (Drift scan, 9.12M x 1024: FP8 hi+lo 33.7 -> 32.4
+      // ms, and FP8 x scale 22.2 -> 20.4 ms before its 512-channel kernel
+      // read eight channels per lane; same results bit for bit.)
       const uint4* A16 = sA16(ab);
       const uint2* A8 = sA8(ab);
       const uint32_t any = nzc[0] | nzc[1] | nzc[2] | nzc[3];
